@@ -1,0 +1,189 @@
+/* cqc.h - reconstruction of cut-circuit output distributions on AMD MI355X (gfx950).
+ *
+ * A circuit cut on K wires into n_C subcircuits is reconstructed from the
+ * subcircuit "entry" tensors as the sum, over the 4^K Pauli label assignments
+ * of the cut wires, of Kronecker products of entries, scaled by 2^-K
+ * (Tang et al., CutQC, ASPLOS '21: Section 3.1 Eq. 1 for the per-cut Pauli
+ * expansion and its factor 1/2, Section 3.2.3 for the term sum of one cut,
+ * Section 3.3 for 4^K products with K cuts):
+ *
+ *     p(x) = 2^-K * sum_{l in {I,X,Y,Z}^K} prod_c E_c[ row_c(l), x_c ]
+ *
+ * Conventions shared by every entry point
+ *   - Global output index: x = sum_q b_q 2^(n-1-q); qubit 0 is the most
+ *     significant bit (the |q_0 ... q_{n-1}> notation of Section 3.2).
+ *   - Entry tensor E_c: row-major [4^k_c][2^f_c], k_c = number of cuts incident
+ *     to c, f_c = output qubits of c (Eq. 7).  Row digits: labels of the cuts
+ *     incident to c in ascending cut id, first cut = most significant base-4
+ *     digit, I=0, X=1, Y=2, Z=3.  Column x_c: local output bit j (j = 0 most
+ *     significant) is global qubit out_qubit[sum_{c'<c} f_c' + j].
+ *   - Every call is asynchronous on `stream` unless stated otherwise; device
+ *     buffers must stay alive until the stream has executed the call.
+ *   - All validation happens on the host before anything is enqueued: on any
+ *     non-zero status nothing was launched and no output was touched.
+ *   - The caller owns every buffer, including the workspace; the library keeps
+ *     no device allocations of its own.
+ *   - Values are never clamped: negative reconstructed probabilities (possible
+ *     with finite-shot entries, Section 3.2.3) are returned as they are.
+ *   - Early termination (Section 4.2): a label assignment whose factor row in
+ *     some E_c is entirely +0/-0 is skipped.  With finite entries this changes
+ *     nothing; with Inf/NaN in another factor the skipped product would have
+ *     been NaN.
+ *   - Thread safety: functions are re-entrant; concurrent calls must use
+ *     distinct workspaces.
+ */
+#ifndef CQC_H
+#define CQC_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+enum {
+  CQC_OK = 0,
+  CQC_ERR_INVALID_ARG = 1,  /* null pointer, bad enum, out-of-range id          */
+  CQC_ERR_SHAPE = 2,        /* sum f_c != n, output order not a permutation, ... */
+  CQC_ERR_UNSUPPORTED = 3,  /* valid but outside the implemented limits         */
+  CQC_ERR_WORKSPACE = 4,    /* workspace missing or smaller than required       */
+  CQC_ERR_HIP = 5           /* a HIP runtime call failed                        */
+};
+
+typedef enum { CQC_F32 = 0, CQC_F64 = 1 } cqc_dtype;
+
+/* Arithmetic of the term sum.
+ *   FP64:   double inputs (F32 inputs are widened exactly), FP64 MFMA, FP64 accumulate.
+ *   FP32:   float operands, FP32 MFMA with FP32 accumulation; the total mass
+ *           and DD bin masses are summed in FP64.
+ *   BF16X6: each float operand split into three bfloat16 parts (a = a0+a1+a2),
+ *           the six products a_i b_j with i+j <= 2 on BF16 MFMA with FP32
+ *           accumulation (Henry, Tang, Heinecke, ARITH 2019).            */
+typedef enum { CQC_PREC_FP64 = 0, CQC_PREC_FP32 = 1, CQC_PREC_BF16X6 = 2 } cqc_precision;
+
+/* Limits of this implementation. */
+#define CQC_MAX_SUB 16        /* subcircuits per instance                      */
+#define CQC_MAX_CUTS 24       /* cut wires per instance                        */
+#define CQC_MAX_K_SUB 12      /* cuts incident to one subcircuit               */
+#define CQC_MAX_FD_QUBITS 40  /* n for the full-definition output (2^n values) */
+#define CQC_MAX_DD_QUBITS 128 /* n for dynamic definition                      */
+#define CQC_MAX_F_SUB 30      /* output qubits of one subcircuit               */
+
+/* Cut description (the problem statement of Sections 3 and 4.1: subcircuits,
+ * cut wires with an upstream measured end u and a downstream initialised end v
+ * (Figure 3), and the output qubit order).  All arrays are HOST memory. */
+typedef struct {
+  int32_t n_qubits;          /* n: output qubits of the uncut circuit             */
+  int32_t n_sub;             /* n_C                                               */
+  int32_t n_cuts;            /* K                                                 */
+  const int32_t *f;          /* [n_sub] output qubits of each subcircuit (Eq. 7)  */
+  const int32_t *edge_up;    /* [n_cuts] upstream (measured) subcircuit of cut e  */
+  const int32_t *edge_down;  /* [n_cuts] downstream (initialised) subcircuit      */
+  const int32_t *out_qubit;  /* [n_qubits] concatenated over c: local bit -> qubit*/
+} cqc_cut;
+
+typedef struct {
+  cqc_cut cut;
+  const void *const *entries; /* HOST array [n_sub] of DEVICE pointers, E_c as above */
+  void *out;                  /* DEVICE: FD output [2^n] in the output dtype        */
+  double *mass;               /* DEVICE [1] or NULL: FP64 sum of the written outputs */
+} cqc_instance;
+
+/* Full-definition reconstruction (Section 4.2 "FD query"): writes all 2^n
+ * probabilities of every instance, each output element written exactly once,
+ * and (if mass != NULL) their FP64 sum.  n_inst > 1 reconstructs a batch of
+ * independent instances in one call.  in_t is the dtype of every entry
+ * tensor, out_t the dtype of every output.  workspace: DEVICE buffer of at
+ * least cqc_fd_workspace_size() bytes, 256-byte aligned. */
+int cqc_fd_workspace_size(const cqc_instance *inst, int32_t n_inst, cqc_dtype in_t,
+                          cqc_dtype out_t, cqc_precision prec, size_t *bytes);
+int cqc_reconstruct_fd(const cqc_instance *inst, int32_t n_inst, cqc_dtype in_t,
+                       cqc_dtype out_t, cqc_precision prec, void *workspace,
+                       size_t ws_bytes, hipStream_t stream);
+
+/* Dynamic definition (Algorithm 1, Section 4.3).
+ * Recursion 1 makes `first_active` (or, if NULL, the first n_active qubits in
+ * output order) active; every later recursion picks, among all bins produced
+ * so far that are not yet expanded and still contain merged qubits, the one
+ * with the largest FP64 mass (ties: lowest recursion, then lowest bin index),
+ * zooms its active qubits to the bin's bits, and makes the next n_active
+ * un-zoomed qubits in output order active.  Merged qubits are summed out of
+ * the entries (FP64 accumulation) before the term sum.  Bin b of a recursion
+ * has its active qubits (ascending id) as bits, first = most significant.
+ * Stops early when no bin can be refined.
+ * This call is host-driven: it synchronises `stream` once per recursion to
+ * read the chosen bin, and returns after the last recursion completed. */
+typedef struct {
+  int32_t n_active;          /* a: active qubits per recursion, 1..30            */
+  int32_t n_recursions;      /* R >= 1                                            */
+  const int32_t *first_active; /* HOST [n_active] or NULL                         */
+  int32_t strategy;          /* 0 = heaviest unexpanded bin (Algorithm 1)        */
+} cqc_dd_params;
+
+typedef struct {
+  int32_t parent_rec;        /* -1 for recursion 1                                */
+  int32_t n_active;          /* active qubits of this recursion (<= a)            */
+  int64_t parent_bin;        /* bin of parent_rec that this recursion refines     */
+  double mass;               /* FP64 sum of this recursion's bins                 */
+  int8_t role[CQC_MAX_DD_QUBITS]; /* per qubit: -2 active, -1 merged, 0/1 zoomed  */
+} cqc_dd_record;
+
+int cqc_dd_workspace_size(const cqc_instance *inst, cqc_dtype in_t, cqc_precision prec,
+                          const cqc_dd_params *p, size_t *bytes);
+/* bins: DEVICE [n_recursions][2^n_active] FP64 (rows past the last recursion
+ * are not written); records: HOST [n_recursions]; n_done: HOST, recursions run.
+ * inst->out and inst->mass are ignored. */
+int cqc_reconstruct_dd(const cqc_instance *inst, cqc_dtype in_t, cqc_precision prec,
+                       const cqc_dd_params *p, double *bins, cqc_dd_record *records,
+                       int32_t *n_done, void *workspace, size_t ws_bytes,
+                       hipStream_t stream);
+
+/* Adjoint of the FD build: given G = dL/dp (DEVICE [2^n] per instance, dtype
+ * in_t), writes dL/dE_c for every subcircuit (DEVICE, same layout and dtype
+ * as E_c):
+ *     dL/dE_c[r, y] = 2^-K sum_{l: row_c(l)=r} sum_{x: x_c=y} G[x] prod_{c'!=c} E_c'[row_c'(l), x_c']
+ * Every output element is written (not accumulated).  Reductions run in a
+ * fixed order, so results are bitwise reproducible. */
+int cqc_backward_workspace_size(const cqc_instance *inst, int32_t n_inst, cqc_dtype in_t,
+                                cqc_precision prec, size_t *bytes);
+int cqc_reconstruct_backward(const cqc_instance *inst, int32_t n_inst, cqc_dtype in_t,
+                             cqc_precision prec, const void *const *grad_out,
+                             void *const *const *grad_entries, void *workspace,
+                             size_t ws_bytes, hipStream_t stream);
+
+/* Eq. 14 of Section 4.1.4 for one instance, with subcircuits taken in the
+ * greedy smallest-first order of Section 4.2: 4^K * sum_{c>=2} prod_{i<=c} 2^f_i
+ * multiplications.  Also returns the multiply-adds of this library's plan. */
+int cqc_cost(const cqc_cut *cut, double *eq14_mults, double *plan_macs);
+
+/* Tile autotuner: times the candidate tile shapes of every contraction the
+ * instance needs (on `stream`, synchronously), keeps the fastest per shape
+ * class in a process-wide cache, and persists the cache to the file named by
+ * the CQC_TUNE_CACHE environment variable if set.  Outputs are clobbered. */
+int cqc_autotune(const cqc_instance *inst, int32_t n_inst, cqc_dtype in_t,
+                 cqc_dtype out_t, cqc_precision prec, void *workspace,
+                 size_t ws_bytes, hipStream_t stream);
+
+/* Kernel tracing: when enabled, every kernel the library launches is
+ * bracketed by HIP events on its stream; cqc_trace_read reports, per kernel
+ * name, the launch count and the summed event time (ms), and resets. */
+int cqc_trace_enable(int on);
+int cqc_trace_read(char *names, size_t names_len, int32_t *counts, double *ms,
+                   int32_t max_kernels, int32_t *n_kernels);
+
+const char *cqc_status_string(int status);
+const char *cqc_last_error_detail(void); /* thread-local, of the last failing call */
+int cqc_version(void);
+
+/* Self test of the MFMA operand/accumulator lane layouts the kernels assume:
+ * runs one 16x16x4 FP32 and one FP64 matrix-core product on known operands
+ * (DEVICE out: 256 floats then 256 doubles) and returns CQC_OK if launched. */
+int cqc_selftest_mfma(void *out, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CQC_H */

@@ -1,0 +1,273 @@
+"""cqc: cut-circuit reconstruction on AMD MI355X.
+
+Thin Python binding of libcqc.so (include/cqc.h).  PyTorch provides device
+memory and the current stream; every step of the reconstruction runs in the
+library's HIP kernels.  There is no CPU fallback: if the library or a GPU is
+missing, calls raise.
+
+    cut = CutMap(n, f, edges=[(up, down), ...], out_qubits=[...])
+    p, mass = reconstruct_fd(entries, cut, precision="fp32")
+    bins, records = reconstruct_dd(entries, cut, n_active, n_recursions)
+    p = ReconstructFD.apply(cut, "fp32", *entries)      # differentiable
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import CqcError, PREC
+
+__all__ = ["CutMap", "reconstruct_fd", "reconstruct_dd", "reconstruct_backward", "FDCall",
+           "ReconstructFD", "cost", "trace", "CqcError", "selftest_mfma", "library_path"]
+
+_DT = {torch.float32: _lib.F32, torch.float64: _lib.F64}
+
+
+def library_path():
+    return _lib.LIB_PATH
+
+
+class CutMap:
+    """Cut description: n output qubits, f[c] output qubits per subcircuit,
+    edges[e] = (upstream, downstream) subcircuit of cut e, out_qubits =
+    concatenated local-bit -> global-qubit map (local bit 0 most significant)."""
+
+    def __init__(self, n, f, edges, out_qubits):
+        self.n = int(n)
+        self.f = [int(v) for v in f]
+        self.edges = [(int(u), int(d)) for (u, d) in edges]
+        self.out_qubits = [int(q) for q in out_qubits]
+        I32 = ctypes.c_int32
+        self._f = (I32 * max(1, len(self.f)))(*self.f)
+        self._up = (I32 * max(1, len(self.edges)))(*[u for u, _ in self.edges])
+        self._down = (I32 * max(1, len(self.edges)))(*[d for _, d in self.edges])
+        self._oq = (I32 * max(1, len(self.out_qubits)))(*self.out_qubits)
+        self.c = _lib.CqcCut(self.n, len(self.f), len(self.edges), self._f, self._up, self._down, self._oq)
+
+    @classmethod
+    def from_workload(cls, cm):
+        """From a workloads.CutMap (f, edge_up, edge_down, out_qubit)."""
+        return cls(cm.n, cm.f, list(zip(cm.edge_up, cm.edge_down)), cm.out_qubit)
+
+    @property
+    def n_sub(self):
+        return len(self.f)
+
+    @property
+    def n_cuts(self):
+        return len(self.edges)
+
+    def k(self, c):
+        return sum(1 for (u, d) in self.edges if u == c or d == c)
+
+    def entry_shape(self, c):
+        return (4 ** self.k(c), 2 ** self.f[c])
+
+
+def _stream_ptr(device=None):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check_entries(entries, cut, dtype=None):
+    if len(entries) != cut.n_sub:
+        raise ValueError(f"expected {cut.n_sub} entry tensors, got {len(entries)}")
+    dt = dtype or entries[0].dtype
+    for c, E in enumerate(entries):
+        if not E.is_cuda:
+            raise ValueError("entry tensors must be on the GPU")
+        if E.dtype != dt:
+            raise ValueError("all entry tensors must share one dtype")
+        if tuple(E.shape) != cut.entry_shape(c) or not E.is_contiguous():
+            raise ValueError(f"entries[{c}] must be contiguous with shape {cut.entry_shape(c)}")
+    if dt not in _DT:
+        raise ValueError("entries must be float32 or float64")
+    return dt
+
+
+_ws_cache = {}
+
+
+def _workspace(nbytes, device):
+    key = (device.index if device.index is not None else torch.cuda.current_device())
+    buf = _ws_cache.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+        _ws_cache[key] = buf
+    return buf
+
+
+class FDCall:
+    """A prepared FD reconstruction: validated shapes, workspace and output
+    buffers allocated once; run() enqueues the whole hot path on the current
+    stream with one library call."""
+
+    def __init__(self, entries_list, cuts, precision="fp32", out_dtype=None, outs=None,
+                 with_mass=True, workspace=None):
+        if isinstance(cuts, CutMap):
+            cuts, entries_list = [cuts], [entries_list]
+        self.cuts = list(cuts)
+        self.entries_list = [list(e) for e in entries_list]
+        in_dt = _check_entries(self.entries_list[0], self.cuts[0])
+        for e, c in zip(self.entries_list, self.cuts):
+            _check_entries(e, c, in_dt)
+        self.in_dtype = in_dt
+        self.out_dtype = out_dtype or in_dt
+        self.prec = PREC[precision]
+        dev = self.entries_list[0][0].device
+        self.device = dev
+        n_inst = len(self.cuts)
+        self.outs = outs if outs is not None else [
+            torch.empty(2 ** c.n, dtype=self.out_dtype, device=dev) for c in self.cuts]
+        self.mass = torch.zeros(n_inst, dtype=torch.float64, device=dev) if with_mass else None
+        Arr = _lib.CqcInstance * n_inst
+        self._insts = Arr()
+        self._keep = []
+        for i, (c, ents) in enumerate(zip(self.cuts, self.entries_list)):
+            ptrs = (ctypes.c_void_p * len(ents))(*[E.data_ptr() for E in ents])
+            self._keep.append(ptrs)
+            self._insts[i] = _lib.CqcInstance(
+                c.c, ptrs, self.outs[i].data_ptr(),
+                (self.mass.data_ptr() + 8 * i) if with_mass else None)
+        self.n_inst = n_inst
+        self._in_t, self._out_t = _DT[self.in_dtype], _DT[self.out_dtype]
+        nb = ctypes.c_size_t(0)
+        _lib.check(_lib.lib().cqc_fd_workspace_size(self._insts, n_inst, self._in_t, self._out_t,
+                                                    self.prec, ctypes.byref(nb)))
+        self.ws_bytes = int(nb.value)
+        self.ws = workspace if workspace is not None else torch.empty(
+            max(self.ws_bytes, 256), dtype=torch.uint8, device=dev)
+        self._fn = _lib.lib().cqc_reconstruct_fd
+
+    def set_outputs(self, outs):
+        for i, o in enumerate(outs):
+            self.outs[i] = o
+            self._insts[i].out = o.data_ptr()
+
+    def run(self, stream=None):
+        s = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        _lib.check(self._fn(self._insts, self.n_inst, self._in_t, self._out_t, self.prec,
+                            self.ws.data_ptr(), self.ws_bytes, s))
+
+
+def reconstruct_fd(entries, cut, precision="fp32", out_dtype=None, with_mass=True):
+    """Full-definition reconstruction of one instance -> (p[2^n], mass or None)."""
+    call = FDCall(entries, cut, precision, out_dtype, with_mass=with_mass)
+    call.run()
+    return call.outs[0], (call.mass[0] if with_mass else None)
+
+
+def reconstruct_dd(entries, cut, n_active, n_recursions, first_active=None, precision="fp32"):
+    """Dynamic definition (Algorithm 1) -> (bins [R_done, 2^a] float64, records list)."""
+    in_dt = _check_entries(entries, cut)
+    dev = entries[0].device
+    ptrs = (ctypes.c_void_p * len(entries))(*[E.data_ptr() for E in entries])
+    inst = _lib.CqcInstance(cut.c, ptrs, None, None)
+    fa = None
+    if first_active is not None:
+        fa = (ctypes.c_int32 * len(first_active))(*[int(q) for q in first_active])
+    params = _lib.CqcDDParams(int(n_active), int(n_recursions), fa, 0)
+    L = _lib.lib()
+    nb = ctypes.c_size_t(0)
+    _lib.check(L.cqc_dd_workspace_size(ctypes.byref(inst), _DT[in_dt], PREC[precision],
+                                       ctypes.byref(params), ctypes.byref(nb)))
+    ws = _workspace(int(nb.value), dev)
+    a = min(int(n_active), cut.n)
+    bins = torch.zeros((int(n_recursions), 2 ** a), dtype=torch.float64, device=dev)
+    recs = (_lib.CqcDDRecord * int(n_recursions))()
+    done = ctypes.c_int32(0)
+    _lib.check(L.cqc_reconstruct_dd(ctypes.byref(inst), _DT[in_dt], PREC[precision],
+                                    ctypes.byref(params), bins.data_ptr(), recs,
+                                    ctypes.byref(done), ws.data_ptr(), int(nb.value),
+                                    _stream_ptr(dev)))
+    out = []
+    for r in range(done.value):
+        rec = recs[r]
+        role = [int(rec.role[q]) for q in range(cut.n)]
+        out.append(dict(parent=(int(rec.parent_rec), int(rec.parent_bin)), n_active=int(rec.n_active),
+                        mass=float(rec.mass), role=role,
+                        active=[q for q in range(cut.n) if role[q] == -2]))
+    return bins[:done.value], out
+
+
+def reconstruct_backward(entries, cut, grad_out, precision="fp32"):
+    """dL/dE_c for every subcircuit given dL/dp (same dtype as the entries)."""
+    in_dt = _check_entries(entries, cut)
+    dev = entries[0].device
+    if grad_out.dtype != in_dt or not grad_out.is_contiguous() or grad_out.numel() != 2 ** cut.n:
+        raise ValueError("grad_out must be a contiguous [2^n] tensor of the entry dtype")
+    grads = [torch.empty_like(E) for E in entries]
+    ptrs = (ctypes.c_void_p * len(entries))(*[E.data_ptr() for E in entries])
+    inst = _lib.CqcInstance(cut.c, ptrs, None, None)
+    gptr = (ctypes.c_void_p * 1)(grad_out.data_ptr())
+    gents = (ctypes.c_void_p * len(grads))(*[g.data_ptr() for g in grads])
+    gents_pp = (ctypes.POINTER(ctypes.c_void_p) * 1)(gents)
+    L = _lib.lib()
+    nb = ctypes.c_size_t(0)
+    _lib.check(L.cqc_backward_workspace_size(ctypes.byref(inst), 1, _DT[in_dt], PREC[precision],
+                                             ctypes.byref(nb)))
+    ws = _workspace(int(nb.value), dev)
+    _lib.check(L.cqc_reconstruct_backward(ctypes.byref(inst), 1, _DT[in_dt], PREC[precision],
+                                          gptr, gents_pp, ws.data_ptr(), int(nb.value),
+                                          _stream_ptr(dev)))
+    return grads
+
+
+class ReconstructFD(torch.autograd.Function):
+    """p = FD(entries); backward runs the library's adjoint kernels."""
+
+    @staticmethod
+    def forward(ctx, cut, precision, *entries):
+        p, _ = reconstruct_fd(list(entries), cut, precision, with_mass=False)
+        ctx.cut, ctx.precision = cut, precision
+        ctx.save_for_backward(*entries)
+        return p
+
+    @staticmethod
+    def backward(ctx, grad_p):
+        entries = ctx.saved_tensors
+        g = grad_p.contiguous().to(entries[0].dtype)
+        grads = reconstruct_backward(list(entries), ctx.cut, g, ctx.precision)
+        return (None, None) + tuple(grads)
+
+
+def cost(cut):
+    """(Eq. 14 multiplications with greedy order, multiply-adds of the library's plan)."""
+    a, b = ctypes.c_double(0), ctypes.c_double(0)
+    _lib.check(_lib.lib().cqc_cost(ctypes.byref(cut.c), ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+class trace:
+    """Context manager: per-kernel event timing of every library launch."""
+
+    def __enter__(self):
+        _lib.lib().cqc_trace_enable(1)
+        return self
+
+    def __exit__(self, *exc):
+        _lib.lib().cqc_trace_enable(0)
+        self.result = read_trace()
+        return False
+
+
+def read_trace(max_kernels=64):
+    L = _lib.lib()
+    names = ctypes.create_string_buffer(8192)
+    counts = (ctypes.c_int32 * max_kernels)()
+    ms = (ctypes.c_double * max_kernels)()
+    nk = ctypes.c_int32(0)
+    _lib.check(L.cqc_trace_read(names, 8192, counts, ms, max_kernels, ctypes.byref(nk)))
+    nl = names.value.decode().split("\n") if nk.value else []
+    return {nl[i]: (int(counts[i]), float(ms[i])) for i in range(nk.value)}
+
+
+def selftest_mfma(device="cuda"):
+    """Run the MFMA lane-layout probe -> (D_f32[16,16], D_f64[16,16])."""
+    buf = torch.zeros(256 * 4 + 256 * 8, dtype=torch.uint8, device=device)
+    _lib.check(_lib.lib().cqc_selftest_mfma(buf.data_ptr(), _stream_ptr()))
+    torch.cuda.synchronize()
+    f = buf[:1024].view(torch.float32).reshape(16, 16).cpu()
+    d = buf[1024:].view(torch.float64).reshape(16, 16).cpu()
+    return f, d

@@ -1,0 +1,67 @@
+// Shared host-side definitions of the cqc library: status handling, HIP error
+// mapping, kernel launch tracing.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/cqc.h"
+
+namespace cqc {
+
+// Thread-local detail string of the last failing call.
+void set_error(const std::string &msg);
+const char *error_detail();
+
+struct Status {
+  int code = CQC_OK;
+  static Status ok() { return Status{}; }
+  static Status fail(int c, const std::string &msg) {
+    set_error(msg);
+    Status s;
+    s.code = c;
+    return s;
+  }
+  bool good() const { return code == CQC_OK; }
+};
+
+#define CQC_HIP_TRY(expr)                                                    \
+  do {                                                                       \
+    hipError_t e_ = (expr);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      return ::cqc::Status::fail(CQC_ERR_HIP, std::string(#expr) + ": " +  \
+                                                  hipGetErrorString(e_));    \
+  } while (0)
+
+#define CQC_TRY(expr)                \
+  do {                               \
+    ::cqc::Status s_ = (expr);       \
+    if (!s_.good()) return s_;       \
+  } while (0)
+
+// Kernel launch tracing (events around launches when enabled).
+bool trace_on();
+void trace_begin(const char *name, hipStream_t s, hipEvent_t *start);
+void trace_end(const char *name, hipStream_t s, hipEvent_t start);
+
+// Launch helper: traces when enabled, checks the launch error.
+template <typename Kernel, typename... Args>
+Status launch(const char *name, Kernel k, dim3 grid, dim3 block, size_t shmem,
+              hipStream_t s, Args... args) {
+  if (grid.x == 0 || grid.y == 0 || grid.z == 0) return Status::ok();
+  hipEvent_t ev = nullptr;
+  if (trace_on()) trace_begin(name, s, &ev);
+  hipLaunchKernelGGL(k, grid, block, shmem, s, args...);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess)
+    return Status::fail(CQC_ERR_HIP, std::string("launch ") + name + ": " +
+                                         hipGetErrorString(e));
+  if (ev) trace_end(name, s, ev);
+  return Status::ok();
+}
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace cqc

@@ -1,0 +1,44 @@
+// Workspace layout and enqueue of a contraction plan (shared by FD and DD).
+#pragma once
+
+#include <vector>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+
+namespace cqc {
+
+struct NetLayout {
+  Plan plan;
+  Acc acc = Acc::F32;
+  size_t esz = 4;
+  std::vector<size_t> t_off;   // intermediates (and unit tensor): byte offset
+  std::vector<size_t> f_off;   // row flags of every tensor: byte offset
+  std::vector<int> tile;       // per step
+  std::vector<int64_t> nblocks;
+  size_t partials_off = 0, counter_off = 0;
+  size_t bytes = 0;            // end offset (relative to the layout base)
+};
+
+// Lay out a plan's workspace starting at byte offset `base`.
+NetLayout layout_net(const Plan &plan, Acc acc, size_t base);
+
+// Enqueue the plan.  `entries[c]` are Acc-typed device tensors, flags of the
+// entry tensors must already be computed into their f_off slots unless
+// compute_entry_flags is set.
+Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &entries,
+               void *out, bool out_double, double *mass, bool compute_entry_flags,
+               hipStream_t s);
+
+inline bool is_blocked(const Plan &p, const Step &st) {
+  const auto &X = p.tensors[st.x], &Y = p.tensors[st.y];
+  const int nY = (int)Y.bits.size();
+  for (int j = 0; j < nY; ++j)
+    if (p.bitpos[Y.bits[nY - 1 - j]] != j) return false;
+  const int nX = (int)X.bits.size();
+  for (int j = 0; j < nX; ++j)
+    if (p.bitpos[X.bits[nX - 1 - j]] != nY + j) return false;
+  return true;
+}
+
+}  // namespace cqc

@@ -1,0 +1,33 @@
+"""Helpers of the GPU parity tests (inputs on the device, oracle bounds)."""
+import numpy as np
+import torch
+
+from oracle import fd
+
+U32 = 2.0 ** -24
+U64 = 2.0 ** -53
+
+
+def to_dev(entries, dtype):
+    np_dt = np.float32 if dtype == torch.float32 else np.float64
+    host = [np.ascontiguousarray(E, dtype=np_dt) for E in entries]
+    return host, [torch.from_numpy(E).to("cuda") for E in host]
+
+
+def oracle_inputs(host):
+    """Reading for FP32 inputs: the oracle sees the same rounded entries, widened exactly."""
+    return [E.astype(np.float64) for E in host]
+
+
+def abs_bound(entries64, cut, xs=None):
+    """T_x = 2^-K sum_l prod_c |E_c| : scale of every rounding error at output x."""
+    return fd.reconstruct([np.abs(E) for E in entries64], cut, xs)
+
+
+def elementwise_ok(p, ref, T, unit, terms):
+    """|p - ref| <= 4 (terms + 2) u T_x, the bound of any order of the term sum
+    with one rounding per multiply and per add."""
+    tol = 4.0 * (terms + 2) * unit * T
+    err = np.abs(np.asarray(p, dtype=np.float64) - ref)
+    bad = np.nonzero(err > tol)[0]
+    return bad.size == 0, (bad[:5], err[bad[:5]] if bad.size else None, tol[bad[:5]] if bad.size else None)

@@ -1,0 +1,121 @@
+"""Host-only checks of the C ABI: the library loads, exports every function
+include/cqc.h declares, and rejects bad arguments before enqueuing anything.
+No GPU is touched: every call here fails validation or is a pure host query."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2012_02333_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cqc.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(_lib.LIB_PATH), reason="libcqc.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cqc_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_function():
+    L = _lib.lib()
+    names = declared_functions()
+    assert "cqc_reconstruct_fd" in names and "cqc_reconstruct_dd" in names
+    assert "cqc_reconstruct_backward" in names
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) <= set(_lib.EXPORTS)
+
+
+def _inst(n, f, edges, outq, nsub=None):
+    I32 = ctypes.c_int32
+    keep = []
+    fa = (I32 * max(1, len(f)))(*f)
+    up = (I32 * max(1, len(edges)))(*[u for u, _ in edges])
+    dn = (I32 * max(1, len(edges)))(*[d for _, d in edges])
+    oq = (I32 * max(1, len(outq)))(*outq)
+    keep += [fa, up, dn, oq]
+    cut = _lib.CqcCut(n, nsub if nsub is not None else len(f), len(edges), fa, up, dn, oq)
+    ents = (ctypes.c_void_p * max(1, len(f)))(*([0x1000] * len(f)))
+    keep.append(ents)
+    inst = _lib.CqcInstance(cut, ents, 0x2000, None)
+    inst._keep = keep
+    return inst
+
+
+def ws_size(inst, prec=1, in_t=0, out_t=0):
+    nb = ctypes.c_size_t(0)
+    rc = _lib.lib().cqc_fd_workspace_size(ctypes.byref(inst), 1, in_t, out_t, prec, ctypes.byref(nb))
+    return rc, nb.value
+
+
+def test_valid_cut_workspace_query():
+    inst = _inst(24, [11, 13], [(0, 1), (0, 1)], list(range(24)))
+    rc, nb = ws_size(inst)
+    assert rc == 0 and nb > 0
+    rc64, nb64 = ws_size(inst, prec=0, in_t=1, out_t=1)
+    assert rc64 == 0
+    # FP32 entries under FP64 arithmetic need a widened copy: more workspace
+    rc_mix, nb_mix = ws_size(inst, prec=0, in_t=0, out_t=1)
+    assert rc_mix == 0 and nb_mix > nb64
+
+
+@pytest.mark.parametrize("n,f,edges,outq,code", [
+    (8, [4, 3], [(0, 1)], list(range(8)), 2),            # sum f != n
+    (8, [4, 4], [(0, 1)], [0, 1, 2, 3, 4, 5, 6, 6], 2),  # not a permutation
+    (8, [4, 4], [(0, 1)], [0, 1, 2, 3, 4, 5, 6, 8], 2),  # qubit out of range
+    (8, [4, 4], [(0, 2)], list(range(8)), 1),            # cut names a missing subcircuit
+    (8, [4, 4], [(1, 1)], list(range(8)), 2),            # cut inside one subcircuit
+    (41, [20, 21], [(0, 1)], list(range(41)), 3),        # 2^41 outputs: beyond FD limit
+    (8, [-1, 9], [(0, 1)], list(range(8)), 2),           # negative f
+])
+def test_invalid_cuts(n, f, edges, outq, code):
+    rc, _ = ws_size(_inst(n, f, edges, outq))
+    assert rc == code
+    detail = _lib.lib().cqc_last_error_detail().decode()
+    assert detail
+
+
+def test_bad_enums_and_pointers():
+    L = _lib.lib()
+    inst = _inst(8, [4, 4], [(0, 1)], list(range(8)))
+    nb = ctypes.c_size_t(0)
+    assert L.cqc_fd_workspace_size(ctypes.byref(inst), 1, 7, 0, 1, ctypes.byref(nb)) == 1
+    assert L.cqc_fd_workspace_size(ctypes.byref(inst), 1, 0, 0, 9, ctypes.byref(nb)) == 1
+    assert L.cqc_fd_workspace_size(ctypes.byref(inst), 0, 0, 0, 1, ctypes.byref(nb)) == 1
+    assert L.cqc_fd_workspace_size(None, 1, 0, 0, 1, ctypes.byref(nb)) == 1
+    assert L.cqc_fd_workspace_size(ctypes.byref(inst), 1, 0, 0, 1, None) == 1
+    # null entry pointer is caught before anything is enqueued
+    inst.entries[1] = None
+    assert L.cqc_reconstruct_fd(ctypes.byref(inst), 1, 0, 0, 1, 0x3000, 1 << 30, None) == 1
+
+
+def test_workspace_too_small_enqueues_nothing():
+    L = _lib.lib()
+    inst = _inst(8, [4, 4], [(0, 1)], list(range(8)))
+    rc, need = ws_size(inst)
+    assert rc == 0
+    assert L.cqc_reconstruct_fd(ctypes.byref(inst), 1, 0, 0, 1, 0x3000, need - 1, None) == 4
+    assert L.cqc_reconstruct_fd(ctypes.byref(inst), 1, 0, 0, 1, None, need, None) == 4
+    assert L.cqc_reconstruct_fd(ctypes.byref(inst), 1, 0, 0, 1, 0x3010, need, None) == 4  # misaligned
+
+
+def test_status_strings():
+    L = _lib.lib()
+    assert L.cqc_status_string(0) == b"CQC_OK"
+    assert L.cqc_status_string(4) == b"CQC_ERR_WORKSPACE"
+    assert L.cqc_version() >= 100
+
+
+def test_cost_eq14():
+    L = _lib.lib()
+    inst = _inst(30, [9, 9, 12], [(0, 1)] * 3 + [(1, 2)] * 3, list(range(30)))
+    a, b = ctypes.c_double(0), ctypes.c_double(0)
+    assert L.cqc_cost(ctypes.byref(inst.cut), ctypes.byref(a), ctypes.byref(b)) == 0
+    assert a.value == 4 ** 6 * (2 ** 18 + 2 ** 30)
+    # library plan: A-B over 3 labels into 64 x 2^18, then 2^18 x 2^12 over 3 labels
+    assert b.value == 64 * 64 * 2 ** 18 + 64 * 2 ** 30

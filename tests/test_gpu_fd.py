@@ -1,0 +1,174 @@
+"""GPU parity of the full-definition path against the FP64 oracle.
+
+Tolerances: relative L1 <= 1e-6 for the FP32 forms (the target accuracy),
+<= 1e-12 for the FP64 form; in addition every element must lie within the
+rounding bound 4 (t + 2) u T_x of any summation order of the t terms it adds,
+with T_x = 2^-K sum_l prod_c |E_c| computed by the oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import fd, metrics
+from tests.gpu_util import to_dev, oracle_inputs, abs_bound, elementwise_ok, U32, U64
+
+pytestmark = pytest.mark.gpu
+
+cqc = pytest.importorskip("paper_2012_02333_amd")
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def test_mfma_lane_layout():
+    _gpu()
+    f, d = cqc.selftest_mfma()
+    i = np.arange(16)[:, None]
+    j = np.arange(16)[None, :]
+    ref = sum((i + 16 * k) * (1 + k + 4 * j) for k in range(4)).astype(np.float64)
+    assert np.array_equal(f.numpy().astype(np.float64), ref)
+    assert np.array_equal(d.numpy(), ref)
+
+
+def _run(entries_np, wcut, dtype, prec, out_dtype=None):
+    host, dev = to_dev(entries_np, dtype)
+    cut = cqc.CutMap.from_workload(wcut)
+    p, mass = cqc.reconstruct_fd(dev, cut, precision=prec, out_dtype=out_dtype)
+    torch.cuda.synchronize()
+    return host, p.cpu().numpy().astype(np.float64), float(mass.cpu())
+
+
+def _inner_terms(wcut):
+    cut = cqc.CutMap.from_workload(wcut)
+    _, macs = cqc.cost(cut)
+    return max(4, int(round(macs / 2 ** wcut.n)))
+
+
+@pytest.mark.parametrize("prec,dtype,tol,unit", [("fp64", torch.float64, 1e-12, U64),
+                                                 ("fp32", torch.float32, 1e-6, U32)])
+@pytest.mark.parametrize("shape", [((4, 3), (1,), 4), ((5, 5), (2,), 6), ((3, 2, 3), (3, 3), 4),
+                                   ((3, 3, 3), (2, 2), 6), ((2, 3, 3, 2), (1, 2, 2), 4),
+                                   ((6, 6), (3,), 6), ((7, 7), (2,), 4)])
+def test_fd_simulated_circuits(shape, prec, dtype, tol, unit):
+    _gpu()
+    own, bridges, layers = shape
+    inst = W.make_instance(own, bridges, layers, seed=101)
+    host, p, mass = _run(inst.entries, inst.cut, dtype, prec)
+    e64 = oracle_inputs(host)
+    ref = fd.reconstruct(e64, inst.cut)
+    err = metrics.rel_l1(p, ref)
+    print(f"{shape} {prec}: rel_l1={err:.3e}")
+    assert err <= tol
+    ok, info = elementwise_ok(p, ref, abs_bound(e64, inst.cut), unit, _inner_terms(inst.cut))
+    assert ok, info
+    assert abs(mass - ref.sum()) <= 1e-6 * np.abs(ref).sum()
+
+
+@pytest.mark.parametrize("prec,dtype,unit", [("fp64", torch.float64, U64), ("fp32", torch.float32, U32)])
+@pytest.mark.parametrize("case", ["perm", "kron2", "kron3", "single", "triangle", "ragged",
+                                  "zero_rows", "k0_f0"])
+def test_fd_random_structures(case, prec, dtype, unit):
+    _gpu()
+    C = W.CutMap
+    if case == "perm":          # outputs scattered over the global order
+        cut = C(9, [4, 5], [0, 0], [1, 1], [5, 0, 3, 8, 1, 2, 4, 7, 6])
+    elif case == "kron2":       # disconnected: plain Kronecker product
+        cut = C(7, [3, 4], [], [], list(range(7)))
+    elif case == "kron3":
+        cut = C(9, [2, 3, 4], [0], [1], list(range(9)))
+    elif case == "single":
+        cut = C(6, [6], [], [], [3, 1, 0, 5, 2, 4])
+    elif case == "triangle":    # cyclic subcircuit graph, reversed edge directions
+        cut = C(12, [4, 4, 4], [0, 1, 2, 0], [1, 2, 0, 1], list(range(12)))
+    elif case == "ragged":      # tiny and odd tile shapes: 1, 2, 8 wide operands
+        cut = C(11, [1, 2, 8], [0, 1, 1, 2], [1, 2, 2, 0], list(range(11)))
+    elif case == "zero_rows":   # early termination: some rows exactly zero
+        cut = C(10, [5, 5], [0, 0, 0], [1, 1, 1], list(range(10)))
+    else:                       # a subcircuit with no output qubit
+        cut = C(8, [0, 8], [0, 0], [1, 1], list(range(8)))
+    zr = ((0, 3), (0, 17), (1, 40), (1, 0)) if case == "zero_rows" else ()
+    seed = ["perm", "kron2", "kron3", "single", "triangle", "ragged", "zero_rows", "k0_f0"].index(case)
+    ents = W.random_entries(cut, seed=100 + seed, zero_rows=zr)
+    host, p, mass = _run(ents, cut, dtype, prec)
+    e64 = oracle_inputs(host)
+    ref = fd.reconstruct(e64, cut)
+    T = abs_bound(e64, cut)
+    ok, info = elementwise_ok(p, ref, T, unit, 4 ** cut.n_cuts)
+    assert ok, (case, info)
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    assert metrics.rel_l1(p, ref) <= tol * metrics.kappa(e64, cut, np.abs(ref).sum())
+
+
+def test_fd_c1_plain_fp64():
+    _gpu()
+    inst = W.config_instance("c1")
+    host, p, mass = _run(inst.entries, inst.cut, torch.float64, "fp64")
+    ref = fd.reconstruct(inst.entries, inst.cut)
+    assert metrics.rel_l1(p, ref) <= 1e-13
+    assert abs(mass - 1.0) <= 1e-13
+
+
+@pytest.mark.parametrize("prec,dtype,tol", [("fp32", torch.float32, 1e-6), ("fp64", torch.float64, 1e-12)])
+def test_fd_c2_full_vector(prec, dtype, tol):
+    """n=24, K=2, two 13-qubit subcircuits: the headline shape, all 2^24 outputs."""
+    _gpu()
+    inst = W.config_instance("c2")
+    host, p, mass = _run(inst.entries, inst.cut, dtype, prec)
+    e64 = oracle_inputs(host)
+    from oracle import native
+    ref = native.reconstruct(e64, inst.cut)
+    err = metrics.rel_l1(p, ref)
+    print(f"c2 {prec}: rel_l1={err:.3e} mass={mass!r}")
+    assert err <= tol
+    T = native.reconstruct([np.abs(E) for E in e64], inst.cut)
+    ok, info = elementwise_ok(p, ref, T, U32 if prec == "fp32" else U64, 16)
+    assert ok, info
+    assert abs(mass - ref.sum()) <= 1e-9
+
+
+def test_fd_c3_sampled():
+    """n=30, K=6, three subcircuits (2^30 outputs): sampled outputs against the
+    oracle's per-output definition, plus the FP64 mass."""
+    _gpu()
+    inst = W.config_instance("c3")
+    host, dev = to_dev(inst.entries, torch.float32)
+    cut = cqc.CutMap.from_workload(inst.cut)
+    p, mass = cqc.reconstruct_fd(dev, cut, precision="fp32")
+    xs = W.sample_outputs(inst.n, 4096, seed=33)
+    got = p[torch.from_numpy(xs).to("cuda")].cpu().numpy().astype(np.float64)
+    e64 = oracle_inputs(host)
+    ref = fd.reconstruct(e64, inst.cut, xs)
+    err = metrics.rel_l1(got, ref)
+    print(f"c3 sampled rel_l1={err:.3e} mass={float(mass.cpu())!r}")
+    assert err <= 1e-6
+    assert abs(float(mass.cpu()) - 1.0) <= 1e-5
+    ok, info = elementwise_ok(got, ref, abs_bound(e64, inst.cut, xs), U32, 64 + 64)
+    assert ok, info
+    del p
+
+
+def test_fd_bitwise_repeatable():
+    _gpu()
+    inst = W.make_instance((6, 6), (3,), 6, seed=5)
+    host, dev = to_dev(inst.entries, torch.float32)
+    cut = cqc.CutMap.from_workload(inst.cut)
+    a, ma = cqc.reconstruct_fd(dev, cut, precision="fp32")
+    b, mb = cqc.reconstruct_fd(dev, cut, precision="fp32")
+    assert torch.equal(a, b) and torch.equal(ma, mb)
+
+
+@pytest.mark.parametrize("in_dt,out_dt,prec", [(torch.float32, torch.float64, "fp64"),
+                                              (torch.float64, torch.float32, "fp32"),
+                                              (torch.float32, torch.float64, "fp32")])
+def test_fd_mixed_dtypes(in_dt, out_dt, prec):
+    _gpu()
+    inst = W.make_instance((5, 5), (2,), 6, seed=9)
+    host, dev = to_dev(inst.entries, in_dt)
+    cut = cqc.CutMap.from_workload(inst.cut)
+    p, mass = cqc.reconstruct_fd(dev, cut, precision=prec, out_dtype=out_dt)
+    assert p.dtype == out_dt
+    ref = fd.reconstruct(oracle_inputs(host), inst.cut)
+    assert metrics.rel_l1(p.cpu().numpy().astype(np.float64), ref) <= 1e-6
