@@ -11,9 +11,10 @@
 // per 256-label chunk in ascending s, so the accumulation order is fixed.
 //
 // Matrix-core mapping (16x16x4, one block): MFMA row i <-> output column n,
-// MFMA column j <-> output row m, so each lane ends with 4 consecutive n of
-// one m and stores them as one 16-byte vector; 16 lanes cover 64 contiguous
-// bytes of an output row.  The last step scales by 2^-K (exact) and reduces
+// MFMA column j <-> output row m.  In FP32 each lane ends with 4 consecutive n
+// of one m and stores them as one 16-byte vector (16 lanes cover 64 contiguous
+// bytes of an output row); the FP64 accumulator strides its rows by 4, so the
+// FP64 form stores element by element.  The last step scales by 2^-K (exact) and reduces
 // the FP64 sum of everything it wrote: per-block partials, then the last
 // block to finish adds the partials in block order.
 #include "kernels.hpp"
@@ -24,14 +25,20 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 template <typename T> struct MfmaOp;
+// Accumulator layout of one 16x16 block (measured by k_selftest_mfma):
+//   FP32: lane l, register r holds row 4*(l/16) + r   (4 consecutive rows)
+//   FP64: lane l, register r holds row (l/16) + 4*r   (rows strided by 4)
+// of column l%16, where "row" is the index contributed by the A operand.
 template <> struct MfmaOp<float> {
   using V = f32x4;
+  static constexpr bool kConsecutive = true;
   static __device__ __forceinline__ V run(float a, float b, V c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
 };
 template <> struct MfmaOp<double> {
   using V = f64x4;
+  static constexpr bool kConsecutive = false;
   static __device__ __forceinline__ V run(double a, double b, V c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
@@ -247,37 +254,57 @@ __global__ __launch_bounds__(256) void k_contract(const ContractArgs a) {
     if (m >= M) continue;
 #pragma unroll
     for (int j = 0; j < BNB; ++j) {
-      const int64_t n = n0 + wn0 + j * 16 + 4 * (lane >> 4);
-      if (n >= N) continue;
-      O v[4];
+      const int64_t nb = n0 + wn0 + j * 16;
+      if (Op::kConsecutive) {
+        const int64_t n = nb + 4 * (lane >> 4);
+        if (n >= N) continue;
+        if (a.mode == kModeIntermediate) {
+          T *Z = static_cast<T *>(a.Z) + batch * M * N + m * N + n;
+          T w[4] = {acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]};
+          if (n + 3 < N) store4<T>(Z, w);
+          else
+            for (int r = 0; r < 4; ++r)
+              if (n + r < N) Z[r] = w[r];
+        } else {
+          O v[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) v[r] = final_mode ? (O)(acc[i][j][r]) * scale : (O)acc[i][j][r];
-      if (a.mode == kModeIntermediate) {
-        T *Z = static_cast<T *>(a.Z) + batch * M * N + m * N + n;
-        T w[4] = {(T)acc[i][j][0], (T)acc[i][j][1], (T)acc[i][j][2], (T)acc[i][j][3]};
-        if (n + 3 < N) store4<T>(Z, w);
-        else
-          for (int r = 0; r < 4; ++r)
-            if (n + r < N) Z[r] = w[r];
-      } else if (a.mode == kModeFinalBlocked) {
-        O *Z = static_cast<O *>(a.Z) + m * N + n;
-        if (n + 3 < N) store4<O>(Z, v);
-        else
-          for (int r = 0; r < 4; ++r)
-            if (n + r < N) Z[r] = v[r];
-        for (int r = 0; r < 4; ++r)
-          if (n + r < N) msum += (double)v[r];
-      } else {
-        O *Z = static_cast<O *>(a.Z);
-        const int64_t ro = deposit(m, a.posX, a.logM);
-        for (int r = 0; r < 4; ++r)
-          if (n + r < N) {
-            Z[ro + deposit(n + r, a.posY, a.logN)] = v[r];
-            msum += (double)v[r];
+          for (int r = 0; r < 4; ++r) v[r] = (O)acc[i][j][r] * scale;
+          if (a.mode == kModeFinalBlocked) {
+            O *Z = static_cast<O *>(a.Z) + m * N + n;
+            if (n + 3 < N) store4<O>(Z, v);
+            else
+              for (int r = 0; r < 4; ++r)
+                if (n + r < N) Z[r] = v[r];
+          } else {
+            O *Z = static_cast<O *>(a.Z);
+            const int64_t ro = deposit(m, a.posX, a.logM);
+            for (int r = 0; r < 4; ++r)
+              if (n + r < N) Z[ro + deposit(n + r, a.posY, a.logN)] = v[r];
           }
+          for (int r = 0; r < 4; ++r)
+            if (n + r < N) msum += (double)v[r];
+        }
+      } else {
+        // rows strided by 4: one element per register
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t n = nb + (lane >> 4) + 4 * r;
+          if (n >= N) continue;
+          if (a.mode == kModeIntermediate) {
+            static_cast<T *>(a.Z)[batch * M * N + m * N + n] = acc[i][j][r];
+          } else {
+            const O v = (O)acc[i][j][r] * scale;
+            if (a.mode == kModeFinalBlocked)
+              static_cast<O *>(a.Z)[m * N + n] = v;
+            else
+              static_cast<O *>(a.Z)[deposit(m, a.posX, a.logM) + deposit(n, a.posY, a.logN)] = v;
+            msum += (double)v;
+          }
+        }
       }
     }
   }
+  (void)final_mode;
   if (a.mode == kModeIntermediate) {
     if (a.flagZ && tm == 0 && tn == 0 && tid == 0) a.flagZ[batch] = total_live > 0;
     return;
@@ -326,8 +353,8 @@ __global__ __launch_bounds__(256) void k_convert(const S *src, D *dst, int64_t c
 }
 
 // Lane-layout probe: D = A * B for one 16x16x4 block with A[i][k] = i + 16 k,
-// B[k][j] = 1 + k + 4 j (exact in FP32), stored as D[i][j] by the assumed
-// accumulator layout (lane holds rows 4*(lane/16)+r of column lane%16).
+// B[k][j] = 1 + k + 4 j (exact in FP32), stored as D[i][j] by the accumulator
+// layouts the contraction kernel relies on (MfmaOp above).
 __global__ void k_selftest_mfma(float *outf, double *outd) {
   const int lane = threadIdx.x;
   const int i = lane & 15, k = lane >> 4, j = lane & 15;
@@ -336,9 +363,9 @@ __global__ void k_selftest_mfma(float *outf, double *outd) {
   f64x4 cd = {0, 0, 0, 0};
   cd = __builtin_amdgcn_mfma_f64_16x16x4f64((double)(i + 16 * k), (double)(1 + k + 4 * j), cd, 0, 0, 0);
   for (int r = 0; r < 4; ++r) {
-    const int row = 4 * (lane >> 4) + r, col = lane & 15;
-    outf[row * 16 + col] = cf[r];
-    outd[row * 16 + col] = cd[r];
+    const int col = lane & 15;
+    outf[(4 * (lane >> 4) + r) * 16 + col] = cf[r];
+    outd[((lane >> 4) + 4 * r) * 16 + col] = cd[r];
   }
 }
 
