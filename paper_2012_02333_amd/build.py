@@ -42,7 +42,7 @@ def build(verbose=False, jobs=8):
     for p in procs:
         _wait(p)
     tmp = LIB + ".tmp"
-    subprocess.check_call([HIPCC] + FLAGS + objs + ["-o", tmp])
+    subprocess.check_call([HIPCC] + FLAGS + objs + ["-Wl,--no-undefined", "-o", tmp])
     os.replace(tmp, LIB)
     return LIB
 

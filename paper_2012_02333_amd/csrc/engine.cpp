@@ -16,7 +16,10 @@ NetLayout layout_net(const Plan &plan, Acc acc, size_t base) {
   L.f_off.assign(nt, 0);
   for (size_t t = 0; t < nt; ++t) {
     L.f_off[t] = off;
-    off = align_up(off + sizeof(int32_t) * (size_t)plan.tensors[t].rows(), 256);
+    const auto &T = plan.tensors[t];
+    // entry tensors carry chunk flags; intermediates one flag per row
+    const int64_t nch = T.entry >= 0 ? flag_chunks(T.cols()) : 1;
+    off = align_up(off + sizeof(int32_t) * (size_t)(T.rows() * nch), 256);
   }
   const int last = (int)plan.steps.size() - 1;
   for (size_t t = 0; t < nt; ++t) {
@@ -42,21 +45,26 @@ NetLayout layout_net(const Plan &plan, Acc acc, size_t base) {
   if (last >= 0) max_final_blocks = L.nblocks[last];
   L.partials_off = off;
   off = align_up(off + 8 * (size_t)max_final_blocks, 256);
-  L.counter_off = off;
-  off = align_up(off + 8, 256);
   L.bytes = off;
   return L;
 }
 
-static DigitMapDev to_dev(const DigitMap &m) {
+DigitMapDev to_dev(const DigitMap &m) {
   DigitMapDev d;
   std::memset(&d, 0, sizeof(d));
   d.n = m.n;
   for (int i = 0; i < m.n; ++i) {
-    d.src[i] = m.src[i];
-    d.shift[i] = m.shift[i];
+    if (m.src[i]) d.srcmask |= 1u << i;
+    d.shifts[i / 10] |= (uint64_t)(m.shift[i] & 63) << (6 * (i % 10));
   }
   return d;
+}
+
+BitPos pack_pos(const std::vector<int> &pos) {
+  BitPos b;
+  std::memset(&b, 0, sizeof(b));
+  for (size_t j = 0; j < pos.size(); ++j) b.w[j / 10] |= (uint64_t)(pos[j] & 63) << (6 * (j % 10));
+  return b;
 }
 
 Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &entries,
@@ -70,11 +78,10 @@ Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &en
     if (T.entry >= 0) tptr[t] = entries[T.entry];
     else tptr[t] = ws + L.t_off[t];
   }
-  uint32_t *counter = reinterpret_cast<uint32_t *>(ws + L.counter_off);
   if (compute_entry_flags) {
     FlagArgs fa;
     std::memset(&fa, 0, sizeof(fa));
-    int64_t rows = 0;
+    int64_t blocks = 0;
     int n = 0;
     for (size_t t = 0; t < nt; ++t) {
       const auto &T = p.tensors[t];
@@ -84,17 +91,16 @@ Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &en
       d.rows = T.rows();
       d.cols = T.cols();
       d.flags = reinterpret_cast<int32_t *>(ws + L.f_off[t]);
-      d.row_start = rows;
-      rows += T.rows();
+      d.block_start = blocks;
+      blocks += T.rows() * flag_chunks(T.cols());
     }
     fa.n = n;
     fa.is_double = L.acc == Acc::F64;
-    fa.counter = counter;
     if (p.single) {
       fa.unit = ws + L.t_off[1];
       fa.unit_flag = reinterpret_cast<int32_t *>(ws + L.f_off[1]);
     }
-    CQC_TRY(launch_row_flags(fa, rows, s));
+    CQC_TRY(launch_row_flags(fa, blocks, s));
   }
   for (size_t i = 0; i < p.steps.size(); ++i) {
     const Step &st = p.steps[i];
@@ -105,6 +111,8 @@ Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &en
     a.Y = tptr[st.y];
     a.flagX = reinterpret_cast<const int32_t *>(ws + L.f_off[st.x]);
     a.flagY = reinterpret_cast<const int32_t *>(ws + L.f_off[st.y]);
+    a.nchX = p.tensors[st.x].entry >= 0 ? (int)flag_chunks(p.tensors[st.x].cols()) : 1;
+    a.nchY = p.tensors[st.y].entry >= 0 ? (int)flag_chunks(p.tensors[st.y].cols()) : 1;
     a.logM = st.logM;
     a.logN = st.logN;
     a.nS = (int)st.S.size();
@@ -131,15 +139,15 @@ Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &en
         a.mode = kModeFinalDeposit;
         const auto &X = p.tensors[st.x], &Y = p.tensors[st.y];
         const int nX = (int)X.bits.size(), nY = (int)Y.bits.size();
-        for (int j = 0; j < nX; ++j) a.posX[j] = (int8_t)p.bitpos[X.bits[nX - 1 - j]];
-        for (int j = 0; j < nY; ++j) a.posY[j] = (int8_t)p.bitpos[Y.bits[nY - 1 - j]];
+        std::vector<int> px(nX), py(nY);
+        for (int j = 0; j < nX; ++j) px[j] = p.bitpos[X.bits[nX - 1 - j]];
+        for (int j = 0; j < nY; ++j) py[j] = p.bitpos[Y.bits[nY - 1 - j]];
+        a.posX = pack_pos(px);
+        a.posY = pack_pos(py);
       }
-      if (mass) {
-        a.partials = reinterpret_cast<double *>(ws + L.partials_off);
-        a.counter = counter;
-        a.mass = mass;
-      }
+      if (mass) a.partials = reinterpret_cast<double *>(ws + L.partials_off);
       CQC_TRY(launch_contract(L.acc, out_double, L.tile[i], a, s));
+      if (mass) CQC_TRY(launch_mass_final(a.partials, a.nblocks, mass, s));
     }
   }
   return Status::ok();

@@ -16,7 +16,7 @@ struct NetLayout {
   std::vector<size_t> f_off;   // row flags of every tensor: byte offset
   std::vector<int> tile;       // per step
   std::vector<int64_t> nblocks;
-  size_t partials_off = 0, counter_off = 0;
+  size_t partials_off = 0;
   size_t bytes = 0;            // end offset (relative to the layout base)
 };
 
@@ -29,6 +29,9 @@ NetLayout layout_net(const Plan &plan, Acc acc, size_t base);
 Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &entries,
                void *out, bool out_double, double *mass, bool compute_entry_flags,
                hipStream_t s);
+
+DigitMapDev to_dev(const DigitMap &m);
+BitPos pack_pos(const std::vector<int> &pos);
 
 inline bool is_blocked(const Plan &p, const Step &st) {
   const auto &X = p.tensors[st.x], &Y = p.tensors[st.y];

@@ -4,17 +4,21 @@
 // gathered operand rows:
 //     C_b[m][n] = sum_{s live} X[rowX(s, rX)][m] * Y[rowY(s, rY)][n]
 // Both operands are "k-major" (a label row is a contiguous vector over output
-// columns), so every LDS stage loads whole row segments with 16-byte loads.
-// The inner index s enumerates the assignments of the shared cut labels; a
-// term whose X row or Y row is entirely zero is dropped before it reaches the
-// matrix cores (early termination, Section 4.2).  Live terms are compacted
-// per 256-label chunk in ascending s, so the accumulation order is fixed.
+// columns) and small next to the output, so every wave loads its operands
+// straight from L2 into registers in the matrix-core lane layout (16 lanes read
+// 16 consecutive columns of one label row) and runs independently of the other
+// waves: no LDS staging and no barrier inside the term loop.  The inner index
+// s enumerates the assignments of the shared cut labels; a term whose X row or
+// Y row is entirely zero is dropped before it reaches the matrix cores (early
+// termination, Section 4.2).  Live terms are compacted per 256-label chunk in
+// ascending s into a per-block gather list, so the accumulation order is fixed.
 //
 // Matrix-core mapping (16x16x4, one block): MFMA row i <-> output column n,
 // MFMA column j <-> output row m.  In FP32 each lane ends with 4 consecutive n
 // of one m and stores them as one 16-byte vector (16 lanes cover 64 contiguous
-// bytes of an output row); the FP64 accumulator strides its rows by 4, so the
-// FP64 form stores element by element.  The last step scales by 2^-K (exact) and reduces
+// bytes of an output row).  The FP64 accumulator strides its rows by 4, so the
+// FP64 form swaps the operands (MFMA row <-> m): 16 lanes then hold 16
+// consecutive n of one row and store 128 contiguous bytes per register.  The last step scales by 2^-K (exact) and reduces
 // the FP64 sum of everything it wrote: per-block partials, then the last
 // block to finish adds the partials in block order.
 #include "kernels.hpp"
@@ -48,17 +52,30 @@ __device__ __forceinline__ int row_of(const DigitMapDev &m, int s, int r) {
   int row = 0;
 #pragma unroll 1
   for (int i = 0; i < m.n; ++i) {
-    int v = m.src[i] ? r : s;
-    row = (row << 2) | ((v >> m.shift[i]) & 3);
+    const int v = ((m.srcmask >> i) & 1u) ? r : s;
+    const uint64_t w = i < 10 ? m.shifts[0] : m.shifts[1];
+    const int sh = (int)((w >> (6 * (i < 10 ? i : i - 10))) & 63);
+    row = (row << 2) | ((v >> sh) & 3);
   }
   return row;
 }
 
-__device__ __forceinline__ int64_t deposit(int64_t v, const int8_t *pos, int nbits) {
+__device__ int64_t deposit(int64_t v, const BitPos &pos, int nbits) {
   int64_t out = 0;
 #pragma unroll 1
-  for (int j = 0; j < nbits; ++j) out |= ((v >> j) & 1) << pos[j];
+  for (int j = 0; j < nbits; ++j) {
+    const uint64_t w = pos.w[0] * (j / 10 == 0) + pos.w[1] * (j / 10 == 1) + pos.w[2] * (j / 10 == 2) +
+                       pos.w[3] * (j / 10 == 3) + pos.w[4] * (j / 10 == 4);
+    out |= ((v >> j) & 1) << ((w >> (6 * (j % 10))) & 63);
+  }
   return out;
+}
+
+// A row is live if any of its chunk flags is set.
+__device__ __forceinline__ int row_live(const int32_t *flags, int nch, int row) {
+  int any = 0;
+  for (int c = 0; c < nch; ++c) any |= flags[(int64_t)row * nch + c];
+  return any != 0;
 }
 
 // Spread consecutive logical blocks over one XCD: hardware dispatches block i
@@ -89,12 +106,6 @@ template <> __device__ __forceinline__ void store4<double>(double *p, const doub
   reinterpret_cast<double2 *>(p)[1] = make_double2(v[2], v[3]);
 }
 
-__device__ __forceinline__ double atomic_load_f64(const double *p) {
-  unsigned long long u = __hip_atomic_load(reinterpret_cast<const unsigned long long *>(p),
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return __longlong_as_double((long long)u);
-}
-
 // Block-wide FP64 sum in a fixed order (wave butterfly, then waves 0..3).
 __device__ __forceinline__ double block_sum_f64(double v, double *red) {
 #pragma unroll
@@ -108,55 +119,43 @@ __device__ __forceinline__ double block_sum_f64(double v, double *red) {
   return t;
 }
 
-// Last block of the grid adds all per-block partials in block order.
-__device__ void finish_mass(const ContractArgs &a, int64_t my_block, double block_total,
-                            double *red) {
-  __shared__ int is_last;
-  if (threadIdx.x == 0) {
-    a.partials[my_block] = block_total;
-    __threadfence();
-    unsigned prev = atomicAdd(a.counter, 1u);
-    is_last = (prev == (unsigned)(a.nblocks - 1));
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  double v = 0.0;
-  for (int64_t i = threadIdx.x; i < a.nblocks; i += blockDim.x) v += atomic_load_f64(&a.partials[i]);
-  // fixed-order tree over the 256 thread sums
+// FP64 mass: every block of the last step stores the FP64 sum of what it
+// wrote; k_mass_final then adds the partials in block order.  (A completion
+// counter in the contraction kernel would need a device-scope release fence
+// per block, which on a multi-XCD part writes back the L2 - full of freshly
+// written outputs - once per block.)
+__global__ __launch_bounds__(256) void k_mass_final(const double *partials, int64_t count,
+                                                    double *mass) {
   __shared__ double tsum[256];
+  double v = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += blockDim.x) v += partials[i];
   tsum[threadIdx.x] = v;
   __syncthreads();
   for (int w = 128; w >= 1; w >>= 1) {
     if ((int)threadIdx.x < w) tsum[threadIdx.x] += tsum[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    if (a.mass) a.mass[0] = tsum[0];
-    *a.counter = 0u;
-  }
-  (void)red;
+  if (threadIdx.x == 0) mass[0] = tsum[0];
 }
 
-template <typename T, typename O, int BM, int BN, int WM, int WN>
+template <typename T, typename O, int BM, int BN, int WM, int WN, int MODE>
 __global__ __launch_bounds__(256) void k_contract(const ContractArgs a) {
-  constexpr int BK = 16;
-  constexpr int TM = BM / WM, TN = BN / WN;
-  constexpr int BMB = TM / 16, BNB = TN / 16;
-  constexpr int PAD = sizeof(T) == 4 ? 16 : 8;
+  constexpr int TM = BM / WM, TN = BN / WN;     // wave tile
+  constexpr int BMB = TM / 16, BNB = TN / 16;    // 16x16 blocks per wave
+  constexpr int KG = 4;                          // k-quads per register group (16 terms)
   static_assert(WM * WN == 4, "four waves");
   static_assert(BMB >= 1 && BNB >= 1, "wave tile at least 16x16");
   using Op = MfmaOp<T>;
   using V = typename Op::V;
 
-  __shared__ T Xs[BK][BM + PAD];
-  __shared__ T Ys[BK][BN + PAD];
-  __shared__ int2 lst[256];
+  __shared__ int2 lst[256 + 16];
   __shared__ int wcnt[4];
   __shared__ double red[4];
+  __shared__ int64_t rowoff[MODE == kModeFinalDeposit ? BM : 1];
+  __shared__ int64_t coloff[MODE == kModeFinalDeposit ? BN : 1];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t blk = xcd_remap(blockIdx.x, a.nblocks);
+  const int64_t blk = a.xcd_remap ? xcd_remap(blockIdx.x, a.nblocks) : (int64_t)blockIdx.x;
   const int64_t tiles = (int64_t)a.tilesM * a.tilesN;
   const int64_t batch = blk / tiles;
   const int64_t t = blk - batch * tiles;
@@ -164,10 +163,26 @@ __global__ __launch_bounds__(256) void k_contract(const ContractArgs a) {
   const int rX = (int)(batch >> (2 * a.nRY));
   const int rY = (int)(batch & ((int64_t(1) << (2 * a.nRY)) - 1));
   const int64_t M = int64_t(1) << a.logM, N = int64_t(1) << a.logN;
-  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
-  const int wm0 = (wave / WN) * TM, wn0 = (wave % WN) * TN;
+  const int64_t mw = (int64_t)tm * BM + (wave / WN) * TM;   // this wave's first m
+  const int64_t nw = (int64_t)tn * BN + (wave % WN) * TN;   // this wave's first n
   const T *X = static_cast<const T *>(a.X);
   const T *Y = static_cast<const T *>(a.Y);
+  const int l16 = lane & 15, lg = lane >> 4;
+  if (MODE == kModeFinalDeposit) {
+    // output offsets of this block's rows and columns (bit deposit, once)
+    for (int r = tid; r < BM; r += 256)
+      rowoff[r] = (int64_t)tm * BM + r < M ? deposit((int64_t)tm * BM + r, a.posX, a.logM) : 0;
+    for (int c = tid; c < BN; c += 256)
+      coloff[c] = (int64_t)tn * BN + c < N ? deposit((int64_t)tn * BN + c, a.posY, a.logN) : 0;
+  }
+
+  // column offsets of this lane's operands (masked where the tile overhangs)
+  int64_t xcol[BMB], ycol[BNB];
+  bool xok[BMB], yok[BNB];
+#pragma unroll
+  for (int i = 0; i < BMB; ++i) { xcol[i] = mw + i * 16 + l16; xok[i] = xcol[i] < M; }
+#pragma unroll
+  for (int j = 0; j < BNB; ++j) { ycol[j] = nw + j * 16 + l16; yok[j] = ycol[j] < N; }
 
   V acc[BMB][BNB];
 #pragma unroll
@@ -178,13 +193,13 @@ __global__ __launch_bounds__(256) void k_contract(const ContractArgs a) {
   const int nSv = 1 << (2 * a.nS);
   int total_live = 0;
   for (int s0 = 0; s0 < nSv; s0 += 256) {
-    // ---- compact the live labels of this chunk, ascending s
+    // ---- compact the live labels of this chunk, ascending s (zero-padded to 16)
     const int s = s0 + tid;
     int live = 0, rx = 0, ry = 0;
     if (s < nSv) {
       rx = row_of(a.mx, s, rX);
       ry = row_of(a.my, s, rY);
-      live = (a.flagX[rx] != 0) && (a.flagY[ry] != 0);
+      live = row_live(a.flagX, a.nchX, rx) & row_live(a.flagY, a.nchY, ry);
     }
     const unsigned long long bal = __ballot(live);
     const int pre = __popcll(bal & ((1ull << lane) - 1ull));
@@ -194,71 +209,49 @@ __global__ __launch_bounds__(256) void k_contract(const ContractArgs a) {
     for (int w = 0; w < wave; ++w) base += wcnt[w];
     const int cnt = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
     if (live) lst[base + pre] = make_int2(rx, ry);
+    if (tid < 16) lst[cnt + tid] = make_int2(-1, -1);
     __syncthreads();
     total_live += cnt;
 
-    for (int k0 = 0; k0 < cnt; k0 += BK) {
-      // ---- stage BK gathered rows of X (BM wide) and Y (BN wide) in LDS
-      for (int idx = tid * 4; idx < BK * BM; idx += 1024) {
-        const int r = idx / BM, c = idx - r * BM;
-        T v[4] = {0, 0, 0, 0};
-        if (k0 + r < cnt) {
-          const T *src = X + (int64_t)lst[k0 + r].x * M + m0 + c;
-          if (m0 + c + 3 < M) load4<T>(src, v);
-          else
-            for (int e = 0; e < 4; ++e)
-              if (m0 + c + e < M) v[e] = src[e];
-        }
+    // ---- term sum: operands straight from L2 into registers, 16 terms at a time
+    for (int k0 = 0; k0 < cnt; k0 += 4 * KG) {
+      T bx[KG][BMB], ay[KG][BNB];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) Xs[r][c + e] = v[e];
+      for (int q = 0; q < KG; ++q) {
+        const int2 rr = lst[k0 + 4 * q + lg];
+        const bool kok = rr.x >= 0;
+        const T *xr = X + (int64_t)(kok ? rr.x : 0) * M;
+        const T *yr = Y + (int64_t)(kok ? rr.y : 0) * N;
+#pragma unroll
+        for (int i = 0; i < BMB; ++i) bx[q][i] = (kok && xok[i]) ? xr[xcol[i]] : (T)0;
+#pragma unroll
+        for (int j = 0; j < BNB; ++j) ay[q][j] = (kok && yok[j]) ? yr[ycol[j]] : (T)0;
       }
-      for (int idx = tid * 4; idx < BK * BN; idx += 1024) {
-        const int r = idx / BN, c = idx - r * BN;
-        T v[4] = {0, 0, 0, 0};
-        if (k0 + r < cnt) {
-          const T *src = Y + (int64_t)lst[k0 + r].y * N + n0 + c;
-          if (n0 + c + 3 < N) load4<T>(src, v);
-          else
-            for (int e = 0; e < 4; ++e)
-              if (n0 + c + e < N) v[e] = src[e];
-        }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) Ys[r][c + e] = v[e];
-      }
-      __syncthreads();
-      // ---- matrix cores
-#pragma unroll
-      for (int kq = 0; kq < BK; kq += 4) {
-        const int kr = kq + (lane >> 4);
-        T bx[BMB], ay[BNB];
-#pragma unroll
-        for (int i = 0; i < BMB; ++i) bx[i] = Xs[kr][wm0 + i * 16 + (lane & 15)];
-#pragma unroll
-        for (int j = 0; j < BNB; ++j) ay[j] = Ys[kr][wn0 + j * 16 + (lane & 15)];
+      for (int q = 0; q < KG; ++q)
 #pragma unroll
         for (int i = 0; i < BMB; ++i)
 #pragma unroll
-          for (int j = 0; j < BNB; ++j) acc[i][j] = Op::run(ay[j], bx[i], acc[i][j]);
-      }
-      __syncthreads();
+          for (int j = 0; j < BNB; ++j)
+            acc[i][j] = Op::kConsecutive ? Op::run(ay[q][j], bx[q][i], acc[i][j])
+                                         : Op::run(bx[q][i], ay[q][j], acc[i][j]);
     }
+    __syncthreads();   // lst is rewritten by the next chunk
   }
 
   // ---- epilogue
   double msum = 0.0;
-  const bool final_mode = a.mode != kModeIntermediate;
   const O scale = (O)a.scale;
 #pragma unroll
   for (int i = 0; i < BMB; ++i) {
-    const int64_t m = m0 + wm0 + i * 16 + (lane & 15);
-    if (m >= M) continue;
 #pragma unroll
     for (int j = 0; j < BNB; ++j) {
-      const int64_t nb = n0 + wn0 + j * 16;
+      const int64_t nb = nw + j * 16;
       if (Op::kConsecutive) {
-        const int64_t n = nb + 4 * (lane >> 4);
-        if (n >= N) continue;
-        if (a.mode == kModeIntermediate) {
+        const int64_t m = mw + i * 16 + l16;
+        const int64_t n = nb + 4 * lg;
+        if (m >= M || n >= N) continue;
+        if (MODE == kModeIntermediate) {
           T *Z = static_cast<T *>(a.Z) + batch * M * N + m * N + n;
           T w[4] = {acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]};
           if (n + 3 < N) store4<T>(Z, w);
@@ -269,7 +262,7 @@ __global__ __launch_bounds__(256) void k_contract(const ContractArgs a) {
           O v[4];
 #pragma unroll
           for (int r = 0; r < 4; ++r) v[r] = (O)acc[i][j][r] * scale;
-          if (a.mode == kModeFinalBlocked) {
+          if (MODE == kModeFinalBlocked) {
             O *Z = static_cast<O *>(a.Z) + m * N + n;
             if (n + 3 < N) store4<O>(Z, v);
             else
@@ -277,70 +270,243 @@ __global__ __launch_bounds__(256) void k_contract(const ContractArgs a) {
                 if (n + r < N) Z[r] = v[r];
           } else {
             O *Z = static_cast<O *>(a.Z);
-            const int64_t ro = deposit(m, a.posX, a.logM);
+            const int64_t ro = rowoff[m - (int64_t)tm * BM];
             for (int r = 0; r < 4; ++r)
-              if (n + r < N) Z[ro + deposit(n + r, a.posY, a.logN)] = v[r];
+              if (n + r < N) Z[ro + coloff[n + r - (int64_t)tn * BN]] = v[r];
           }
           for (int r = 0; r < 4; ++r)
             if (n + r < N) msum += (double)v[r];
         }
       } else {
-        // rows strided by 4: one element per register
+        // FP64: operands swapped (MFMA row <-> m), so register r of lane l holds
+        // output row mb + l/16 + 4r at column nb + l%16: 16 lanes store 128
+        // contiguous bytes of one row.
+        const int64_t n = nb + l16;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int64_t n = nb + (lane >> 4) + 4 * r;
-          if (n >= N) continue;
-          if (a.mode == kModeIntermediate) {
+          const int64_t m = mw + i * 16 + lg + 4 * r;
+          if (m >= M || n >= N) continue;
+          if (MODE == kModeIntermediate) {
             static_cast<T *>(a.Z)[batch * M * N + m * N + n] = acc[i][j][r];
           } else {
             const O v = (O)acc[i][j][r] * scale;
-            if (a.mode == kModeFinalBlocked)
+            if (MODE == kModeFinalBlocked)
               static_cast<O *>(a.Z)[m * N + n] = v;
             else
-              static_cast<O *>(a.Z)[deposit(m, a.posX, a.logM) + deposit(n, a.posY, a.logN)] = v;
+              static_cast<O *>(a.Z)[rowoff[m - (int64_t)tm * BM] + coloff[n - (int64_t)tn * BN]] = v;
             msum += (double)v;
           }
         }
       }
     }
   }
-  (void)final_mode;
-  if (a.mode == kModeIntermediate) {
+  if (MODE == kModeIntermediate) {
     if (a.flagZ && tm == 0 && tn == 0 && tid == 0) a.flagZ[batch] = total_live > 0;
     return;
   }
   if (a.partials) {
     const double tot = block_sum_f64(msum, red);
-    finish_mass(a, blockIdx.x, tot, red);
+    if (tid == 0) a.partials[blockIdx.x] = tot;
+  }
+}
+
+// Variant for at most 16 live terms (4^|S| <= 16): the Y operands of every
+// term stay in registers, and each 16-row block of the wave tile is written
+// as soon as its matrix-core products are done, so stores start early and
+// few registers are live (all blocks of a launch fit on the chip at once).
+template <typename T, typename O, int BM, int BN, int WM, int WN, int MODE>
+__global__ __launch_bounds__(256) void k_contract_small(const ContractArgs a) {
+  constexpr int TM = BM / WM, TN = BN / WN;
+  constexpr int BMB = TM / 16, BNB = TN / 16;
+  static_assert(WM * WN == 4, "four waves");
+  using Op = MfmaOp<T>;
+  using V = typename Op::V;
+
+  __shared__ int2 lst[16];
+  __shared__ double red[4];
+  __shared__ int64_t rowoff[MODE == kModeFinalDeposit ? BM : 1];
+  __shared__ int64_t coloff[MODE == kModeFinalDeposit ? BN : 1];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t blk = a.xcd_remap ? (uint32_t)xcd_remap(blockIdx.x, a.nblocks) : blockIdx.x;
+  const uint32_t tiles = (uint32_t)a.tilesM * (uint32_t)a.tilesN;
+  const uint32_t batch = blk / tiles;
+  const uint32_t t = blk - batch * tiles;
+  const uint32_t tm = t / (uint32_t)a.tilesN, tn = t - tm * (uint32_t)a.tilesN;
+  const int rX = (int)(batch >> (2 * a.nRY));
+  const int rY = (int)(batch & ((1u << (2 * a.nRY)) - 1u));
+  const int64_t M = int64_t(1) << a.logM, N = int64_t(1) << a.logN;
+  const int64_t mw = (int64_t)tm * BM + (wave / WN) * TM;
+  const int64_t nw = (int64_t)tn * BN + (wave % WN) * TN;
+  const T *X = static_cast<const T *>(a.X);
+  const T *Y = static_cast<const T *>(a.Y);
+  const int l16 = lane & 15, lg = lane >> 4;
+
+  if (MODE == kModeFinalDeposit) {
+    for (int r = tid; r < BM; r += 256)
+      rowoff[r] = (int64_t)tm * BM + r < M ? deposit((int64_t)tm * BM + r, a.posX, a.logM) : 0;
+    for (int c = tid; c < BN; c += 256)
+      coloff[c] = (int64_t)tn * BN + c < N ? deposit((int64_t)tn * BN + c, a.posY, a.logN) : 0;
+  }
+  // live terms (ascending s), computed by the first 16 lanes of wave 0
+  const int nSv = 1 << (2 * a.nS);
+  int cnt = 0;
+  if (wave == 0) {
+    int live = 0, rx = 0, ry = 0;
+    if (lane < nSv) {
+      rx = row_of(a.mx, lane, rX);
+      ry = row_of(a.my, lane, rY);
+      live = row_live(a.flagX, a.nchX, rx) & row_live(a.flagY, a.nchY, ry);
+    }
+    const unsigned long long bal = __ballot(live);
+    const int pre = __popcll(bal & ((1ull << lane) - 1ull));
+    cnt = __popcll(bal);
+    if (live) lst[pre] = make_int2(rx, ry);
+    if (lane >= cnt && lane < 16) lst[lane] = make_int2(-1, -1);
+  }
+  __syncthreads();
+  // Y operands of all terms for this wave's columns
+  T ay[4][BNB];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int2 rr = lst[4 * q + lg];
+    const bool kok = rr.x >= 0;
+    const T *yr = Y + (int64_t)(kok ? rr.y : 0) * N;
+#pragma unroll
+    for (int j = 0; j < BNB; ++j) {
+      const int64_t c = nw + j * 16 + l16;
+      ay[q][j] = (kok && c < N) ? yr[c] : (T)0;
+    }
+  }
+  int2 rrq[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) rrq[q] = lst[4 * q + lg];
+
+  double msum = 0.0;
+  const O scale = (O)a.scale;
+#pragma unroll
+  for (int i = 0; i < BMB; ++i) {
+    T bx[4];
+    const int64_t xc = mw + i * 16 + l16;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      bx[q] = (rrq[q].x >= 0 && xc < M) ? X[(int64_t)rrq[q].x * M + xc] : (T)0;
+    V acc[BNB];
+#pragma unroll
+    for (int j = 0; j < BNB; ++j) acc[j] = V{0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int j = 0; j < BNB; ++j)
+        acc[j] = Op::kConsecutive ? Op::run(ay[q][j], bx[q], acc[j]) : Op::run(bx[q], ay[q][j], acc[j]);
+#pragma unroll
+    for (int j = 0; j < BNB; ++j) {
+      const int64_t nb = nw + j * 16;
+      if (Op::kConsecutive) {
+        const int64_t m = mw + i * 16 + l16;
+        const int64_t n = nb + 4 * lg;
+        if (m >= M || n >= N) continue;
+        if (MODE == kModeIntermediate) {
+          T *Z = static_cast<T *>(a.Z) + (int64_t)batch * M * N + m * N + n;
+          T w[4] = {acc[j][0], acc[j][1], acc[j][2], acc[j][3]};
+          if (n + 3 < N) store4<T>(Z, w);
+          else
+            for (int r = 0; r < 4; ++r)
+              if (n + r < N) Z[r] = w[r];
+        } else {
+          O v[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) v[r] = (O)acc[j][r] * scale;
+          if (MODE == kModeFinalBlocked) {
+            O *Z = static_cast<O *>(a.Z) + m * N + n;
+            if (n + 3 < N) store4<O>(Z, v);
+            else
+              for (int r = 0; r < 4; ++r)
+                if (n + r < N) Z[r] = v[r];
+          } else {
+            O *Z = static_cast<O *>(a.Z);
+            const int64_t ro = rowoff[m - (int64_t)tm * BM];
+            for (int r = 0; r < 4; ++r)
+              if (n + r < N) Z[ro + coloff[n + r - (int64_t)tn * BN]] = v[r];
+          }
+          for (int r = 0; r < 4; ++r)
+            if (n + r < N) msum += (double)v[r];
+        }
+      } else {
+        const int64_t n = nb + l16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t m = mw + i * 16 + lg + 4 * r;
+          if (m >= M || n >= N) continue;
+          if (MODE == kModeIntermediate) {
+            static_cast<T *>(a.Z)[(int64_t)batch * M * N + m * N + n] = acc[j][r];
+          } else {
+            const O v = (O)acc[j][r] * scale;
+            if (MODE == kModeFinalBlocked)
+              static_cast<O *>(a.Z)[m * N + n] = v;
+            else
+              static_cast<O *>(a.Z)[rowoff[m - (int64_t)tm * BM] + coloff[n - (int64_t)tn * BN]] = v;
+            msum += (double)v;
+          }
+        }
+      }
+    }
+  }
+  if (MODE == kModeIntermediate) {
+    if (a.flagZ && tm == 0 && tn == 0 && tid == 0) a.flagZ[batch] = lst[0].x >= 0;
+    return;
+  }
+  if (a.partials) {
+    const double tot = block_sum_f64(msum, red);
+    if (tid == 0) a.partials[blockIdx.x] = tot;
   }
 }
 
 // ---------------------------------------------------------------------------
-// Row flags of the entry tensors: flag[r] = row r has a non-zero element.
+// Row flags of the entry tensors: one block per (row, chunk of kFlagChunk
+// columns) writes whether that chunk has a non-zero element.
 __global__ __launch_bounds__(256) void k_row_flags(const FlagArgs a) {
   const int64_t bid = blockIdx.x;
   int i = 0;
-  while (i + 1 < a.n && bid >= a.d[i + 1].row_start) ++i;
+  while (i + 1 < a.n && bid >= a.d[i + 1].block_start) ++i;
   const FlagDesc &d = a.d[i];
-  const int64_t r = bid - d.row_start;
+  const int64_t nch = flag_chunks(d.cols);
+  const int64_t rc = bid - d.block_start;
+  const int64_t r = rc / nch, ch = rc - r * nch;
+  const int64_t c0 = ch * kFlagChunk, c1 = min(d.cols, c0 + kFlagChunk);
   int any = 0;
   if (a.is_double) {
     const double *p = static_cast<const double *>(d.ptr) + r * d.cols;
-    for (int64_t c = threadIdx.x; c < d.cols; c += blockDim.x) any |= (p[c] != 0.0);
+    if (d.cols % 2 == 0) {
+      const double2 *q = reinterpret_cast<const double2 *>(p);
+#pragma unroll 4
+      for (int64_t c = c0 / 2 + threadIdx.x; c < c1 / 2; c += blockDim.x) {
+        const double2 v = q[c];
+        any |= (v.x != 0.0) | (v.y != 0.0);
+      }
+    } else {
+      for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) any |= (p[c] != 0.0);
+    }
   } else {
     const float *p = static_cast<const float *>(d.ptr) + r * d.cols;
-    for (int64_t c = threadIdx.x; c < d.cols; c += blockDim.x) any |= (p[c] != 0.0f);
+    if (d.cols % 4 == 0) {
+      const float4 *q = reinterpret_cast<const float4 *>(p);
+#pragma unroll 2
+      for (int64_t c = c0 / 4 + threadIdx.x; c < c1 / 4; c += blockDim.x) {
+        const float4 v = q[c];
+        any |= (v.x != 0.0f) | (v.y != 0.0f) | (v.z != 0.0f) | (v.w != 0.0f);
+      }
+    } else {
+      for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) any |= (p[c] != 0.0f);
+    }
   }
   any = __syncthreads_or(any);
   if (threadIdx.x == 0) {
-    d.flags[r] = any ? 1 : 0;
-    if (bid == 0) {
-      if (a.counter) *a.counter = 0u;
-      if (a.unit) {
-        if (a.is_double) *static_cast<double *>(a.unit) = 1.0;
-        else *static_cast<float *>(a.unit) = 1.0f;
-        *a.unit_flag = 1;
-      }
+    d.flags[rc] = any ? 1 : 0;
+    if (bid == 0 && a.unit) {
+      if (a.is_double) *static_cast<double *>(a.unit) = 1.0;
+      else *static_cast<float *>(a.unit) = 1.0f;
+      *a.unit_flag = 1;
     }
   }
 }
@@ -387,15 +553,30 @@ int choose_tile(int logM, int logN) {
   return kTileS;
 }
 
+template <typename T, typename O, int MODE>
+static Status launch_contract_m(int cfg, const ContractArgs &a, hipStream_t s) {
+  const dim3 grid((unsigned)a.nblocks), block(256);
+  if (a.nS <= 2) {
+    switch (cfg) {
+      case kTileL: return launch("contract_small_64x256", k_contract_small<T, O, 64, 256, 1, 4, MODE>, grid, block, 0, s, a);
+      case kTileM: return launch("contract_small_32x128", k_contract_small<T, O, 32, 128, 1, 4, MODE>, grid, block, 0, s, a);
+      case kTileS: return launch("contract_small_16x64", k_contract_small<T, O, 16, 64, 1, 4, MODE>, grid, block, 0, s, a);
+      default: return launch("contract_small_256x16", k_contract_small<T, O, 256, 16, 4, 1, MODE>, grid, block, 0, s, a);
+    }
+  }
+  switch (cfg) {
+    case kTileL: return launch("contract_64x256", k_contract<T, O, 64, 256, 1, 4, MODE>, grid, block, 0, s, a);
+    case kTileM: return launch("contract_32x128", k_contract<T, O, 32, 128, 1, 4, MODE>, grid, block, 0, s, a);
+    case kTileS: return launch("contract_16x64", k_contract<T, O, 16, 64, 1, 4, MODE>, grid, block, 0, s, a);
+    default: return launch("contract_256x16", k_contract<T, O, 256, 16, 4, 1, MODE>, grid, block, 0, s, a);
+  }
+}
+
 template <typename T, typename O>
 static Status launch_contract_t(int cfg, const ContractArgs &a, hipStream_t s) {
-  const dim3 grid((unsigned)a.nblocks), block(256);
-  switch (cfg) {
-    case kTileL: return launch("contract_64x256", k_contract<T, O, 64, 256, 1, 4>, grid, block, 0, s, a);
-    case kTileM: return launch("contract_32x128", k_contract<T, O, 32, 128, 1, 4>, grid, block, 0, s, a);
-    case kTileS: return launch("contract_16x64", k_contract<T, O, 16, 64, 1, 4>, grid, block, 0, s, a);
-    default: return launch("contract_256x16", k_contract<T, O, 256, 16, 4, 1>, grid, block, 0, s, a);
-  }
+  if (a.mode == kModeFinalBlocked) return launch_contract_m<T, O, kModeFinalBlocked>(cfg, a, s);
+  if (a.mode == kModeFinalDeposit) return launch_contract_m<T, O, kModeFinalDeposit>(cfg, a, s);
+  return launch_contract_m<T, T, kModeIntermediate>(cfg, a, s);
 }
 
 Status launch_contract(Acc acc, bool out_double, int cfg, const ContractArgs &a, hipStream_t s) {
@@ -406,8 +587,12 @@ Status launch_contract(Acc acc, bool out_double, int cfg, const ContractArgs &a,
                     : launch_contract_t<double, float>(cfg, a, s);
 }
 
-Status launch_row_flags(const FlagArgs &a, int64_t total_rows, hipStream_t s) {
-  return launch("row_flags", k_row_flags, dim3((unsigned)total_rows), dim3(256), 0, s, a);
+Status launch_mass_final(const double *partials, int64_t count, double *mass, hipStream_t s) {
+  return launch("mass_final", k_mass_final, dim3(1), dim3(256), 0, s, partials, count, mass);
+}
+
+Status launch_row_flags(const FlagArgs &a, int64_t total_blocks, hipStream_t s) {
+  return launch("row_flags", k_row_flags, dim3((unsigned)total_blocks), dim3(256), 0, s, a);
 }
 
 Status launch_convert(const void *src, bool src_double, void *dst, bool dst_double,

@@ -7,10 +7,21 @@
 
 namespace cqc {
 
+// Row-index map of one operand, packed into scalars so the kernel never indexes
+// a kernel-argument array with a runtime index (that turns into dependent
+// vector loads from the argument segment).  Digit i (most significant first)
+// takes source (srcmask >> i) & 1 (0: shared index s, 1: rest index r) and
+// shift (shifts[i / 10] >> 6 (i % 10)) & 63.
 struct DigitMapDev {
-  int8_t n;
-  int8_t src[CQC_MAX_K_SUB + 4];
-  int8_t shift[CQC_MAX_K_SUB + 4];
+  int32_t n;
+  uint32_t srcmask;
+  uint64_t shifts[2];
+};
+
+// Output-bit positions of the column bits of an operand (bit j counted from
+// the least significant), 6 bits each, 10 per word.
+struct BitPos {
+  uint64_t w[5];
 };
 
 // One pairwise contraction step (see plan.hpp), executed as a batched GEMM
@@ -24,37 +35,42 @@ enum ContractMode : int32_t {
 struct ContractArgs {
   const void *X;
   const void *Y;
-  const int32_t *flagX;
+  const int32_t *flagX;   // [rows][nchX] chunk flags
   const int32_t *flagY;
+  int32_t nchX, nchY;
   int32_t *flagZ;
   void *Z;
   int32_t logM, logN;
   int32_t nS, nRX, nRY;
   int32_t tilesM, tilesN;
   int32_t mode;
+  int32_t xcd_remap;  // 1: keep consecutive logical tiles on one XCD
   int64_t nblocks;
   double scale;
   DigitMapDev mx, my;
-  int8_t posX[48];   // column bit j (from the least significant) of X -> output bit position
-  int8_t posY[48];
-  double *partials;  // per-block FP64 sum of written outputs (final mode) or null
-  uint32_t *counter; // last-block counter, zeroed by the row-flag kernel
-  double *mass;      // FP64 total (final mode) or null
+  BitPos posX, posY;  // deposit mode: column bit -> output bit position
+  double *partials;  // [nblocks] per-block FP64 sums of the written outputs, or null
 };
+
+// Row flags are kept per (row, chunk of kFlagChunk columns): flag[r * nch + c]
+// says whether chunk c of row r has a non-zero element; a row is live if any
+// of its chunk flags is set.  Splitting rows lets the flag pass run with many
+// small blocks instead of one block per long row.
+constexpr int kFlagChunk = 2048;
+__host__ __device__ inline int64_t flag_chunks(int64_t cols) { return (cols + kFlagChunk - 1) / kFlagChunk; }
 
 struct FlagDesc {
   const void *ptr;
   int64_t rows;
   int64_t cols;
-  int32_t *flags;
-  int64_t row_start;
+  int32_t *flags;      // [rows][flag_chunks(cols)]
+  int64_t block_start; // first block of this tensor
 };
 
 struct FlagArgs {
   FlagDesc d[CQC_MAX_SUB + 1];
   int32_t n;
   int32_t is_double;
-  uint32_t *counter;    // zeroed (may be null)
   void *unit;           // if non-null: one Acc-typed 1.0 written here, unit_flag = 1
   int32_t *unit_flag;
 };
@@ -67,7 +83,8 @@ struct TileShape { int bm, bn; };
 TileShape tile_shape(int cfg);
 int choose_tile(int logM, int logN);
 
-Status launch_row_flags(const FlagArgs &a, int64_t total_rows, hipStream_t s);
+Status launch_row_flags(const FlagArgs &a, int64_t total_blocks, hipStream_t s);
+Status launch_mass_final(const double *partials, int64_t count, double *mass, hipStream_t s);
 Status launch_contract(Acc acc, bool out_double, int cfg, const ContractArgs &a, hipStream_t s);
 Status launch_convert(const void *src, bool src_double, void *dst, bool dst_double,
                       int64_t count, hipStream_t s);
