@@ -4,14 +4,6 @@
 
 extern "C" {
 
-int cqc_dd_workspace_size(const cqc_instance *, cqc_dtype, cqc_precision, const cqc_dd_params *,
-                          size_t *) {
-  return cqc::Status::fail(CQC_ERR_UNSUPPORTED, "dynamic definition not available").code;
-}
-int cqc_reconstruct_dd(const cqc_instance *, cqc_dtype, cqc_precision, const cqc_dd_params *,
-                       double *, cqc_dd_record *, int32_t *, void *, size_t, hipStream_t) {
-  return cqc::Status::fail(CQC_ERR_UNSUPPORTED, "dynamic definition not available").code;
-}
 int cqc_backward_workspace_size(const cqc_instance *, int32_t, cqc_dtype, cqc_precision, size_t *) {
   return cqc::Status::fail(CQC_ERR_UNSUPPORTED, "backward not available").code;
 }

@@ -1,0 +1,153 @@
+"""GPU parity of dynamic definition (Algorithm 1) against the FP64 oracle.
+
+Bins: relative L1 <= 1e-12 (FP64 form) or <= 1e-6 (FP32 form) per recursion,
+plus the element-wise rounding bound.  Where two bin masses tie within the
+FP32 error, either choice is correct (reading of the bin rule), so the oracle
+follows the GPU's choice of parent and the choice itself is checked to be the
+heaviest unexpanded bin of the GPU's own masses.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import dd, fd, metrics
+from tests.gpu_util import to_dev, oracle_inputs, U32, U64
+
+pytestmark = pytest.mark.gpu
+cqc = pytest.importorskip("paper_2012_02333_amd")
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _run(entries_np, wcut, a, R, prec, dtype, first=None):
+    host, dev = to_dev(entries_np, dtype)
+    cut = cqc.CutMap.from_workload(wcut)
+    bins, recs = cqc.reconstruct_dd(dev, cut, a, R, first_active=first, precision=prec)
+    torch.cuda.synchronize()
+    return host, bins.cpu().numpy(), recs
+
+
+def _follow(gpu_recs):
+    def chooser(records, expanded):
+        r = len(records)
+        if r >= len(gpu_recs):
+            return None
+        return tuple(gpu_recs[r]["parent"])
+    return chooser
+
+
+def _check_heaviest(bins, recs):
+    """Each parent is the heaviest unexpanded bin (GPU masses), ties to lowest (rec, bin)."""
+    expanded = set()
+    for r in range(1, len(recs)):
+        best, best_key = None, None
+        for k in range(r):
+            if all(v != -1 for v in recs[k]["role"]):
+                continue                                  # no merged qubit
+            nb = 2 ** recs[k]["n_active"]
+            for i in range(nb):
+                if (k, i) in expanded:
+                    continue
+                key = (-bins[k, i], k, i)
+                if best_key is None or key < best_key:
+                    best, best_key = (k, i), key
+        assert tuple(recs[r]["parent"]) == best, (r, recs[r]["parent"], best)
+        expanded.add(best)
+
+
+@pytest.mark.parametrize("prec,dtype,tol", [("fp64", torch.float64, 1e-12), ("fp32", torch.float32, 1e-6)])
+@pytest.mark.parametrize("shape,a,R", [(((4, 3), (1,), 4), 3, 4), (((3, 2, 3), (2, 2), 6), 4, 6),
+                                       (((4, 4, 4), (1, 2), 4), 5, 5), (((3, 3), (2,), 4), 2, 12)])
+def test_dd_matches_oracle(shape, a, R, prec, dtype, tol):
+    _gpu()
+    own, bridges, layers = shape
+    inst = W.make_instance(own, bridges, layers, seed=42)
+    host, bins, recs = _run(inst.entries, inst.cut, a, R, prec, dtype)
+    e64 = oracle_inputs(host)
+    ref = dd.reconstruct(e64, inst.cut, a, R, chooser=_follow(recs))
+    assert len(ref) == len(recs)
+    _check_heaviest(bins, recs)
+    for r, (g, o) in enumerate(zip(recs, ref)):
+        assert g["role"] == o["role"], r
+        nb = 2 ** g["n_active"]
+        got = bins[r, :nb]
+        err = metrics.rel_l1(got, o["bins"])
+        assert err <= tol, (r, err)
+        assert abs(g["mass"] - o["bins"].sum()) <= tol * np.abs(o["bins"]).sum() + 1e-15
+        if r > 0:
+            pr, pb = g["parent"]
+            assert abs(got.sum() - bins[pr, pb]) <= 10 * tol * max(1e-300, abs(bins[pr, pb])) + 1e-14
+
+
+@pytest.mark.parametrize("prec,dtype", [("fp64", torch.float64), ("fp32", torch.float32)])
+def test_dd_locates_deterministic_state(prec, dtype):
+    _gpu()
+    target = [1, 0, 1, 1, 0, 1, 1]
+    circ = W.bridged_chain((3, 2), (2,), 4, seed=0, x_gates=tuple((0, q) for q, b in enumerate(target) if b))
+    circ.angles[:] = 0.0
+    cut = circ.cut_map()
+    host, bins, recs = _run(W.circuit_entries(circ), cut, 1, cut.n, prec, dtype)
+    assert len(recs) == cut.n
+    for r, rec in enumerate(recs):
+        assert rec["active"] == [r]
+        assert np.allclose(bins[r, :2], [1 - target[r], target[r]], atol=1e-6)
+    assert abs(recs[0]["mass"] - 1.0) < 1e-6
+
+
+def test_dd_first_active_and_refill():
+    """Explicit first active set; many recursions so that the candidate list of
+    the first recursion is consumed and refilled."""
+    _gpu()
+    inst = W.make_instance((4, 4), (2,), 4, seed=7)
+    first = [9, 2, 5, 0]
+    host, bins, recs = _run(inst.entries, inst.cut, 4, 20, "fp64", torch.float64, first=first)
+    assert recs[0]["active"] == sorted(first)
+    assert sum(1 for r in recs if r["parent"][0] == 0) > 8      # first list consumed, refilled
+    ref = dd.reconstruct(oracle_inputs(host), inst.cut, 4, 20, first_active=first)
+    assert [tuple(r["parent"]) for r in recs] == [r["parent"] for r in ref]
+    for r, o in enumerate(ref):
+        assert np.max(np.abs(bins[r, :len(o["bins"])] - o["bins"])) < 1e-14
+
+
+def test_dd_c4_n40():
+    """n=40, K=8, four 12-qubit subcircuits, 2^20 active bins, 5 recursions (FP32
+    term sum, FP64 bins): sampled bins against the oracle's per-bin definition,
+    recursion-1 total mass 1, refinements conserve their parent's mass."""
+    _gpu()
+    inst = W.config_instance("c4")
+    a, R = W.DD_C4["n_active"], W.DD_C4["n_recursions"]
+    host, bins, recs = _run(inst.entries, inst.cut, a, R, "fp32", torch.float32)
+    assert len(recs) == R
+    _check_heaviest(bins, recs)
+    e64 = oracle_inputs(host)
+    assert abs(recs[0]["mass"] - 1.0) < 1e-5
+    for r, g in enumerate(recs):
+        role = g["role"]
+        merged = dd.merge_entries(e64, inst.cut, role)
+        nb = 2 ** g["n_active"]
+        betas = np.unique(np.concatenate([W.sample_outputs(g["n_active"], 48, seed=r), [int(np.argmax(bins[r, :nb]))]]))
+        ref = dd.bins_from_merged(merged, inst.cut, role, betas)
+        got = bins[r, betas]
+        T = dd.bins_from_merged([np.abs(m) for m in merged], inst.cut, role, betas)
+        assert np.all(np.abs(got - ref) <= 4 * (256 + 2) * U32 * T + 1e-300), r
+        assert metrics.rel_l1(got, ref) <= 1e-6
+        if r > 0:
+            pr, pb = g["parent"]
+            assert abs(bins[r, :nb].sum() - bins[pr, pb]) <= 1e-5 * abs(bins[pr, pb])
+
+
+def test_dd_bad_arguments():
+    _gpu()
+    inst = W.make_instance((3, 3), (1,), 4, seed=1)
+    host, dev = to_dev(inst.entries, torch.float32)
+    cut = cqc.CutMap.from_workload(inst.cut)
+    with pytest.raises(cqc.CqcError) as e:
+        cqc.reconstruct_dd(dev, cut, 0, 2)
+    assert e.value.code == 1
+    with pytest.raises(cqc.CqcError) as e:
+        cqc.reconstruct_dd(dev, cut, 2, 2, first_active=[1, 1])
+    assert e.value.code == 1
