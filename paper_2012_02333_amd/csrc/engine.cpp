@@ -69,7 +69,7 @@ BitPos pack_pos(const std::vector<int> &pos) {
 
 Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &entries,
                void *out, bool out_double, double *mass, bool compute_entry_flags,
-               hipStream_t s) {
+               hipStream_t s, bool skip_final) {
   const Plan &p = L.plan;
   const size_t nt = p.tensors.size();
   std::vector<const void *> tptr(nt, nullptr);
@@ -105,6 +105,7 @@ Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &en
   for (size_t i = 0; i < p.steps.size(); ++i) {
     const Step &st = p.steps[i];
     const bool last = i + 1 == p.steps.size();
+    if (last && skip_final) break;
     ContractArgs a;
     std::memset(&a, 0, sizeof(a));
     a.X = tptr[st.x];

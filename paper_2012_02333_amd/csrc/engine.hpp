@@ -26,9 +26,10 @@ NetLayout layout_net(const Plan &plan, Acc acc, size_t base);
 // Enqueue the plan.  `entries[c]` are Acc-typed device tensors, flags of the
 // entry tensors must already be computed into their f_off slots unless
 // compute_entry_flags is set.
+// skip_final: run every step but the last (the intermediates the adjoint needs).
 Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &entries,
                void *out, bool out_double, double *mass, bool compute_entry_flags,
-               hipStream_t s);
+               hipStream_t s, bool skip_final = false);
 
 DigitMapDev to_dev(const DigitMap &m);
 BitPos pack_pos(const std::vector<int> &pos);

@@ -1,0 +1,301 @@
+// Adjoint kernels of one contraction step
+//     Z[(rX,rY)][m][n] = sum_s X[rowX(s,rX)][m] * Y[rowY(s,rY)][n]
+// given dZ = dL/dZ (row-major per batch):
+//     dX[rowX(s,rX)][m] = sum_{rY} sum_n dZ[(rX,rY)][m][n] * Y[rowY(s,rY)][n]    (k_bwd_x)
+//     dY[rowY(s,rY)][n] = sum_{rX} sum_m X[rowX(s,rX)][m] * dZ[(rX,rY)][m][n]    (k_bwd_y)
+// Both are GEMMs with a long inner dimension (output columns of the other
+// operand, and its rest labels), run split-K: every block owns one chunk of
+// the inner dimension and writes its partial sums; k_bwd_reduce then adds the
+// partials in chunk order (fixed, so results are bitwise reproducible) and
+// applies the scale.  Matrix-core row i <-> label s, column j <-> the output
+// column, k <-> the inner index; each lane takes 4 consecutive inner indices
+// with one 16-byte load and feeds them to 4 MFMAs (inner index 4*(lane/16)+t
+// in MFMA t, the same for both operands).
+#include "bwd.hpp"
+
+namespace cqc {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct BOp;
+template <> struct BOp<float> {
+  using V = f32x4;
+  static constexpr bool kConsecutive = true;  // register r <-> row 4*(l/16)+r
+  static __device__ __forceinline__ V run(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct BOp<double> {
+  using V = f64x4;
+  static constexpr bool kConsecutive = false;  // register r <-> row (l/16)+4r
+  static __device__ __forceinline__ V run(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+__device__ __forceinline__ int brow_of(const DigitMapDev &m, int s, int r) {
+  int row = 0;
+#pragma unroll 1
+  for (int i = 0; i < m.n; ++i) {
+    const int v = ((m.srcmask >> i) & 1u) ? r : s;
+    const uint64_t w = i < 10 ? m.shifts[0] : m.shifts[1];
+    const int sh = (int)((w >> (6 * (i < 10 ? i : i - 10))) & 63);
+    row = (row << 2) | ((v >> sh) & 3);
+  }
+  return row;
+}
+
+template <typename T>
+__device__ __forceinline__ void load4m(const T *p, int64_t c, int64_t lim, T *v) {
+  // v[t] = p[c + t] for c + t < lim, else 0 (c is a multiple of 4)
+  if (c + 3 < lim) {
+    if (sizeof(T) == 4) {
+      const float4 q = *reinterpret_cast<const float4 *>(p + c);
+      v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
+      const double2 a = *reinterpret_cast<const double2 *>(p + c);
+      const double2 b = *reinterpret_cast<const double2 *>(p + c + 2);
+      v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) v[t] = c + t < lim ? p[c + t] : (T)0;
+  }
+}
+
+// grid: x = (((p * RXn + rX) * sSuper + ss) * mTiles + mt), p = (rY, k-chunk)
+template <typename T, int SB, int MB>
+__global__ __launch_bounds__(256) void k_bwd_x(const BwdArgs a) {
+  using Op = BOp<T>;
+  using V = typename Op::V;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, lg = lane >> 4;
+  const int64_t M = int64_t(1) << a.logM, N = int64_t(1) << a.logN;
+  const int RYn = 1 << (2 * a.nRY), RXn = 1 << (2 * a.nRX), SN = 1 << (2 * a.nS);
+  const int sSuper = (SN + 16 * SB - 1) / (16 * SB);
+  const int64_t mTiles = (M + 64 * MB - 1) / (64 * MB);
+  int64_t b = blockIdx.x;
+  const int64_t mt = b % mTiles; b /= mTiles;
+  const int ss = (int)(b % sSuper); b /= sSuper;
+  const int rX = (int)(b % RXn); b /= RXn;
+  const int64_t p = b;                       // partial index = rY * kChunks + kc
+  const int rY = (int)(p / a.kChunks), kc = (int)(p % a.kChunks);
+  const int64_t k0 = (int64_t)kc * a.kChunk;
+  const int64_t k1 = N < k0 + a.kChunk ? N : k0 + a.kChunk;
+  const int64_t mw = mt * 64 * MB + wave * 16 * MB;
+  const T *X = static_cast<const T *>(a.X);  (void)X;
+  const T *Y = static_cast<const T *>(a.Y);
+  const T *dZ = static_cast<const T *>(a.dZ) + ((int64_t)rX * RYn + rY) * M * N;
+  int yrow[SB];
+  bool sok[SB];
+#pragma unroll
+  for (int sb = 0; sb < SB; ++sb) {
+    const int s = (ss * SB + sb) * 16 + l16;
+    sok[sb] = s < SN;
+    yrow[sb] = sok[sb] ? brow_of(a.my, s, rY) : 0;
+  }
+  V acc[SB][MB];
+#pragma unroll
+  for (int i = 0; i < SB; ++i)
+#pragma unroll
+    for (int j = 0; j < MB; ++j) acc[i][j] = V{0, 0, 0, 0};
+  for (int64_t n0 = k0; n0 < k1; n0 += 16) {
+    const int64_t c = n0 + 4 * lg;
+    T av[SB][4], bv[MB][4];
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) {
+      if (sok[sb]) load4m<T>(Y + (int64_t)yrow[sb] * N, c, k1, av[sb]);
+      else
+        for (int t = 0; t < 4; ++t) av[sb][t] = 0;
+    }
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const int64_t m = mw + mb * 16 + l16;
+      if (m < M) load4m<T>(dZ + m * N, c, k1, bv[mb]);
+      else
+        for (int t = 0; t < 4; ++t) bv[mb][t] = 0;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) acc[sb][mb] = Op::run(av[sb][t], bv[mb][t], acc[sb][mb]);
+  }
+  T *part = static_cast<T *>(a.part) + p * a.rowsX * M;
+#pragma unroll
+  for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const int64_t m = mw + mb * 16 + l16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int s = (ss * SB + sb) * 16 + (Op::kConsecutive ? 4 * lg + r : lg + 4 * r);
+        if (s < SN && m < M) part[(int64_t)brow_of(a.mx, s, rX) * M + m] = acc[sb][mb][r];
+      }
+    }
+}
+
+// grid: x = (((p * RYn + rY) * sSuper + ss) * nTiles + nt), p = (rX, k-chunk over m)
+template <typename T, int SB, int NB>
+__global__ __launch_bounds__(256) void k_bwd_y(const BwdArgs a) {
+  using Op = BOp<T>;
+  using V = typename Op::V;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, lg = lane >> 4;
+  const int64_t M = int64_t(1) << a.logM, N = int64_t(1) << a.logN;
+  const int RYn = 1 << (2 * a.nRY), SN = 1 << (2 * a.nS);
+  const int sSuper = (SN + 16 * SB - 1) / (16 * SB);
+  const int64_t nTiles = (N + 64 * NB - 1) / (64 * NB);
+  int64_t b = blockIdx.x;
+  const int64_t nt = b % nTiles; b /= nTiles;
+  const int ss = (int)(b % sSuper); b /= sSuper;
+  const int rY = (int)(b % RYn); b /= RYn;
+  const int64_t p = b;                       // partial index = rX * kChunks + kc
+  const int rX = (int)(p / a.kChunks), kc = (int)(p % a.kChunks);
+  const int64_t k0 = (int64_t)kc * a.kChunk;
+  const int64_t k1 = M < k0 + a.kChunk ? M : k0 + a.kChunk;
+  const int64_t nw = nt * 64 * NB + wave * 16 * NB;
+  const T *X = static_cast<const T *>(a.X);
+  const T *dZ = static_cast<const T *>(a.dZ) + ((int64_t)rX * RYn + rY) * M * N;
+  int xrow[SB];
+  bool sok[SB];
+#pragma unroll
+  for (int sb = 0; sb < SB; ++sb) {
+    const int s = (ss * SB + sb) * 16 + l16;
+    sok[sb] = s < SN;
+    xrow[sb] = sok[sb] ? brow_of(a.mx, s, rX) : 0;
+  }
+  V acc[SB][NB];
+#pragma unroll
+  for (int i = 0; i < SB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[i][j] = V{0, 0, 0, 0};
+  for (int64_t m0 = k0; m0 < k1; m0 += 16) {
+    const int64_t c = m0 + 4 * lg;
+    T av[SB][4], bv[NB][4];
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) {
+      if (sok[sb]) load4m<T>(X + (int64_t)xrow[sb] * M, c, k1, av[sb]);
+      else
+        for (int t = 0; t < 4; ++t) av[sb][t] = 0;
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int64_t n = nw + nb * 16 + l16;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) bv[nb][t] = (n < N && c + t < k1) ? dZ[(c + t) * N + n] : (T)0;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[sb][nb] = Op::run(av[sb][t], bv[nb][t], acc[sb][nb]);
+  }
+  T *part = static_cast<T *>(a.part) + p * a.rowsY * N;
+#pragma unroll
+  for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int64_t n = nw + nb * 16 + l16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int s = (ss * SB + sb) * 16 + (Op::kConsecutive ? 4 * lg + r : lg + 4 * r);
+        if (s < SN && n < N) part[(int64_t)brow_of(a.my, s, rY) * N + n] = acc[sb][nb][r];
+      }
+    }
+}
+
+// out[i] = scale * sum_{p < P} part[p][i], partials added in ascending p.
+template <typename T, typename O>
+__global__ __launch_bounds__(256) void k_bwd_reduce(const T *part, int64_t count, int64_t P,
+                                                    double scale, O *out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    T s = 0;
+    for (int64_t p = 0; p < P; ++p) s += part[p * count + i];
+    out[i] = (O)(s * (T)scale);
+  }
+}
+
+// Gather a globally ordered vector into blocked [m][n] order:
+// dst[m * N + n] = src[rowoff(m) + coloff(n)].
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_blocked(const T *src, T *dst, int logM, int logN,
+                                                        BitPos px, BitPos py) {
+  const int64_t total = int64_t(1) << (logM + logN);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t m = i >> logN, n = i & ((int64_t(1) << logN) - 1);
+    int64_t addr = 0;
+    for (int j = 0; j < logM; ++j) {
+      const uint64_t w = px.w[j / 10];
+      addr |= ((m >> j) & 1) << ((w >> (6 * (j % 10))) & 63);
+    }
+    for (int j = 0; j < logN; ++j) {
+      const uint64_t w = py.w[j / 10];
+      addr |= ((n >> j) & 1) << ((w >> (6 * (j % 10))) & 63);
+    }
+    dst[i] = src[addr];
+  }
+}
+
+static int sb_for(int nS) { return nS <= 2 ? 1 : (nS == 3 ? 4 : 16); }
+
+template <typename T>
+static Status launch_bwd_t(const BwdArgs &a, bool which_y, hipStream_t s) {
+  const int SN = 1 << (2 * a.nS);
+  const int SB = sb_for(a.nS);
+  const int sSuper = (SN + 16 * SB - 1) / (16 * SB);
+  const int64_t M = int64_t(1) << a.logM, N = int64_t(1) << a.logN;
+  const int RXn = 1 << (2 * a.nRX), RYn = 1 << (2 * a.nRY);
+  if (!which_y) {
+    const int MB = SB == 16 ? 1 : 4;
+    const int64_t tiles = (M + 64 * MB - 1) / (64 * MB);
+    const int64_t P = (int64_t)RYn * a.kChunks;
+    const dim3 g((unsigned)(P * RXn * sSuper * tiles)), b(256);
+    if (SB == 1) return launch("bwd_x", k_bwd_x<T, 1, 4>, g, b, 0, s, a);
+    if (SB == 4) return launch("bwd_x", k_bwd_x<T, 4, 4>, g, b, 0, s, a);
+    return launch("bwd_x", k_bwd_x<T, 16, 1>, g, b, 0, s, a);
+  }
+  const int NB = SB == 16 ? 1 : 4;
+  const int64_t tiles = (N + 64 * NB - 1) / (64 * NB);
+  const int64_t P = (int64_t)RXn * a.kChunks;
+  const dim3 g((unsigned)(P * RYn * sSuper * tiles)), b(256);
+  if (SB == 1) return launch("bwd_y", k_bwd_y<T, 1, 4>, g, b, 0, s, a);
+  if (SB == 4) return launch("bwd_y", k_bwd_y<T, 4, 4>, g, b, 0, s, a);
+  return launch("bwd_y", k_bwd_y<T, 16, 1>, g, b, 0, s, a);
+}
+
+Status launch_bwd(Acc acc, const BwdArgs &a, bool which_y, hipStream_t s) {
+  return acc == Acc::F32 ? launch_bwd_t<float>(a, which_y, s) : launch_bwd_t<double>(a, which_y, s);
+}
+
+Status launch_bwd_reduce(Acc acc, const void *part, int64_t count, int64_t P, double scale,
+                         void *out, bool out_double, hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>((count + 255) / 256, 8192);
+  const dim3 g((unsigned)std::max<int64_t>(blocks, 1)), b(256);
+  if (acc == Acc::F32) {
+    const float *pp = static_cast<const float *>(part);
+    return out_double ? launch("bwd_reduce", k_bwd_reduce<float, double>, g, b, 0, s, pp, count, P, scale, static_cast<double *>(out))
+                      : launch("bwd_reduce", k_bwd_reduce<float, float>, g, b, 0, s, pp, count, P, scale, static_cast<float *>(out));
+  }
+  const double *pp = static_cast<const double *>(part);
+  return out_double ? launch("bwd_reduce", k_bwd_reduce<double, double>, g, b, 0, s, pp, count, P, scale, static_cast<double *>(out))
+                    : launch("bwd_reduce", k_bwd_reduce<double, float>, g, b, 0, s, pp, count, P, scale, static_cast<float *>(out));
+}
+
+Status launch_gather_blocked(Acc acc, const void *src, void *dst, int logM, int logN,
+                             const BitPos &px, const BitPos &py, hipStream_t s) {
+  const int64_t total = int64_t(1) << (logM + logN);
+  const dim3 g((unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 16384))), b(256);
+  if (acc == Acc::F32)
+    return launch("gather_blocked", k_gather_blocked<float>, g, b, 0, s, static_cast<const float *>(src),
+                  static_cast<float *>(dst), logM, logN, px, py);
+  return launch("gather_blocked", k_gather_blocked<double>, g, b, 0, s, static_cast<const double *>(src),
+                static_cast<double *>(dst), logM, logN, px, py);
+}
+
+}  // namespace cqc

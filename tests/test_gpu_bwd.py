@@ -1,0 +1,187 @@
+"""GPU parity of the adjoint (gradients w.r.t. every entry tensor).
+
+Bar: relative L2 per entry tensor <= 1e-5 for the FP32 form, <= 1e-12 for the
+FP64 form, against the oracle's plain-definition vector-Jacobian product fed
+the same dL/dp; plus FP64 central finite differences of a cross-entropy loss
+through the GPU forward, and bitwise repeatability.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import adjoint, fd, metrics
+from tests.gpu_util import to_dev, oracle_inputs
+
+pytestmark = pytest.mark.gpu
+cqc = pytest.importorskip("paper_2012_02333_amd")
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _vjp_gpu(entries_np, wcut, G, dtype, prec):
+    host, dev = to_dev(entries_np, dtype)
+    cut = cqc.CutMap.from_workload(wcut)
+    g = torch.from_numpy(np.asarray(G, dtype=np.float64)).to(device="cuda", dtype=dtype)
+    grads = cqc.reconstruct_backward(dev, cut, g, precision=prec)
+    torch.cuda.synchronize()
+    return host, g.double().cpu().numpy(), [x.double().cpu().numpy() for x in grads]
+
+
+@pytest.mark.parametrize("prec,dtype,tol", [("fp64", torch.float64, 1e-12), ("fp32", torch.float32, 1e-5)])
+@pytest.mark.parametrize("shape", [((4, 3), (1,), 4), ((5, 5), (2,), 6), ((3, 2, 3), (3, 3), 4),
+                                   ((2, 3, 3, 2), (1, 2, 2), 4), ((6, 6), (3,), 6)])
+def test_vjp_simulated(shape, prec, dtype, tol):
+    _gpu()
+    own, bridges, layers = shape
+    inst = W.make_instance(own, bridges, layers, seed=77)
+    G = np.random.default_rng(5).standard_normal(2 ** inst.n)
+    host, Gd, grads = _vjp_gpu(inst.entries, inst.cut, G, dtype, prec)
+    ref = adjoint.vjp(oracle_inputs(host), inst.cut, Gd)
+    for c, (g, r) in enumerate(zip(grads, ref)):
+        err = metrics.rel_l2(g, r)
+        assert err <= tol, (c, err)
+
+
+@pytest.mark.parametrize("prec,dtype,tol", [("fp64", torch.float64, 1e-12), ("fp32", torch.float32, 1e-5)])
+@pytest.mark.parametrize("case", ["perm", "kron3", "single", "triangle", "ragged", "zero_rows"])
+def test_vjp_structures(case, prec, dtype, tol):
+    _gpu()
+    C = W.CutMap
+    if case == "perm":
+        cut = C(9, [4, 5], [0, 0], [1, 1], [5, 0, 3, 8, 1, 2, 4, 7, 6])
+    elif case == "kron3":
+        cut = C(9, [2, 3, 4], [0], [1], list(range(9)))
+    elif case == "single":
+        cut = C(6, [6], [], [], [3, 1, 0, 5, 2, 4])
+    elif case == "triangle":
+        cut = C(12, [4, 4, 4], [0, 1, 2, 0], [1, 2, 0, 1], list(range(12)))
+    elif case == "ragged":
+        cut = C(11, [1, 2, 8], [0, 1, 1, 2], [1, 2, 2, 0], list(range(11)))
+    else:
+        cut = C(10, [5, 5], [0, 0, 0], [1, 1, 1], list(range(10)))
+    zr = ((0, 3), (1, 40)) if case == "zero_rows" else ()
+    ents = W.random_entries(cut, seed=200 + len(case), zero_rows=zr)
+    G = np.random.default_rng(6).standard_normal(2 ** cut.n)
+    host, Gd, grads = _vjp_gpu(ents, cut, G, dtype, prec)
+    ref = adjoint.vjp(oracle_inputs(host), cut, Gd)
+    for c, (g, r) in enumerate(zip(grads, ref)):
+        assert metrics.rel_l2(g, r) <= tol, (case, c, metrics.rel_l2(g, r))
+    if case == "zero_rows":          # a zero row still has a non-zero gradient
+        assert np.abs(grads[0][3]).max() > 0
+
+
+def test_vjp_c2_full():
+    """n=24, K=2: both gradients (16 x 2^11 and 16 x 2^13) from a full 2^24 dL/dp."""
+    _gpu()
+    inst = W.config_instance("c2")
+    G = np.random.default_rng(9).standard_normal(2 ** inst.n)
+    host, Gd, grads = _vjp_gpu(inst.entries, inst.cut, G, torch.float32, "fp32")
+    e64 = oracle_inputs(host)
+    # n_C = 2: the definition reduces to two matrix products (checked against
+    # the plain definition in the oracle's own tests)
+    A, B = e64
+    Gm = Gd.reshape(2 ** 11, 2 ** 13)
+    refA, refB = 0.25 * (B @ Gm.T), 0.25 * (A @ Gm)
+    assert metrics.rel_l2(grads[0], refA) <= 1e-5
+    assert metrics.rel_l2(grads[1], refB) <= 1e-5
+
+
+def test_autograd_cross_entropy_matches_oracle():
+    _gpu()
+    inst = W.make_instance((4, 3, 4), (2, 1), 4, seed=12)
+    host, dev = to_dev(inst.entries, torch.float32)
+    cut = cqc.CutMap.from_workload(inst.cut)
+    t = W.dirichlet_target(inst.n, seed=1000)
+    ents = [e.clone().requires_grad_(True) for e in dev]
+    p = cqc.ReconstructFD.apply(cut, "fp32", *ents)
+    tt = torch.from_numpy(t).cuda()
+    loss = -(tt * torch.log(torch.clamp(p.double(), min=1e-30))).sum()
+    loss.backward()
+    e64 = oracle_inputs(host)
+    p_ref = fd.reconstruct(e64, inst.cut)
+    # same dL/dp on both sides (the GPU's p), so only the adjoint is compared
+    Gd = adjoint.cross_entropy_grad(p.detach().double().cpu().numpy(), t)
+    ref = adjoint.vjp(e64, inst.cut, Gd.astype(np.float32).astype(np.float64))
+    for c in range(len(ents)):
+        assert metrics.rel_l2(ents[c].grad.double().cpu().numpy(), ref[c]) <= 1e-5
+    # end to end (dL/dp = -t/p from the FP64 oracle's p instead of the FP32 p):
+    # -t/p amplifies the FP32 rounding of tiny p, so this is reported, with only
+    # a sanity bound
+    ref_e2e = adjoint.vjp(e64, inst.cut, adjoint.cross_entropy_grad(p_ref, t))
+    e2e = max(metrics.rel_l2(ents[c].grad.double().cpu().numpy(), ref_e2e[c]) for c in range(len(ents)))
+    print(f"end-to-end gradient rel L2 = {e2e:.2e}")
+    assert e2e <= 1e-1
+
+
+def test_fp64_finite_differences_through_gpu():
+    _gpu()
+    inst = W.make_instance((3, 3), (2,), 4, seed=3)
+    cut = cqc.CutMap.from_workload(inst.cut)
+    t = W.dirichlet_target(inst.n, seed=1001)
+    tt = torch.from_numpy(t).cuda()
+    ents = [torch.from_numpy(E).cuda() for E in inst.entries]
+
+    def loss_of(es):
+        p, _ = cqc.reconstruct_fd(es, cut, precision="fp64", with_mass=False)
+        return float(-(tt * torch.log(torch.clamp(p, min=1e-30))).sum())
+
+    p, _ = cqc.reconstruct_fd(ents, cut, precision="fp64", with_mass=False)
+    G = -(tt / p)
+    grads = cqc.reconstruct_backward(ents, cut, G.contiguous(), precision="fp64")
+    rng = np.random.default_rng(2)
+    for c in range(len(ents)):
+        E = ents[c]
+        h = 1e-6 * float(E.abs().max())
+        for _ in range(4):
+            r, x = int(rng.integers(E.shape[0])), int(rng.integers(E.shape[1]))
+            ep = [e.clone() for e in ents]
+            em = [e.clone() for e in ents]
+            ep[c][r, x] += h
+            em[c][r, x] -= h
+            num = (loss_of(ep) - loss_of(em)) / (2 * h)
+            # central differences carry an O(h^2) truncation error (cross-entropy
+            # curves sharply where p is small): the gradient bar is 1e-5
+            assert abs(num - float(grads[c][r, x])) <= 1e-5 * max(1.0, abs(num))
+
+
+def test_linear_loss_finite_differences_exact():
+    """p is linear in each E_c, so for L = <w, p> the central difference is
+    exact up to rounding: a tight FP64 check of the adjoint through the GPU."""
+    _gpu()
+    inst = W.make_instance((3, 2, 3), (2, 1), 4, seed=8)
+    cut = cqc.CutMap.from_workload(inst.cut)
+    w = torch.from_numpy(np.random.default_rng(3).standard_normal(2 ** inst.n)).cuda()
+    ents = [torch.from_numpy(E).cuda() for E in inst.entries]
+
+    def loss_of(es):
+        p, _ = cqc.reconstruct_fd(es, cut, precision="fp64", with_mass=False)
+        return float((w * p).sum())
+
+    grads = cqc.reconstruct_backward(ents, cut, w.contiguous(), precision="fp64")
+    rng = np.random.default_rng(4)
+    for c in range(len(ents)):
+        E = ents[c]
+        h = 0.25 * float(E.abs().max())
+        for _ in range(4):
+            r, x = int(rng.integers(E.shape[0])), int(rng.integers(E.shape[1]))
+            ep = [e.clone() for e in ents]
+            em = [e.clone() for e in ents]
+            ep[c][r, x] += h
+            em[c][r, x] -= h
+            num = (loss_of(ep) - loss_of(em)) / (2 * h)
+            assert abs(num - float(grads[c][r, x])) <= 1e-10 * max(1.0, abs(num))
+
+
+def test_backward_bitwise_repeatable():
+    _gpu()
+    inst = W.make_instance((5, 5), (2,), 6, seed=4)
+    host, dev = to_dev(inst.entries, torch.float32)
+    cut = cqc.CutMap.from_workload(inst.cut)
+    g = torch.randn(2 ** inst.n, device="cuda", dtype=torch.float32, generator=torch.Generator("cuda").manual_seed(0))
+    a = cqc.reconstruct_backward(dev, cut, g)
+    b = cqc.reconstruct_backward(dev, cut, g)
+    assert all(torch.equal(x, y) for x, y in zip(a, b))
