@@ -104,6 +104,30 @@ int cqc_reconstruct_fd(const cqc_instance *inst, int32_t n_inst, cqc_dtype in_t,
                        cqc_dtype out_t, cqc_precision prec, void *workspace,
                        size_t ws_bytes, hipStream_t stream);
 
+/* Prepared batches (the batched form of cqc_reconstruct_fd).  A batch of
+ * independent instances of uneven n and K is reconstructed by a fixed, small
+ * number of kernel launches: one row-flag pass over every entry tensor, one
+ * persistent launch per group of contraction steps of equal kernel shape (all
+ * instances' intermediate contractions first, then all final ones, each
+ * group drained from a cost-ordered work queue) and one pass for every FP64
+ * mass.
+ * cqc_batch_create validates and plans the batch, writes its descriptor tables
+ * into `workspace` (at least cqc_fd_workspace_size() bytes for the same
+ * instances, which must stay allocated and unmodified by the caller while the
+ * batch exists) and synchronises `stream` once.  Entry, output and mass
+ * pointers are bound at creation.  The output dtype must be the precision's
+ * (F32 for FP32, F64 for FP64).
+ * cqc_batch_run enqueues only kernel launches, with no host synchronisation
+ * and no allocation, so it may be captured into a HIP graph and replayed.
+ * Runs of one batch on different streams must not overlap.
+ * cqc_batch_destroy frees the host-side handle only. */
+typedef struct cqc_batch_s *cqc_batch;
+int cqc_batch_create(const cqc_instance *inst, int32_t n_inst, cqc_dtype in_t, cqc_dtype out_t,
+                     cqc_precision prec, void *workspace, size_t ws_bytes, hipStream_t stream,
+                     cqc_batch *out);
+int cqc_batch_run(cqc_batch batch, hipStream_t stream);
+int cqc_batch_destroy(cqc_batch batch);
+
 /* Dynamic definition (Algorithm 1, Section 4.3).
  * Recursion 1 makes `first_active` (or, if NULL, the first n_active qubits in
  * output order) active; every later recursion picks, among all bins produced

@@ -19,7 +19,7 @@ import torch
 from . import _lib
 from ._lib import CqcError, PREC
 
-__all__ = ["CutMap", "reconstruct_fd", "reconstruct_dd", "reconstruct_backward", "FDCall",
+__all__ = ["CutMap", "reconstruct_fd", "reconstruct_dd", "reconstruct_backward", "FDCall", "Batch",
            "ReconstructFD", "cost", "trace", "CqcError", "selftest_mfma", "library_path"]
 
 _DT = {torch.float32: _lib.F32, torch.float64: _lib.F64}
@@ -149,6 +149,36 @@ class FDCall:
         s = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
         _lib.check(self._fn(self._insts, self.n_inst, self._in_t, self._out_t, self.prec,
                             self.ws.data_ptr(), self.ws_bytes, s))
+
+
+class Batch(FDCall):
+    """A prepared batch of instances (cqc_batch_create): the descriptor tables
+    are uploaded once; run() enqueues a fixed handful of kernel launches and is
+    safe to capture into a CUDA/HIP graph.  Outputs and masses are bound at
+    construction."""
+
+    def __init__(self, entries_list, cuts, precision="fp32", outs=None, with_mass=True):
+        super().__init__(entries_list, cuts, precision, None, outs, with_mass)
+        if self.n_inst < 2:
+            raise ValueError("a batch needs at least two instances")
+        h = ctypes.c_void_p(0)
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        _lib.check(_lib.lib().cqc_batch_create(self._insts, self.n_inst, self._in_t, self._out_t, self.prec,
+                                               self.ws.data_ptr(), self.ws_bytes, s, ctypes.byref(h)))
+        self._h = h
+
+    def set_outputs(self, outs):
+        raise RuntimeError("outputs of a prepared batch are fixed; create a new Batch")
+
+    def run(self, stream=None):
+        s = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        _lib.check(_lib.lib().cqc_batch_run(self._h, s))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.lib().cqc_batch_destroy(h)
+            self._h = None
 
 
 def reconstruct_fd(entries, cut, precision="fp32", out_dtype=None, with_mass=True):

@@ -18,7 +18,7 @@ EXPORTS = [
     "cqc_fd_workspace_size", "cqc_reconstruct_fd", "cqc_dd_workspace_size", "cqc_reconstruct_dd",
     "cqc_backward_workspace_size", "cqc_reconstruct_backward", "cqc_cost", "cqc_autotune",
     "cqc_trace_enable", "cqc_trace_read", "cqc_status_string", "cqc_last_error_detail",
-    "cqc_version", "cqc_selftest_mfma",
+    "cqc_version", "cqc_selftest_mfma", "cqc_batch_create", "cqc_batch_run", "cqc_batch_destroy",
 ]
 
 
@@ -82,6 +82,10 @@ def lib():
     L.cqc_last_error_detail.restype = ctypes.c_char_p
     L.cqc_last_error_detail.argtypes = []
     L.cqc_selftest_mfma.argtypes = [vp, vp]
+    L.cqc_batch_create.argtypes = [P(CqcInstance), i32, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, sz, vp,
+                                   P(vp)]
+    L.cqc_batch_run.argtypes = [vp, vp]
+    L.cqc_batch_destroy.argtypes = [vp]
     for name in EXPORTS:
         f = getattr(L, name)
         if f.restype is None or f.restype is ctypes.c_int:

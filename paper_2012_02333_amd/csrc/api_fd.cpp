@@ -2,18 +2,12 @@
 #include <cmath>
 #include <cstring>
 
-#include "engine.hpp"
+#include "fdplan.hpp"
 
 namespace cqc {
 
-struct FdInstancePlan {
-  CutInfo cut;
-  NetLayout net;
-  std::vector<size_t> conv_off;  // per entry: converted copy (or SIZE_MAX)
-  size_t end = 0;
-};
 
-static Status precision_acc(cqc_precision prec, Acc *acc) {
+Status precision_acc(cqc_precision prec, Acc *acc) {
   switch (prec) {
     case CQC_PREC_FP64: *acc = Acc::F64; return Status::ok();
     case CQC_PREC_FP32: *acc = Acc::F32; return Status::ok();
@@ -23,12 +17,12 @@ static Status precision_acc(cqc_precision prec, Acc *acc) {
   }
 }
 
-static Status check_dtype(cqc_dtype t) {
+Status check_dtype(cqc_dtype t) {
   if (t != CQC_F32 && t != CQC_F64) return Status::fail(CQC_ERR_INVALID_ARG, "unknown dtype");
   return Status::ok();
 }
 
-static Status plan_fd_instance(const cqc_instance &in, cqc_dtype in_t, Acc acc, size_t base,
+Status plan_fd_instance(const cqc_instance &in, cqc_dtype in_t, Acc acc, size_t base,
                                bool need_ptrs, FdInstancePlan *out) {
   FdInstancePlan ip;
   CQC_TRY(validate_cut(&in.cut, CQC_MAX_FD_QUBITS, &ip.cut));
@@ -58,7 +52,7 @@ static Status plan_fd_instance(const cqc_instance &in, cqc_dtype in_t, Acc acc, 
   return Status::ok();
 }
 
-static Status fd_plans(const cqc_instance *inst, int32_t n_inst, cqc_dtype in_t, cqc_dtype out_t,
+Status fd_plans(const cqc_instance *inst, int32_t n_inst, cqc_dtype in_t, cqc_dtype out_t,
                        cqc_precision prec, bool need_ptrs, std::vector<FdInstancePlan> *plans,
                        Acc *acc_out) {
   if (!inst) return Status::fail(CQC_ERR_INVALID_ARG, "inst is NULL");
@@ -83,6 +77,9 @@ static Status fd_plans(const cqc_instance *inst, int32_t n_inst, cqc_dtype in_t,
   return Status::ok();
 }
 
+size_t batch_workspace_bytes(const cqc_instance *inst, int32_t n_inst, cqc_dtype in_t, cqc_dtype out_t,
+                             cqc_precision prec, Status *st);
+
 }  // namespace cqc
 
 using namespace cqc;
@@ -97,6 +94,11 @@ int cqc_fd_workspace_size(const cqc_instance *inst, int32_t n_inst, cqc_dtype in
   Status st = fd_plans(inst, n_inst, in_t, out_t, prec, false, &plans, &acc);
   if (!st.good()) return st.code;
   *bytes = plans.back().end;
+  if (n_inst > 1 && (out_t == CQC_F64) == (acc == Acc::F64)) {
+    const size_t b = batch_workspace_bytes(inst, n_inst, in_t, out_t, prec, &st);
+    if (!st.good()) return st.code;
+    *bytes = b;
+  }
   return CQC_OK;
 }
 
@@ -116,6 +118,15 @@ int cqc_reconstruct_fd(const cqc_instance *inst, int32_t n_inst, cqc_dtype in_t,
     return Status::fail(CQC_ERR_WORKSPACE, "workspace must be 256-byte aligned").code;
   char *ws = static_cast<char *>(workspace);
   const bool in_double = in_t == CQC_F64, acc_double = acc == Acc::F64;
+  if (n_inst > 1 && (out_t == CQC_F64) == acc_double) {
+    // batched: one flag pass, one launch per step group, one mass pass
+    cqc_batch b = nullptr;
+    int rc = cqc_batch_create(inst, n_inst, in_t, out_t, prec, workspace, ws_bytes, stream, &b);
+    if (rc != CQC_OK) return rc;
+    rc = cqc_batch_run(b, stream);
+    cqc_batch_destroy(b);
+    return rc;
+  }
   for (int32_t i = 0; i < n_inst; ++i) {
     const FdInstancePlan &ip = plans[i];
     std::vector<const void *> ents(ip.cut.nsub);

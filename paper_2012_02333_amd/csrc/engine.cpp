@@ -1,6 +1,7 @@
 // Workspace layout and enqueue of a contraction plan.
 #include "engine.hpp"
 
+#include <algorithm>
 #include <cstring>
 
 namespace cqc {
@@ -42,7 +43,15 @@ NetLayout layout_net(const Plan &plan, Acc acc, size_t base) {
     L.tile.push_back(cfg);
     L.nblocks.push_back(tm * tn * st.nbatch);
   }
-  if (last >= 0) max_final_blocks = L.nblocks[last];
+  if (last >= 0) {
+    // room for the per-tile partials of any tile shape the last step may run
+    // with (the batched path uses its own shape choice; kTileS has the most tiles)
+    const Step &st = plan.steps[last];
+    const TileShape sh = tile_shape(kTileS);
+    const int64_t tS = (((int64_t(1) << st.logM) + sh.bm - 1) / sh.bm) *
+                       (((int64_t(1) << st.logN) + sh.bn - 1) / sh.bn) * st.nbatch;
+    max_final_blocks = std::max(L.nblocks[last], tS);
+  }
   L.partials_off = off;
   off = align_up(off + 8 * (size_t)max_final_blocks, 256);
   L.bytes = off;
@@ -97,8 +106,8 @@ Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &en
     fa.n = n;
     fa.is_double = L.acc == Acc::F64;
     if (p.single) {
-      fa.unit = ws + L.t_off[1];
-      fa.unit_flag = reinterpret_cast<int32_t *>(ws + L.f_off[1]);
+      fa.d[0].unit = ws + L.t_off[1];
+      fa.d[0].unit_flag = reinterpret_cast<int32_t *>(ws + L.f_off[1]);
     }
     CQC_TRY(launch_row_flags(fa, blocks, s));
   }

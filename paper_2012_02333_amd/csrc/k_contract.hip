@@ -139,7 +139,7 @@ __global__ __launch_bounds__(256) void k_mass_final(const double *partials, int6
 }
 
 template <typename T, typename O, int BM, int BN, int WM, int WN, int MODE>
-__global__ __launch_bounds__(256) void k_contract(const ContractArgs a) {
+__device__ __forceinline__ void contract_tile(const ContractArgs &a, uint32_t blk_in) {
   constexpr int TM = BM / WM, TN = BN / WN;     // wave tile
   constexpr int BMB = TM / 16, BNB = TN / 16;    // 16x16 blocks per wave
   constexpr int KG = 4;                          // k-quads per register group (16 terms)
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(256) void k_contract(const ContractArgs a) {
   __shared__ int64_t coloff[MODE == kModeFinalDeposit ? BN : 1];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t blk = a.xcd_remap ? xcd_remap(blockIdx.x, a.nblocks) : (int64_t)blockIdx.x;
+  const int64_t blk = blk_in;
   const int64_t tiles = (int64_t)a.tilesM * a.tilesN;
   const int64_t batch = blk / tiles;
   const int64_t t = blk - batch * tiles;
@@ -306,7 +306,7 @@ __global__ __launch_bounds__(256) void k_contract(const ContractArgs a) {
   }
   if (a.partials) {
     const double tot = block_sum_f64(msum, red);
-    if (tid == 0) a.partials[blockIdx.x] = tot;
+    if (tid == 0) a.partials[blk] = tot;
   }
 }
 
@@ -315,7 +315,7 @@ __global__ __launch_bounds__(256) void k_contract(const ContractArgs a) {
 // as soon as its matrix-core products are done, so stores start early and
 // few registers are live (all blocks of a launch fit on the chip at once).
 template <typename T, typename O, int BM, int BN, int WM, int WN, int MODE>
-__global__ __launch_bounds__(256) void k_contract_small(const ContractArgs a) {
+__device__ __forceinline__ void contract_small_tile(const ContractArgs &a, uint32_t blk_in) {
   constexpr int TM = BM / WM, TN = BN / WN;
   constexpr int BMB = TM / 16, BNB = TN / 16;
   static_assert(WM * WN == 4, "four waves");
@@ -328,7 +328,7 @@ __global__ __launch_bounds__(256) void k_contract_small(const ContractArgs a) {
   __shared__ int64_t coloff[MODE == kModeFinalDeposit ? BN : 1];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const uint32_t blk = a.xcd_remap ? (uint32_t)xcd_remap(blockIdx.x, a.nblocks) : blockIdx.x;
+  const uint32_t blk = blk_in;
   const uint32_t tiles = (uint32_t)a.tilesM * (uint32_t)a.tilesN;
   const uint32_t batch = blk / tiles;
   const uint32_t t = blk - batch * tiles;
@@ -458,24 +458,60 @@ __global__ __launch_bounds__(256) void k_contract_small(const ContractArgs a) {
   }
   if (a.partials) {
     const double tot = block_sum_f64(msum, red);
-    if (tid == 0) a.partials[blockIdx.x] = tot;
+    if (tid == 0) a.partials[blk] = tot;
+  }
+}
+
+// ---- launch wrappers: one step per launch, or a work queue over many steps
+template <typename T, typename O, int BM, int BN, int WM, int WN, int MODE, bool SMALL>
+__global__ __launch_bounds__(256) void k_contract(const ContractArgs a) {
+  const uint32_t blk = a.xcd_remap ? (uint32_t)xcd_remap(blockIdx.x, a.nblocks) : blockIdx.x;
+  if (SMALL) contract_small_tile<T, O, BM, BN, WM, WN, MODE>(a, blk);
+  else contract_tile<T, O, BM, BN, WM, WN, MODE>(a, blk);
+}
+
+__device__ __forceinline__ int find_desc(const int64_t *prefix, int n, int64_t item) {
+  int lo = 0, hi = n - 1;   // largest d with prefix[d] <= item
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Persistent blocks take (step, tile) items from an atomic queue until it
+// runs dry; steps are laid out most expensive first, so large instances start
+// early and small ones fill the tail.  Every block leaves once the counter
+// passes `total`.
+template <typename T, typename O, int BM, int BN, int WM, int WN, int MODE, bool SMALL>
+__global__ __launch_bounds__(256) void k_contract_queue(const ContractArgs *descs, const int64_t *prefix,
+                                                        int ndesc, unsigned long long *queue, int64_t total) {
+  __shared__ int64_t item;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) item = (int64_t)atomicAdd(queue, 1ull);
+    __syncthreads();
+    const int64_t it = item;
+    if (it >= total) return;
+    const int d = find_desc(prefix, ndesc, it);
+    if (SMALL) contract_small_tile<T, O, BM, BN, WM, WN, MODE>(descs[d], (uint32_t)(it - prefix[d]));
+    else contract_tile<T, O, BM, BN, WM, WN, MODE>(descs[d], (uint32_t)(it - prefix[d]));
   }
 }
 
 // ---------------------------------------------------------------------------
 // Row flags of the entry tensors: one block per (row, chunk of kFlagChunk
-// columns) writes whether that chunk has a non-zero element.
-__global__ __launch_bounds__(256) void k_row_flags(const FlagArgs a) {
-  const int64_t bid = blockIdx.x;
-  int i = 0;
-  while (i + 1 < a.n && bid >= a.d[i + 1].block_start) ++i;
-  const FlagDesc &d = a.d[i];
+// columns) writes whether that chunk has a non-zero element.  The first block
+// of a tensor that carries a unit operand (single-subcircuit plans) also
+// writes that operand's value 1 and its flag.
+__device__ __forceinline__ void flags_chunk(const FlagDesc &d, int64_t rc, bool is_double) {
   const int64_t nch = flag_chunks(d.cols);
-  const int64_t rc = bid - d.block_start;
   const int64_t r = rc / nch, ch = rc - r * nch;
-  const int64_t c0 = ch * kFlagChunk, c1 = min(d.cols, c0 + kFlagChunk);
+  const int64_t c0 = ch * kFlagChunk;
+  const int64_t c1 = d.cols < c0 + kFlagChunk ? d.cols : c0 + kFlagChunk;
   int any = 0;
-  if (a.is_double) {
+  if (is_double) {
     const double *p = static_cast<const double *>(d.ptr) + r * d.cols;
     if (d.cols % 2 == 0) {
       const double2 *q = reinterpret_cast<const double2 *>(p);
@@ -503,12 +539,47 @@ __global__ __launch_bounds__(256) void k_row_flags(const FlagArgs a) {
   any = __syncthreads_or(any);
   if (threadIdx.x == 0) {
     d.flags[rc] = any ? 1 : 0;
-    if (bid == 0 && a.unit) {
-      if (a.is_double) *static_cast<double *>(a.unit) = 1.0;
-      else *static_cast<float *>(a.unit) = 1.0f;
-      *a.unit_flag = 1;
+    if (rc == 0 && d.unit) {
+      if (is_double) *static_cast<double *>(d.unit) = 1.0;
+      else *static_cast<float *>(d.unit) = 1.0f;
+      *d.unit_flag = 1;
     }
   }
+}
+
+__global__ __launch_bounds__(256) void k_row_flags(const FlagArgs a) {
+  const int64_t bid = blockIdx.x;
+  int i = 0;
+  while (i + 1 < a.n && bid >= a.d[i + 1].block_start) ++i;
+  flags_chunk(a.d[i], bid - a.d[i].block_start, a.is_double != 0);
+}
+
+__global__ __launch_bounds__(256) void k_row_flags_table(const FlagDesc *descs, int32_t n, int32_t is_double,
+                                                         unsigned long long *counters, int32_t n_counters) {
+  const int64_t bid = blockIdx.x;
+  if (bid == 0 && (int)threadIdx.x < n_counters) counters[threadIdx.x] = 0ull;
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].block_start <= bid) lo = mid;
+    else hi = mid - 1;
+  }
+  flags_chunk(descs[lo], bid - descs[lo].block_start, is_double != 0);
+}
+
+// One block per instance: its FP64 mass from the per-tile partials, in order.
+__global__ __launch_bounds__(256) void k_mass_table(const MassDesc *descs) {
+  const MassDesc &d = descs[blockIdx.x];
+  __shared__ double tsum[256];
+  double v = 0.0;
+  for (int64_t i = threadIdx.x; i < d.count; i += blockDim.x) v += d.partials[i];
+  tsum[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) tsum[threadIdx.x] += tsum[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) d.mass[0] = tsum[0];
 }
 
 template <typename S, typename D>
@@ -553,23 +624,48 @@ int choose_tile(int logM, int logN) {
   return kTileS;
 }
 
+template <typename T, typename O, int MODE, bool SMALL>
+static Status launch_contract_ms(int cfg, const ContractArgs &a, hipStream_t s) {
+  const dim3 grid((unsigned)a.nblocks), block(256);
+  switch (cfg) {
+    case kTileL: return launch(SMALL ? "contract_small_64x256" : "contract_64x256", k_contract<T, O, 64, 256, 1, 4, MODE, SMALL>, grid, block, 0, s, a);
+    case kTileM: return launch(SMALL ? "contract_small_32x128" : "contract_32x128", k_contract<T, O, 32, 128, 1, 4, MODE, SMALL>, grid, block, 0, s, a);
+    case kTileS: return launch(SMALL ? "contract_small_16x64" : "contract_16x64", k_contract<T, O, 16, 64, 1, 4, MODE, SMALL>, grid, block, 0, s, a);
+    default: return launch(SMALL ? "contract_small_256x16" : "contract_256x16", k_contract<T, O, 256, 16, 4, 1, MODE, SMALL>, grid, block, 0, s, a);
+  }
+}
+
 template <typename T, typename O, int MODE>
 static Status launch_contract_m(int cfg, const ContractArgs &a, hipStream_t s) {
-  const dim3 grid((unsigned)a.nblocks), block(256);
-  if (a.nS <= 2) {
-    switch (cfg) {
-      case kTileL: return launch("contract_small_64x256", k_contract_small<T, O, 64, 256, 1, 4, MODE>, grid, block, 0, s, a);
-      case kTileM: return launch("contract_small_32x128", k_contract_small<T, O, 32, 128, 1, 4, MODE>, grid, block, 0, s, a);
-      case kTileS: return launch("contract_small_16x64", k_contract_small<T, O, 16, 64, 1, 4, MODE>, grid, block, 0, s, a);
-      default: return launch("contract_small_256x16", k_contract_small<T, O, 256, 16, 4, 1, MODE>, grid, block, 0, s, a);
-    }
-  }
+  if (a.nS <= 2) return launch_contract_ms<T, O, MODE, true>(cfg, a, s);
+  return launch_contract_ms<T, O, MODE, false>(cfg, a, s);
+}
+
+template <typename T, int MODE, bool SMALL>
+static Status launch_queue_t(int cfg, const QueueLaunch &q, hipStream_t s) {
+  const dim3 grid(q.grid), block(256);
+  const char *nm = SMALL ? "contract_small_queue" : "contract_queue";
   switch (cfg) {
-    case kTileL: return launch("contract_64x256", k_contract<T, O, 64, 256, 1, 4, MODE>, grid, block, 0, s, a);
-    case kTileM: return launch("contract_32x128", k_contract<T, O, 32, 128, 1, 4, MODE>, grid, block, 0, s, a);
-    case kTileS: return launch("contract_16x64", k_contract<T, O, 16, 64, 1, 4, MODE>, grid, block, 0, s, a);
-    default: return launch("contract_256x16", k_contract<T, O, 256, 16, 4, 1, MODE>, grid, block, 0, s, a);
+    case kTileL: return launch(nm, k_contract_queue<T, T, 64, 256, 1, 4, MODE, SMALL>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
+    case kTileM: return launch(nm, k_contract_queue<T, T, 32, 128, 1, 4, MODE, SMALL>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
+    default: return launch(nm, k_contract_queue<T, T, 16, 64, 1, 4, MODE, SMALL>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
   }
+}
+
+template <typename T, int MODE>
+static Status launch_queue_m(int cfg, bool small, const QueueLaunch &q, hipStream_t s) {
+  return small ? launch_queue_t<T, MODE, true>(cfg, q, s) : launch_queue_t<T, MODE, false>(cfg, q, s);
+}
+
+Status launch_contract_queue(Acc acc, int mode, int cfg, bool small, const QueueLaunch &q, hipStream_t s) {
+  if (acc == Acc::F32) {
+    if (mode == kModeIntermediate) return launch_queue_m<float, kModeIntermediate>(cfg, small, q, s);
+    if (mode == kModeFinalBlocked) return launch_queue_m<float, kModeFinalBlocked>(cfg, small, q, s);
+    return launch_queue_m<float, kModeFinalDeposit>(cfg, small, q, s);
+  }
+  if (mode == kModeIntermediate) return launch_queue_m<double, kModeIntermediate>(cfg, small, q, s);
+  if (mode == kModeFinalBlocked) return launch_queue_m<double, kModeFinalBlocked>(cfg, small, q, s);
+  return launch_queue_m<double, kModeFinalDeposit>(cfg, small, q, s);
 }
 
 template <typename T, typename O>
@@ -589,6 +685,16 @@ Status launch_contract(Acc acc, bool out_double, int cfg, const ContractArgs &a,
 
 Status launch_mass_final(const double *partials, int64_t count, double *mass, hipStream_t s) {
   return launch("mass_final", k_mass_final, dim3(1), dim3(256), 0, s, partials, count, mass);
+}
+
+Status launch_row_flags_table(const FlagDesc *descs, int32_t n, int64_t total_blocks, bool is_double,
+                              unsigned long long *counters, int32_t n_counters, hipStream_t s) {
+  return launch("row_flags_table", k_row_flags_table, dim3((unsigned)total_blocks), dim3(256), 0, s, descs, n,
+                (int32_t)is_double, counters, n_counters);
+}
+
+Status launch_mass_table(const MassDesc *descs, int32_t n, hipStream_t s) {
+  return launch("mass_table", k_mass_table, dim3((unsigned)n), dim3(256), 0, s, descs);
 }
 
 Status launch_row_flags(const FlagArgs &a, int64_t total_blocks, hipStream_t s) {

@@ -65,14 +65,14 @@ struct FlagDesc {
   int64_t cols;
   int32_t *flags;      // [rows][flag_chunks(cols)]
   int64_t block_start; // first block of this tensor
+  void *unit;          // if non-null: a unit operand (Acc-typed 1.0) is written here
+  int32_t *unit_flag;  //   and its row flag set
 };
 
 struct FlagArgs {
   FlagDesc d[CQC_MAX_SUB + 1];
   int32_t n;
   int32_t is_double;
-  void *unit;           // if non-null: one Acc-typed 1.0 written here, unit_flag = 1
-  int32_t *unit_flag;
 };
 
 enum class Acc { F32, F64 };
@@ -85,6 +85,30 @@ int choose_tile(int logM, int logN);
 
 Status launch_row_flags(const FlagArgs &a, int64_t total_blocks, hipStream_t s);
 Status launch_mass_final(const double *partials, int64_t count, double *mass, hipStream_t s);
+
+// One launch over many contraction steps of the same kernel configuration:
+// descs[d] in device memory, prefix[d] = first queue item of step d (items of
+// step d are its tiles), queue = zeroed counter.
+struct QueueLaunch {
+  const ContractArgs *descs;
+  const int64_t *prefix;
+  int32_t ndesc;
+  unsigned long long *queue;
+  int64_t total;
+  uint32_t grid;
+};
+Status launch_contract_queue(Acc acc, int mode, int cfg, bool small, const QueueLaunch &q, hipStream_t s);
+
+// Batched row flags (descriptor table in device memory, block_start = prefix)
+// and per-instance mass reductions; the flag pass also zeroes `counters`.
+struct MassDesc {
+  const double *partials;
+  int64_t count;
+  double *mass;
+};
+Status launch_row_flags_table(const FlagDesc *descs, int32_t n, int64_t total_blocks, bool is_double,
+                              unsigned long long *counters, int32_t n_counters, hipStream_t s);
+Status launch_mass_table(const MassDesc *descs, int32_t n, hipStream_t s);
 Status launch_contract(Acc acc, bool out_double, int cfg, const ContractArgs &a, hipStream_t s);
 Status launch_convert(const void *src, bool src_double, void *dst, bool dst_double,
                       int64_t count, hipStream_t s);

@@ -1,0 +1,101 @@
+"""Batched reconstruction: many instances of uneven n and K in one call.
+
+Every instance's output must equal (bit for bit) the single-instance call on
+the same inputs - the term order of each output does not depend on the tile
+shape or on batching - and the single-instance path is itself checked against
+the oracle.  A prepared batch is captured into a graph and replayed with eager
+work in between; every replay must reproduce the eager result.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import fd, metrics
+from tests.gpu_util import oracle_inputs
+
+pytestmark = pytest.mark.gpu
+cqc = pytest.importorskip("paper_2012_02333_amd")
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _instances(count, n_lo, n_hi, seed):
+    insts = W.batch_instances(count=count, seed=seed, n_lo=n_lo, n_hi=n_hi)
+    return insts
+
+
+@pytest.mark.parametrize("prec,dtype", [("fp32", torch.float32), ("fp64", torch.float64)])
+def test_batch_equals_single_calls(prec, dtype):
+    _gpu()
+    insts = _instances(24, 8, 14, seed=5)
+    np_dt = np.float32 if dtype == torch.float32 else np.float64
+    ents = [[torch.from_numpy(E.astype(np_dt)).cuda() for E in i.entries] for i in insts]
+    cuts = [cqc.CutMap.from_workload(i.cut) for i in insts]
+    call = cqc.FDCall(ents, cuts, precision=prec)
+    call.run()
+    torch.cuda.synchronize()
+    for k, inst in enumerate(insts):
+        p1, m1 = cqc.reconstruct_fd(ents[k], cuts[k], precision=prec)
+        assert torch.equal(call.outs[k], p1), k
+        assert abs(float(call.mass[k]) - float(m1)) <= 1e-12
+        if k < 6:
+            ref = fd.reconstruct(oracle_inputs([E.astype(np_dt) for E in inst.entries]), inst.cut)
+            assert metrics.rel_l1(call.outs[k].double().cpu().numpy(), ref) <= (1e-6 if prec == "fp32" else 1e-12)
+
+
+def test_batch_structures_mixed():
+    """Batch mixing blocked and permuted outputs, single subcircuits, Kronecker
+    products and cyclic cut graphs."""
+    _gpu()
+    C = W.CutMap
+    cuts_w = [C(9, [4, 5], [0, 0], [1, 1], [5, 0, 3, 8, 1, 2, 4, 7, 6]),
+              C(7, [3, 4], [], [], list(range(7))),
+              C(6, [6], [], [], [3, 1, 0, 5, 2, 4]),
+              C(12, [4, 4, 4], [0, 1, 2, 0], [1, 2, 0, 1], list(range(12))),
+              C(11, [1, 2, 8], [0, 1, 1, 2], [1, 2, 2, 0], list(range(11))),
+              C(10, [5, 5], [0, 0, 0], [1, 1, 1], list(range(10)))]
+    ents_np = [W.random_entries(c, seed=300 + i, zero_rows=((0, 1),) if i == 5 else ()) for i, c in enumerate(cuts_w)]
+    ents = [[torch.from_numpy(E.astype(np.float32)).cuda() for E in e] for e in ents_np]
+    cuts = [cqc.CutMap.from_workload(c) for c in cuts_w]
+    call = cqc.FDCall(ents, cuts, precision="fp32")
+    call.run()
+    torch.cuda.synchronize()
+    for k in range(len(cuts)):
+        p1, _ = cqc.reconstruct_fd(ents[k], cuts[k], precision="fp32")
+        assert torch.equal(call.outs[k], p1), k
+
+
+def test_batch_graph_replay():
+    _gpu()
+    insts = _instances(16, 8, 13, seed=6)
+    ents = [[torch.from_numpy(E.astype(np.float32)).cuda() for E in i.entries] for i in insts]
+    cuts = [cqc.CutMap.from_workload(i.cut) for i in insts]
+    batch = cqc.Batch(ents, cuts, precision="fp32")
+    batch.run()
+    torch.cuda.synchronize()
+    eager = [o.clone() for o in batch.outs]
+    eager_mass = batch.mass.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        for o in batch.outs:
+            o.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            batch.run()
+    torch.cuda.synchronize()
+    for rep in range(4):
+        for o in batch.outs:
+            o.fill_(-1.0)
+        batch.mass.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k in range(len(eager)):
+            assert torch.equal(batch.outs[k], eager[k]), (rep, k)
+        assert torch.equal(batch.mass, eager_mass), rep
