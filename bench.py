@@ -37,7 +37,34 @@ def _args():
     ap.add_argument("--config", default="c2", choices=["c2", "c3"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--calibrate", action="store_true",
+                    help="first run a plain 256 MiB device copy 10 times (reference for HBM counters)")
     return ap.parse_args()
+
+
+TRAFFIC_KERNEL_SOURCES = ["paper_2012_02333_amd/csrc/k_contract.hip", "paper_2012_02333_amd/csrc/kernels.hpp"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(config, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None if there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{config}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha") != kernel_source_hash() or rec.get("kernel") != kernel:
+        return None
+    return rec.get("hbm_bytes_per_launch")
 
 
 def _time_steps(call, outs, steps, warmup, torch):
@@ -101,6 +128,13 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate:
+        a = torch.empty(1 << 26, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     inst = W.config_instance(args.config)
     n, K = inst.n, inst.K
     cut = cqc.CutMap.from_workload(inst.cut)
@@ -143,7 +177,8 @@ def main():
         roof = {"bound": "mfma", "achieved": 2 * macs / (avg_ms * 1e-3) / 1e12, "peak": FP32_PEAK_TFS,
                 "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    tr = recorded_traffic(args.config, name)
+    roof["traffic"] = tr
     roof["kernel"] = name
     roof["kernel_avg_us"] = avg_ms * 1e3
 

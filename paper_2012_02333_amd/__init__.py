@@ -20,7 +20,7 @@ from . import _lib
 from ._lib import CqcError, PREC
 
 __all__ = ["CutMap", "reconstruct_fd", "reconstruct_dd", "reconstruct_backward", "FDCall", "Batch",
-           "ReconstructFD", "cost", "trace", "CqcError", "selftest_mfma", "library_path"]
+           "ReconstructFD", "cost", "autotune", "trace", "CqcError", "selftest_mfma", "library_path"]
 
 _DT = {torch.float32: _lib.F32, torch.float64: _lib.F64}
 
@@ -260,6 +260,14 @@ class ReconstructFD(torch.autograd.Function):
         g = grad_p.contiguous().to(entries[0].dtype)
         grads = reconstruct_backward(list(entries), ctx.cut, g, ctx.precision)
         return (None, None) + tuple(grads)
+
+
+def autotune(call):
+    """Time every tile shape / XCD mapping for the steps of a prepared FDCall
+    (outputs are clobbered) and keep the fastest for their shape classes."""
+    s = torch.cuda.current_stream(call.device).cuda_stream
+    _lib.check(_lib.lib().cqc_autotune(call._insts, call.n_inst, call._in_t, call._out_t, call.prec,
+                                       call.ws.data_ptr(), call.ws_bytes, s))
 
 
 def cost(cut):

@@ -45,12 +45,14 @@ NetLayout layout_net(const Plan &plan, Acc acc, size_t base) {
   }
   if (last >= 0) {
     // room for the per-tile partials of any tile shape the last step may run
-    // with (the batched path uses its own shape choice; kTileS has the most tiles)
+    // with (tuned choices and the batched path may pick another shape)
     const Step &st = plan.steps[last];
-    const TileShape sh = tile_shape(kTileS);
-    const int64_t tS = (((int64_t(1) << st.logM) + sh.bm - 1) / sh.bm) *
-                       (((int64_t(1) << st.logN) + sh.bn - 1) / sh.bn) * st.nbatch;
-    max_final_blocks = std::max(L.nblocks[last], tS);
+    for (int cfg = 0; cfg < kTileCount; ++cfg) {
+      const TileShape sh = tile_shape(cfg);
+      const int64_t t = (((int64_t(1) << st.logM) + sh.bm - 1) / sh.bm) *
+                        (((int64_t(1) << st.logN) + sh.bn - 1) / sh.bn) * st.nbatch;
+      max_final_blocks = std::max(max_final_blocks, t);
+    }
   }
   L.partials_off = off;
   off = align_up(off + 8 * (size_t)max_final_blocks, 256);
@@ -128,22 +130,27 @@ Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &en
     a.nS = (int)st.S.size();
     a.nRX = (int)st.RX.size();
     a.nRY = (int)st.RY.size();
-    TileShape sh = tile_shape(L.tile[i]);
-    a.tilesM = (int)(((int64_t(1) << st.logM) + sh.bm - 1) / sh.bm);
-    a.tilesN = (int)(((int64_t(1) << st.logN) + sh.bn - 1) / sh.bn);
-    a.nblocks = L.nblocks[i];
     a.mx = to_dev(st.mx);
     a.my = to_dev(st.my);
+    const int mode = !last ? kModeIntermediate : (is_blocked(p, st) ? kModeFinalBlocked : kModeFinalDeposit);
+    const bool od = last ? out_double : L.acc == Acc::F64;
+    int cfg = L.tile[i], xcd = 0;
+    if (!tuned_choice(L.acc, mode, a.nS <= 2, st.logM, st.logN, a.nS, od, &cfg, &xcd)) cfg = L.tile[i];
+    const TileShape sh = tile_shape(cfg);
+    a.tilesM = (int)(((int64_t(1) << st.logM) + sh.bm - 1) / sh.bm);
+    a.tilesN = (int)(((int64_t(1) << st.logN) + sh.bn - 1) / sh.bn);
+    a.nblocks = (int64_t)a.tilesM * a.tilesN * st.nbatch;
+    a.xcd_remap = (xcd && a.nblocks % 8 == 0) ? 1 : 0;
     if (!last) {
       a.mode = kModeIntermediate;
       a.Z = ws + L.t_off[st.z];
       a.flagZ = reinterpret_cast<int32_t *>(ws + L.f_off[st.z]);
       a.scale = 1.0;
-      CQC_TRY(launch_contract(L.acc, L.acc == Acc::F64, L.tile[i], a, s));
+      CQC_TRY(launch_contract(L.acc, L.acc == Acc::F64, cfg, a, s));
     } else {
       a.Z = out;
       a.scale = std::ldexp(1.0, -p.K);
-      if (is_blocked(p, st)) {
+      if (mode == kModeFinalBlocked) {
         a.mode = kModeFinalBlocked;
       } else {
         a.mode = kModeFinalDeposit;
@@ -156,7 +163,7 @@ Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &en
         a.posY = pack_pos(py);
       }
       if (mass) a.partials = reinterpret_cast<double *>(ws + L.partials_off);
-      CQC_TRY(launch_contract(L.acc, out_double, L.tile[i], a, s));
+      CQC_TRY(launch_contract(L.acc, out_double, cfg, a, s));
       if (mass) CQC_TRY(launch_mass_final(a.partials, a.nblocks, mass, s));
     }
   }

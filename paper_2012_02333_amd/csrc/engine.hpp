@@ -32,6 +32,8 @@ Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &en
                hipStream_t s, bool skip_final = false);
 
 DigitMapDev to_dev(const DigitMap &m);
+// Tile shape and XCD mapping recorded by the autotuner for a step's shape class.
+bool tuned_choice(Acc acc, int mode, bool small, int logM, int logN, int nS, bool out_double, int *cfg, int *xcd);
 BitPos pack_pos(const std::vector<int> &pos);
 
 inline bool is_blocked(const Plan &p, const Step &st) {

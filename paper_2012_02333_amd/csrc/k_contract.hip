@@ -324,6 +324,11 @@ __device__ __forceinline__ void contract_small_tile(const ContractArgs &a, uint3
 
   __shared__ int2 lst[16];
   __shared__ double red[4];
+  // FP32 store staging: one 16 x TN slice per wave, so each store instruction
+  // writes whole TN-wide row segments instead of 64-byte pieces.
+  constexpr bool kStage = Op::kConsecutive && sizeof(O) == 4 && MODE != kModeFinalDeposit && TN >= 32;
+  constexpr int SLD = TN + 4;
+  __shared__ float stage[kStage ? 4 * 16 * SLD : 1];
   __shared__ int64_t rowoff[MODE == kModeFinalDeposit ? BM : 1];
   __shared__ int64_t coloff[MODE == kModeFinalDeposit ? BN : 1];
 
@@ -348,9 +353,37 @@ __device__ __forceinline__ void contract_small_tile(const ContractArgs &a, uint3
     for (int c = tid; c < BN; c += 256)
       coloff[c] = (int64_t)tn * BN + c < N ? deposit((int64_t)tn * BN + c, a.posY, a.logN) : 0;
   }
-  // live terms (ascending s), computed by the first 16 lanes of wave 0
+  // Operands are loaded for the full term list s = 0..4^|S|-1 at once (term
+  // s = 4q + lane/16 in quad q), in parallel with the row-flag check; only if
+  // some term turns out dead are they reloaded from the compacted live list.
   const int nSv = 1 << (2 * a.nS);
-  int cnt = 0;
+  int2 rrq[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int sq = 4 * q + lg;
+    rrq[q] = sq < nSv ? make_int2(row_of(a.mx, sq, rX), row_of(a.my, sq, rY)) : make_int2(-1, -1);
+  }
+  T ay[4][BNB], bxa[BMB][4];
+  auto load_ops = [&]() {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const bool kok = rrq[q].x >= 0;
+      const T *yr = Y + (int64_t)(kok ? rrq[q].y : 0) * N;
+      const T *xr = X + (int64_t)(kok ? rrq[q].x : 0) * M;
+#pragma unroll
+      for (int j = 0; j < BNB; ++j) {
+        const int64_t c = nw + j * 16 + l16;
+        ay[q][j] = (kok && c < N) ? yr[c] : (T)0;
+      }
+#pragma unroll
+      for (int i = 0; i < BMB; ++i) {
+        const int64_t c = mw + i * 16 + l16;
+        bxa[i][q] = (kok && c < M) ? xr[c] : (T)0;
+      }
+    }
+  };
+  load_ops();
+  __shared__ int cnt_sh;
   if (wave == 0) {
     int live = 0, rx = 0, ry = 0;
     if (lane < nSv) {
@@ -360,37 +393,23 @@ __device__ __forceinline__ void contract_small_tile(const ContractArgs &a, uint3
     }
     const unsigned long long bal = __ballot(live);
     const int pre = __popcll(bal & ((1ull << lane) - 1ull));
-    cnt = __popcll(bal);
+    const int cnt = __popcll(bal);
     if (live) lst[pre] = make_int2(rx, ry);
     if (lane >= cnt && lane < 16) lst[lane] = make_int2(-1, -1);
+    if (lane == 0) cnt_sh = cnt;
   }
   __syncthreads();
-  // Y operands of all terms for this wave's columns
-  T ay[4][BNB];
+  if (cnt_sh != nSv) {       // early termination: drop the dead terms
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int2 rr = lst[4 * q + lg];
-    const bool kok = rr.x >= 0;
-    const T *yr = Y + (int64_t)(kok ? rr.y : 0) * N;
-#pragma unroll
-    for (int j = 0; j < BNB; ++j) {
-      const int64_t c = nw + j * 16 + l16;
-      ay[q][j] = (kok && c < N) ? yr[c] : (T)0;
-    }
+    for (int q = 0; q < 4; ++q) rrq[q] = lst[4 * q + lg];
+    load_ops();
   }
-  int2 rrq[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) rrq[q] = lst[4 * q + lg];
 
   double msum = 0.0;
   const O scale = (O)a.scale;
 #pragma unroll
   for (int i = 0; i < BMB; ++i) {
-    T bx[4];
-    const int64_t xc = mw + i * 16 + l16;
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      bx[q] = (rrq[q].x >= 0 && xc < M) ? X[(int64_t)rrq[q].x * M + xc] : (T)0;
+    const T *bx = bxa[i];
     V acc[BNB];
 #pragma unroll
     for (int j = 0; j < BNB; ++j) acc[j] = V{0, 0, 0, 0};
@@ -399,6 +418,27 @@ __device__ __forceinline__ void contract_small_tile(const ContractArgs &a, uint3
 #pragma unroll
       for (int j = 0; j < BNB; ++j)
         acc[j] = Op::kConsecutive ? Op::run(ay[q][j], bx[q], acc[j]) : Op::run(bx[q], ay[q][j], acc[j]);
+    if (kStage && mw + i * 16 + 16 <= M && nw + TN <= N) {
+      float *st = stage + wave * 16 * SLD;
+      const float sc = MODE == kModeIntermediate ? 1.0f : (float)a.scale;
+#pragma unroll
+      for (int j = 0; j < BNB; ++j)
+        *reinterpret_cast<float4 *>(st + l16 * SLD + j * 16 + 4 * lg) =
+            make_float4((float)acc[j][0] * sc, (float)acc[j][1] * sc, (float)acc[j][2] * sc, (float)acc[j][3] * sc);
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      constexpr int LPR = TN / 4, RPI = 64 / LPR;
+      const int64_t mrow = mw + i * 16;
+      O *Zb = MODE == kModeIntermediate ? static_cast<O *>(a.Z) + (int64_t)batch * M * N : static_cast<O *>(a.Z);
+#pragma unroll
+      for (int rr = 0; rr < 16; rr += RPI) {
+        const int row = rr + lane / LPR, col = (lane % LPR) * 4;
+        const float4 v = *reinterpret_cast<const float4 *>(st + row * SLD + col);
+        *reinterpret_cast<float4 *>(Zb + (mrow + row) * N + nw + col) = v;
+        if (MODE != kModeIntermediate) msum += ((double)v.x + (double)v.y) + ((double)v.z + (double)v.w);
+      }
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      continue;
+    }
 #pragma unroll
     for (int j = 0; j < BNB; ++j) {
       const int64_t nb = nw + j * 16;
@@ -453,7 +493,7 @@ __device__ __forceinline__ void contract_small_tile(const ContractArgs &a, uint3
     }
   }
   if (MODE == kModeIntermediate) {
-    if (a.flagZ && tm == 0 && tn == 0 && tid == 0) a.flagZ[batch] = lst[0].x >= 0;
+    if (a.flagZ && tm == 0 && tn == 0 && tid == 0) a.flagZ[batch] = cnt_sh > 0;
     return;
   }
   if (a.partials) {
