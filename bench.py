@@ -129,12 +129,21 @@ def main():
         print("no GPU", file=sys.stderr)
         sys.exit(1)
     if args.calibrate:
-        a = torch.empty(1 << 26, dtype=torch.float32, device="cuda").fill_(1.0)
+        # reference kernels of known traffic for the HBM counters: a 256 MiB
+        # fill (writes 256 MiB) and a 256 MiB elementwise add (reads 256 MiB,
+        # writes 256 MiB), each on buffers not touched just before
+        a = torch.empty(1 << 26, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
-        for _ in range(10):
-            b.copy_(a)
+        c = torch.empty_like(a)
+        a.fill_(1.0)
+        c.fill_(0.0)
         torch.cuda.synchronize()
-        del a, b
+        for _ in range(3):
+            torch.add(a, 1.0, out=b)
+            torch.add(c, 1.0, out=a)
+            torch.add(b, 1.0, out=c)
+        torch.cuda.synchronize()
+        del a, b, c
     inst = W.config_instance(args.config)
     n, K = inst.n, inst.K
     cut = cqc.CutMap.from_workload(inst.cut)
