@@ -203,8 +203,9 @@ const char *cqc_last_error_detail(void); /* thread-local, of the last failing ca
 int cqc_version(void);
 
 /* Self test of the MFMA operand/accumulator lane layouts the kernels assume:
- * runs one 16x16x4 FP32 and one FP64 matrix-core product on known operands
- * (DEVICE out: 256 floats then 256 doubles) and returns CQC_OK if launched. */
+ * runs one 16x16x4 FP32, one 16x16x4 FP64 and one 16x16x32 BF16 matrix-core
+ * product on known operands (DEVICE out: 256 floats, 256 doubles, 256 floats:
+ * 4096 bytes) and returns CQC_OK if launched. */
 int cqc_selftest_mfma(void *out, hipStream_t stream);
 
 #ifdef __cplusplus

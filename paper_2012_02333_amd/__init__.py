@@ -245,7 +245,8 @@ def reconstruct_backward(entries, cut, grad_out, precision="fp32"):
 
 
 class ReconstructFD(torch.autograd.Function):
-    """p = FD(entries); backward runs the library's adjoint kernels."""
+    """p = FD(entries); backward runs the library's adjoint kernels.  The
+    adjoint has no BF16X6 form: a BF16X6 forward is differentiated in FP32."""
 
     @staticmethod
     def forward(ctx, cut, precision, *entries):
@@ -258,7 +259,8 @@ class ReconstructFD(torch.autograd.Function):
     def backward(ctx, grad_p):
         entries = ctx.saved_tensors
         g = grad_p.contiguous().to(entries[0].dtype)
-        grads = reconstruct_backward(list(entries), ctx.cut, g, ctx.precision)
+        prec = "fp32" if ctx.precision == "bf16x6" else ctx.precision
+        grads = reconstruct_backward(list(entries), ctx.cut, g, prec)
         return (None, None) + tuple(grads)
 
 
@@ -302,10 +304,11 @@ def read_trace(max_kernels=64):
 
 
 def selftest_mfma(device="cuda"):
-    """Run the MFMA lane-layout probe -> (D_f32[16,16], D_f64[16,16])."""
-    buf = torch.zeros(256 * 4 + 256 * 8, dtype=torch.uint8, device=device)
+    """Run the MFMA lane-layout probe -> (D_f32[16,16], D_f64[16,16], D_bf16[16,16])."""
+    buf = torch.zeros(256 * 4 + 256 * 8 + 256 * 4, dtype=torch.uint8, device=device)
     _lib.check(_lib.lib().cqc_selftest_mfma(buf.data_ptr(), _stream_ptr()))
     torch.cuda.synchronize()
     f = buf[:1024].view(torch.float32).reshape(16, 16).cpu()
-    d = buf[1024:].view(torch.float64).reshape(16, 16).cpu()
-    return f, d
+    d = buf[1024:3072].view(torch.float64).reshape(16, 16).cpu()
+    b = buf[3072:].view(torch.float32).reshape(16, 16).cpu()
+    return f, d, b

@@ -37,6 +37,8 @@ struct cqc_batch_s {
     const int64_t *prefix;
     int32_t ndesc;
     int64_t total;
+    const int64_t *bprefix;   // wide kernel: first batch entry of each step (label-list pass)
+    int64_t btotal;
   };
   std::vector<Group> groups;
 };
@@ -61,11 +63,11 @@ struct BatchBuild {
   };
   std::vector<G> groups;
   size_t flag_off = 0, mass_off = 0, counter_off = 0;
-  std::vector<size_t> desc_off, prefix_off;
+  std::vector<size_t> desc_off, prefix_off, bprefix_off;
 };
 
-static int queue_cfg(int logM, int logN) {
-  const int c = choose_tile(logM, logN);
+static int queue_cfg(Acc acc, const Step &st) {
+  const int c = choose_tile(acc, (int)st.S.size(), st.logM, st.logN, st.wide_ok());
   return c == kTileT ? kTileS : c;
 }
 
@@ -125,13 +127,14 @@ static Status build_batch(const cqc_instance *inst, int32_t n_inst, cqc_dtype in
       a.nS = (int)st.S.size();
       a.nRX = (int)st.RX.size();
       a.nRY = (int)st.RY.size();
-      const int cfg = queue_cfg(st.logM, st.logN);
+      const int cfg = queue_cfg(B.acc, st);
       const TileShape sh = tile_shape(cfg);
       a.tilesM = (int)(((int64_t(1) << st.logM) + sh.bm - 1) / sh.bm);
       a.tilesN = (int)(((int64_t(1) << st.logN) + sh.bn - 1) / sh.bn);
       a.nblocks = (int64_t)a.tilesM * a.tilesN * st.nbatch;
       a.mx = to_dev(st.mx);
       a.my = to_dev(st.my);
+      set_lists(L, s, ws, &a);
       int level = (int)s;
       if (!last) {
         a.mode = kModeIntermediate;
@@ -202,6 +205,8 @@ static Status build_batch(const cqc_instance *inst, int32_t n_inst, cqc_dtype in
     off = align_up(off + sizeof(ContractArgs) * g.steps.size(), 256);
     B.prefix_off.push_back(off);
     off = align_up(off + sizeof(int64_t) * (g.steps.size() + 1), 256);
+    B.bprefix_off.push_back(off);
+    if (g.cfg == kTileW) off = align_up(off + sizeof(int64_t) * (g.steps.size() + 1), 256);
   }
   B.bytes = off;
   if (B.groups.size() > 256)
@@ -239,6 +244,8 @@ static Status batch_run(cqc_batch_s *b, hipStream_t s) {
     q.queue = b->counters + g;
     q.total = G.total;
     q.grid = (uint32_t)std::min<int64_t>(G.total, kQueueGrid);
+    q.bprefix = G.bprefix;
+    q.btotal = G.btotal;
     CQC_TRY(launch_contract_queue(b->acc, G.mode, G.cfg, G.small, q, s));
   }
   if (b->n_mass > 0) CQC_TRY(launch_mass_table(b->mass_descs, b->n_mass, s));
@@ -276,13 +283,15 @@ static Status batch_create(const cqc_instance *inst, int32_t n_inst, cqc_dtype i
   for (size_t g = 0; g < B.groups.size(); ++g) {
     const auto &G = B.groups[g];
     std::vector<ContractArgs> descs;
-    std::vector<int64_t> prefix(1, 0);
+    std::vector<int64_t> prefix(1, 0), bprefix(1, 0);
     for (auto &st : G.steps) {
       descs.push_back(st.second);
       prefix.push_back(prefix.back() + st.second.nblocks);
+      bprefix.push_back(bprefix.back() + st.second.nbatch);
     }
     put(B.desc_off[g], descs.data(), sizeof(ContractArgs) * descs.size());
     put(B.prefix_off[g], prefix.data(), sizeof(int64_t) * prefix.size());
+    if (G.cfg == kTileW) put(B.bprefix_off[g], bprefix.data(), sizeof(int64_t) * bprefix.size());
     cqc_batch_s::Group bg;
     bg.level = G.level;
     bg.mode = G.mode;
@@ -292,6 +301,8 @@ static Status batch_create(const cqc_instance *inst, int32_t n_inst, cqc_dtype i
     bg.prefix = reinterpret_cast<const int64_t *>(ws + B.prefix_off[g]);
     bg.ndesc = (int32_t)descs.size();
     bg.total = prefix.back();
+    bg.bprefix = G.cfg == kTileW ? reinterpret_cast<const int64_t *>(ws + B.bprefix_off[g]) : nullptr;
+    bg.btotal = G.cfg == kTileW ? bprefix.back() : 0;
     b->groups.push_back(bg);
   }
   hipError_t e = hipMemcpyAsync(ws + B.tables_off, img.data(), img.size(), hipMemcpyHostToDevice, s);

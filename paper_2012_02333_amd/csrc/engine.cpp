@@ -10,7 +10,7 @@ NetLayout layout_net(const Plan &plan, Acc acc, size_t base) {
   NetLayout L;
   L.plan = plan;
   L.acc = acc;
-  L.esz = acc == Acc::F32 ? 4 : 8;
+  L.esz = acc == Acc::F64 ? 8 : 4;
   size_t off = align_up(base, 256);
   const size_t nt = plan.tensors.size();
   L.t_off.assign(nt, 0);
@@ -36,7 +36,7 @@ NetLayout layout_net(const Plan &plan, Acc acc, size_t base) {
   }
   int64_t max_final_blocks = 1;
   for (const auto &st : plan.steps) {
-    int cfg = choose_tile(st.logM, st.logN);
+    int cfg = choose_tile(acc, (int)st.S.size(), st.logM, st.logN, st.wide_ok());
     TileShape sh = tile_shape(cfg);
     int64_t tm = ((int64_t(1) << st.logM) + sh.bm - 1) / sh.bm;
     int64_t tn = ((int64_t(1) << st.logN) + sh.bn - 1) / sh.bn;
@@ -56,8 +56,26 @@ NetLayout layout_net(const Plan &plan, Acc acc, size_t base) {
   }
   L.partials_off = off;
   off = align_up(off + 8 * (size_t)max_final_blocks, 256);
+  // label lists of every step that may run on the wide kernel
+  L.list_off.assign(plan.steps.size(), SIZE_MAX);
+  if (acc != Acc::F64) {
+    for (size_t i = 0; i < plan.steps.size(); ++i) {
+      const Step &st = plan.steps[i];
+      L.list_off[i] = off;
+      off = align_up(off + wide_list_bytes((int)st.S.size(), st.nbatch), 256);
+    }
+  }
   L.bytes = off;
   return L;
+}
+
+void set_lists(const NetLayout &L, size_t step, char *ws, ContractArgs *a) {
+  const Step &st = L.plan.steps[step];
+  a->nbatch = st.nbatch;
+  if (L.list_off.empty() || L.list_off[step] == SIZE_MAX) return;
+  a->list_ld = wide_list_ld((int)st.S.size());
+  a->lists = reinterpret_cast<int32_t *>(ws + L.list_off[step]);
+  a->counts = reinterpret_cast<int32_t *>(ws + L.list_off[step] + (size_t)st.nbatch * a->list_ld * 8);
 }
 
 DigitMapDev to_dev(const DigitMap &m) {
@@ -132,10 +150,16 @@ Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &en
     a.nRY = (int)st.RY.size();
     a.mx = to_dev(st.mx);
     a.my = to_dev(st.my);
+    set_lists(L, i, ws, &a);
     const int mode = !last ? kModeIntermediate : (is_blocked(p, st) ? kModeFinalBlocked : kModeFinalDeposit);
     const bool od = last ? out_double : L.acc == Acc::F64;
     int cfg = L.tile[i], xcd = 0;
-    if (!tuned_choice(L.acc, mode, a.nS <= 2, st.logM, st.logN, a.nS, od, &cfg, &xcd)) cfg = L.tile[i];
+    if (!tuned_choice(L.acc, mode, a.nS <= 2, st.logM, st.logN, a.nS, od, &cfg, &xcd) || !tile_ok(L.acc, cfg)) {
+      cfg = L.tile[i];
+      // the wide kernel's tiles of one operand row block share that block's
+      // operand columns: keep them on one XCD (and its L2)
+      xcd = cfg == kTileW ? 1 : 0;
+    }
     const TileShape sh = tile_shape(cfg);
     a.tilesM = (int)(((int64_t(1) << st.logM) + sh.bm - 1) / sh.bm);
     a.tilesN = (int)(((int64_t(1) << st.logN) + sh.bn - 1) / sh.bn);

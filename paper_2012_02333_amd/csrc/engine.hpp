@@ -17,6 +17,7 @@ struct NetLayout {
   std::vector<int> tile;       // per step
   std::vector<int64_t> nblocks;
   size_t partials_off = 0;
+  std::vector<size_t> list_off;  // per step: label lists of the wide kernel (SIZE_MAX: none)
   size_t bytes = 0;            // end offset (relative to the layout base)
 };
 
@@ -32,6 +33,8 @@ Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &en
                hipStream_t s, bool skip_final = false);
 
 DigitMapDev to_dev(const DigitMap &m);
+// Points a step's arguments at its label-list workspace (wide kernel).
+void set_lists(const NetLayout &L, size_t step, char *ws, ContractArgs *a);
 // Tile shape and XCD mapping recorded by the autotuner for a step's shape class.
 bool tuned_choice(Acc acc, int mode, bool small, int logM, int logN, int nS, bool out_double, int *cfg, int *xcd);
 BitPos pack_pos(const std::vector<int> &pos);

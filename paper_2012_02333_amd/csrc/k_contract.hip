@@ -21,117 +21,31 @@
 // consecutive n of one row and store 128 contiguous bytes per register.  The last step scales by 2^-K (exact) and reduces
 // the FP64 sum of everything it wrote: per-block partials, then the last
 // block to finish adds the partials in block order.
-#include "kernels.hpp"
+#include "kdev.hpp"
 
 namespace cqc {
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-
-template <typename T> struct MfmaOp;
-// Accumulator layout of one 16x16 block (measured by k_selftest_mfma):
-//   FP32: lane l, register r holds row 4*(l/16) + r   (4 consecutive rows)
-//   FP64: lane l, register r holds row (l/16) + 4*r   (rows strided by 4)
-// of column l%16, where "row" is the index contributed by the A operand.
-template <> struct MfmaOp<float> {
-  using V = f32x4;
-  static constexpr bool kConsecutive = true;
-  static __device__ __forceinline__ V run(float a, float b, V c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-};
-template <> struct MfmaOp<double> {
-  using V = f64x4;
-  static constexpr bool kConsecutive = false;
-  static __device__ __forceinline__ V run(double a, double b, V c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-};
-
-__device__ __forceinline__ int row_of(const DigitMapDev &m, int s, int r) {
-  int row = 0;
-#pragma unroll 1
-  for (int i = 0; i < m.n; ++i) {
-    const int v = ((m.srcmask >> i) & 1u) ? r : s;
-    const uint64_t w = i < 10 ? m.shifts[0] : m.shifts[1];
-    const int sh = (int)((w >> (6 * (i < 10 ? i : i - 10))) & 63);
-    row = (row << 2) | ((v >> sh) & 3);
-  }
-  return row;
-}
-
-__device__ int64_t deposit(int64_t v, const BitPos &pos, int nbits) {
-  int64_t out = 0;
-#pragma unroll 1
-  for (int j = 0; j < nbits; ++j) {
-    const uint64_t w = pos.w[0] * (j / 10 == 0) + pos.w[1] * (j / 10 == 1) + pos.w[2] * (j / 10 == 2) +
-                       pos.w[3] * (j / 10 == 3) + pos.w[4] * (j / 10 == 4);
-    out |= ((v >> j) & 1) << ((w >> (6 * (j % 10))) & 63);
-  }
-  return out;
-}
-
-// A row is live if any of its chunk flags is set.
-__device__ __forceinline__ int row_live(const int32_t *flags, int nch, int row) {
-  int any = 0;
-  for (int c = 0; c < nch; ++c) any |= flags[(int64_t)row * nch + c];
-  return any != 0;
-}
-
-// Spread consecutive logical blocks over one XCD: hardware dispatches block i
-// to XCD i % 8, so logical tile t lands on XCD t / (nblocks / 8) and tiles that
-// share an X row block share that XCD's L2.
-__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
-  if (nblocks % 8) return bid;
-  return (bid % 8) * (nblocks / 8) + bid / 8;
-}
-
-template <typename T> __device__ __forceinline__ void load4(const T *p, T *v);
-template <> __device__ __forceinline__ void load4<float>(const float *p, float *v) {
-  float4 t = *reinterpret_cast<const float4 *>(p);
-  v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
-}
-template <> __device__ __forceinline__ void load4<double>(const double *p, double *v) {
-  double2 a = reinterpret_cast<const double2 *>(p)[0];
-  double2 b = reinterpret_cast<const double2 *>(p)[1];
-  v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
-}
-
-template <typename T> __device__ __forceinline__ void store4(T *p, const T *v);
-template <> __device__ __forceinline__ void store4<float>(float *p, const float *v) {
-  *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
-}
-template <> __device__ __forceinline__ void store4<double>(double *p, const double *v) {
-  reinterpret_cast<double2 *>(p)[0] = make_double2(v[0], v[1]);
-  reinterpret_cast<double2 *>(p)[1] = make_double2(v[2], v[3]);
-}
-
-// Block-wide FP64 sum in a fixed order (wave butterfly, then waves 0..3).
-__device__ __forceinline__ double block_sum_f64(double v, double *red) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x == 0) t = ((red[0] + red[1]) + red[2]) + red[3];
-  __syncthreads();
-  return t;
-}
 
 // FP64 mass: every block of the last step stores the FP64 sum of what it
 // wrote; k_mass_final then adds the partials in block order.  (A completion
 // counter in the contraction kernel would need a device-scope release fence
 // per block, which on a multi-XCD part writes back the L2 - full of freshly
 // written outputs - once per block.)
-__global__ __launch_bounds__(256) void k_mass_final(const double *partials, int64_t count,
-                                                    double *mass) {
-  __shared__ double tsum[256];
-  double v = 0.0;
-  for (int64_t i = threadIdx.x; i < count; i += blockDim.x) v += partials[i];
-  tsum[threadIdx.x] = v;
+__global__ __launch_bounds__(1024) void k_mass_final(const double *partials, int64_t count,
+                                                     double *mass) {
+  // thread t adds partials t + 1024 (8 q + u) into accumulator u (eight loads
+  // in flight per thread), then the accumulators and the threads are combined
+  // in a fixed tree: the same order for every call of the same count
+  __shared__ double tsum[1024];
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t i = threadIdx.x;
+  for (; i + 7 * 1024 < count; i += 8 * 1024) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] += partials[i + u * 1024];
+  }
+  for (; i < count; i += 1024) v[0] += partials[i];
+  tsum[threadIdx.x] = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
   __syncthreads();
-  for (int w = 128; w >= 1; w >>= 1) {
+  for (int w = 512; w >= 1; w >>= 1) {
     if ((int)threadIdx.x < w) tsum[threadIdx.x] += tsum[threadIdx.x + w];
     __syncthreads();
   }
@@ -510,15 +424,6 @@ __global__ __launch_bounds__(256) void k_contract(const ContractArgs a) {
   else contract_tile<T, O, BM, BN, WM, WN, MODE>(a, blk);
 }
 
-__device__ __forceinline__ int find_desc(const int64_t *prefix, int n, int64_t item) {
-  int lo = 0, hi = n - 1;   // largest d with prefix[d] <= item
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (prefix[mid] <= item) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
 
 // Persistent blocks take (step, tile) items from an atomic queue until it
 // runs dry; steps are laid out most expensive first, so large instances start
@@ -631,18 +536,31 @@ __global__ __launch_bounds__(256) void k_convert(const S *src, D *dst, int64_t c
 
 // Lane-layout probe: D = A * B for one 16x16x4 block with A[i][k] = i + 16 k,
 // B[k][j] = 1 + k + 4 j (exact in FP32), stored as D[i][j] by the accumulator
-// layouts the contraction kernel relies on (MfmaOp above).
-__global__ void k_selftest_mfma(float *outf, double *outd) {
+// layouts the contraction kernels rely on (MfmaOp above); and one 16x16x32
+// bfloat16 block with A[i][k] = (i + 3k) % 7 - 3, B[k][j] = (2k + j) % 5 - 2,
+// where lane l supplies A[l % 16][8 (l / 16) + e] and B[8 (l / 16) + e][l % 16]
+// (the operand layout of the wide kernel's BF16X6 form).
+__global__ void k_selftest_mfma(float *outf, double *outd, float *outb) {
+  typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
   const int lane = threadIdx.x;
   const int i = lane & 15, k = lane >> 4, j = lane & 15;
   f32x4 cf = {0, 0, 0, 0};
   cf = __builtin_amdgcn_mfma_f32_16x16x4f32((float)(i + 16 * k), (float)(1 + k + 4 * j), cf, 0, 0, 0);
   f64x4 cd = {0, 0, 0, 0};
   cd = __builtin_amdgcn_mfma_f64_16x16x4f64((double)(i + 16 * k), (double)(1 + k + 4 * j), cd, 0, 0, 0);
+  bf16x8 ab, bb;
+  for (int e = 0; e < 8; ++e) {
+    const int kk = 8 * (lane >> 4) + e;
+    ab[e] = (__bf16)(float)((i + 3 * kk) % 7 - 3);
+    bb[e] = (__bf16)(float)((2 * kk + j) % 5 - 2);
+  }
+  f32x4 cb = {0, 0, 0, 0};
+  cb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab, bb, cb, 0, 0, 0);
   for (int r = 0; r < 4; ++r) {
     const int col = lane & 15;
     outf[(4 * (lane >> 4) + r) * 16 + col] = cf[r];
     outd[((lane >> 4) + 4 * r) * 16 + col] = cd[r];
+    outb[(4 * (lane >> 4) + r) * 16 + col] = cb[r];
   }
 }
 
@@ -652,12 +570,23 @@ TileShape tile_shape(int cfg) {
     case kTileL: return {64, 256};
     case kTileM: return {32, 128};
     case kTileS: return {16, 64};
+    case kTileW: return {128, 128};
     default: return {256, 16};
   }
 }
 
-int choose_tile(int logM, int logN) {
+bool tile_ok(Acc acc, int cfg) {
+  if (cfg < 0 || cfg >= kTileCount) return false;
+  if (acc == Acc::BF16X6) return cfg == kTileW;
+  if (acc == Acc::F64) return cfg != kTileW;
+  return true;
+}
+
+int choose_tile(Acc acc, int nS, int logM, int logN, bool wide_ok) {
   const int64_t M = int64_t(1) << logM, N = int64_t(1) << logN;
+  if (acc == Acc::BF16X6) return kTileW;
+  // long term sums over large tiles are compute-bound: LDS-staged operands
+  if (acc == Acc::F32 && wide_ok && nS >= 3 && M >= 128 && N >= 128) return kTileW;
   if (M >= 64 && N >= 256) return kTileL;
   if (N < 64 && M >= 256) return kTileT;
   if (M >= 32 && N >= 128) return kTileM;
@@ -698,6 +627,8 @@ static Status launch_queue_m(int cfg, bool small, const QueueLaunch &q, hipStrea
 }
 
 Status launch_contract_queue(Acc acc, int mode, int cfg, bool small, const QueueLaunch &q, hipStream_t s) {
+  if (!tile_ok(acc, cfg)) return Status::fail(CQC_ERR_INVALID_ARG, "tile configuration not available for this arithmetic");
+  if (cfg == kTileW) return launch_contract_wide_queue(acc == Acc::BF16X6, mode, q, s);
   if (acc == Acc::F32) {
     if (mode == kModeIntermediate) return launch_queue_m<float, kModeIntermediate>(cfg, small, q, s);
     if (mode == kModeFinalBlocked) return launch_queue_m<float, kModeFinalBlocked>(cfg, small, q, s);
@@ -716,6 +647,8 @@ static Status launch_contract_t(int cfg, const ContractArgs &a, hipStream_t s) {
 }
 
 Status launch_contract(Acc acc, bool out_double, int cfg, const ContractArgs &a, hipStream_t s) {
+  if (!tile_ok(acc, cfg)) return Status::fail(CQC_ERR_INVALID_ARG, "tile configuration not available for this arithmetic");
+  if (cfg == kTileW) return launch_contract_wide(acc == Acc::BF16X6, out_double, a, s);
   if (acc == Acc::F32)
     return out_double ? launch_contract_t<float, double>(cfg, a, s)
                       : launch_contract_t<float, float>(cfg, a, s);
@@ -724,7 +657,7 @@ Status launch_contract(Acc acc, bool out_double, int cfg, const ContractArgs &a,
 }
 
 Status launch_mass_final(const double *partials, int64_t count, double *mass, hipStream_t s) {
-  return launch("mass_final", k_mass_final, dim3(1), dim3(256), 0, s, partials, count, mass);
+  return launch("mass_final", k_mass_final, dim3(1), dim3(1024), 0, s, partials, count, mass);
 }
 
 Status launch_row_flags_table(const FlagDesc *descs, int32_t n, int64_t total_blocks, bool is_double,
@@ -757,7 +690,8 @@ Status launch_convert(const void *src, bool src_double, void *dst, bool dst_doub
 Status launch_selftest_mfma(void *out, hipStream_t s) {
   float *of = static_cast<float *>(out);
   double *od = reinterpret_cast<double *>(of + 256);
-  return launch("selftest_mfma", k_selftest_mfma, dim3(1), dim3(64), 0, s, of, od);
+  float *ob = reinterpret_cast<float *>(od + 256);
+  return launch("selftest_mfma", k_selftest_mfma, dim3(1), dim3(64), 0, s, of, od, ob);
 }
 
 }  // namespace cqc

@@ -1,0 +1,565 @@
+// Wide contraction kernel: LDS-staged operands for steps whose term sums are
+// long enough to make the step compute-bound (many shared cut labels), in two
+// arithmetic forms of the same tile program.
+//
+//   FP32    float operands on v_mfma_f32_16x16x4f32, FP32 accumulation.
+//   BF16X6  every float operand a is split into three bfloat16 parts
+//           a = a0 + a1 + a2 (a0 = a rounded to bfloat16, a1 = the remainder
+//           rounded, a2 = the next remainder rounded; the remainders are exact
+//           in FP32, so the three parts carry 24 significand bits), and the six
+//           products a_i b_j with i + j <= 2 are accumulated in FP32 by
+//           v_mfma_f32_16x16x32_bf16, smallest first.  The three dropped
+//           products are below 2^-24 of |a b|, so the result keeps FP32
+//           accuracy at the bfloat16 matrix-core rate (6 products at 16x the
+//           FP32 rate: 2.7x the FP32 form's arithmetic throughput).
+//
+// A label-list pass first compacts, for every batch entry of the step, the
+// live terms (both operand rows non-zero: early termination, Section 4.2) in
+// ascending label order into the workspace.  The contraction itself runs on
+// persistent blocks of four waves (2 x 2), each owning a 128 x 128 output tile
+// at a time and walking a sequence of tiles (a contiguous range per XCD, so
+// the tiles that share operand columns share an L2; or an atomic work queue
+// over many steps).  Terms are consumed 32 at a time: every thread owns one
+// operand column of the tile (threads 0..127 the X columns, 128..255 the Y
+// columns) and loads that column's 32 term values into registers one chunk
+// ahead - across tile boundaries, so the next tile's first operands are in
+// flight while the current tile computes and stores - then writes them to LDS
+// with the term index fastest, so that each lane fetches a whole matrix-core
+// operand with one 16-byte LDS read.  The epilogue stages each 16-row slice of
+// a wave tile through LDS and writes whole 256-byte row segments.
+#include <algorithm>
+#include <map>
+#include <mutex>
+
+#include "kdev.hpp"
+
+namespace cqc {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x2 __attribute__((ext_vector_type(2)));
+
+namespace {
+constexpr int kWB = 128;        // block tile edge (m and n)
+constexpr int kWT = 64;         // wave tile edge
+constexpr int kWC = 32;         // terms per staged chunk
+constexpr int kF32Ld = 36;      // floats per LDS operand column (FP32 form): 32 terms + pad
+constexpr int kB16Ld = 40;      // bfloat16 per LDS operand column and part (BF16X6 form)
+constexpr int kStLd = kWT + 4;  // floats per row of an epilogue staging slice
+}  // namespace
+
+// a = h + m + l with each part the round-to-nearest bfloat16 of what is left.
+__device__ __forceinline__ void split3(float a, __bf16 *h, __bf16 *m, __bf16 *l) {
+  const __bf16 p0 = (__bf16)a;
+  const float r1 = a - (float)p0;
+  const __bf16 p1 = (__bf16)r1;
+  const float r2 = r1 - (float)p1;
+  *h = p0;
+  *m = p1;
+  *l = (__bf16)r2;
+}
+
+// ---- label lists: one block per batch entry of a step; entries are the byte
+// offsets of the two operand rows (operands hold at most 2^30 elements)
+__device__ __forceinline__ void label_list(const ContractArgs &a, int64_t batch) {
+  __shared__ int wcnt[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rX = (int)(batch >> (2 * a.nRY));
+  const int rY = (int)(batch & ((int64_t(1) << (2 * a.nRY)) - 1));
+  int2 *L = reinterpret_cast<int2 *>(a.lists) + batch * a.list_ld;
+  const int nSv = 1 << (2 * a.nS);
+  int total = 0;
+  for (int s0 = 0; s0 < nSv; s0 += 256) {
+    const int s = s0 + tid;
+    int live = 0, rx = 0, ry = 0;
+    if (s < nSv) {
+      rx = row_of(a.mx, s, rX);
+      ry = row_of(a.my, s, rY);
+      live = row_live(a.flagX, a.nchX, rx) & row_live(a.flagY, a.nchY, ry);
+    }
+    const unsigned long long bal = __ballot(live);
+    const int pre = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wcnt[wave] = __popcll(bal);
+    __syncthreads();
+    int base = 0;
+    for (int w = 0; w < wave; ++w) base += wcnt[w];
+    const int cnt = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    if (live)
+      L[total + base + pre] = make_int2((int)((uint32_t)rx << (a.logM + 2)), (int)((uint32_t)ry << (a.logN + 2)));
+    total += cnt;
+    __syncthreads();   // wcnt is rewritten by the next chunk
+  }
+  // pad to whole chunks (one chunk of padding if nothing is live) with row 0
+  // (a valid address; the terms are masked by the count)
+  const int padded = total == 0 ? kWC : (total + kWC - 1) / kWC * kWC;
+  for (int k = total + tid; k < padded; k += 256) L[k] = make_int2(0, 0);
+  if (tid == 0) {
+    a.counts[batch] = total;
+    if (a.flagZ) a.flagZ[batch] = total > 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_label_list(const ContractArgs a) { label_list(a, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void k_label_list_table(const ContractArgs *descs, const int64_t *bprefix,
+                                                          int ndesc) {
+  const int d = find_desc(bprefix, ndesc, blockIdx.x);
+  label_list(descs[d], (int64_t)blockIdx.x - bprefix[d]);
+}
+
+// Values the compiler cannot prove wave-uniform (loaded through pointers the
+// kernel could in principle write) moved to scalar registers.
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni(int64_t v) {
+  return (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)v) |
+         ((int64_t)__builtin_amdgcn_readfirstlane((int32_t)(v >> 32)) << 32);
+}
+template <typename T> __device__ __forceinline__ T *uni(T *p) {
+  return reinterpret_cast<T *>(uni((int64_t)reinterpret_cast<uintptr_t>(p)));
+}
+__device__ __forceinline__ double uni(double v) { return __builtin_bit_cast(double, uni(__builtin_bit_cast(int64_t, v))); }
+// Global-address-space view of a pointer (a pointer that went through an
+// integer is generic to the compiler, which would emit flat accesses).
+template <typename T> using gptr = __attribute__((address_space(1))) T *;
+template <typename T> __device__ __forceinline__ gptr<T> gbl(T *p) { return (gptr<T>)p; }
+
+// ---- a tile of a step: its block index and chunk count; the geometry is
+// recomputed from the step's arguments where it is needed (few scalars live)
+struct WideTile {
+  uint32_t blk;
+  int nch;   // chunks of kWC terms (at least one)
+  int cnt;   // live terms
+};
+
+struct WideGeom {
+  int64_t M, N, m0, n0, batch;
+  int logM, logN;
+};
+
+__device__ __forceinline__ WideGeom wide_geom(const ContractArgs &a, uint32_t blk) {
+  WideGeom g;
+  const uint32_t tilesN = (uint32_t)uni(a.tilesN);
+  const uint32_t tiles = (uint32_t)uni(a.tilesM) * tilesN;
+  const uint32_t batch = blk / tiles;
+  const uint32_t r = blk - batch * tiles;
+  const uint32_t tm = r / tilesN, tn = r - tm * tilesN;
+  g.logM = uni(a.logM);
+  g.logN = uni(a.logN);
+  g.M = int64_t(1) << g.logM;
+  g.N = int64_t(1) << g.logN;
+  g.m0 = (int64_t)tm * kWB;
+  g.n0 = (int64_t)tn * kWB;
+  g.batch = batch;
+  return g;
+}
+
+__device__ __forceinline__ WideTile wide_decode(const ContractArgs &a, uint32_t blk) {
+  const WideGeom g = wide_geom(a, blk);
+  const int cnt = uni(gbl(uni(a.counts))[g.batch]);
+  return WideTile{blk, cnt == 0 ? 1 : (cnt + kWC - 1) / kWC, cnt};
+}
+
+// Tile sequences of a block.  Strided: one step, tiles of a contiguous range
+// per XCD (hardware places block b on XCD b % 8).  Queue: many steps, the next
+// item is fetched by thread 0 one tile ahead into a parity slot of LDS.
+struct StridedSeq {
+  const ContractArgs &a;
+  int64_t pos, end, stride;
+  __device__ StridedSeq(const ContractArgs &args) : a(args) {
+    const int64_t T = a.nblocks, G = gridDim.x, b = blockIdx.x;
+    if (a.xcd_remap && G % 8 == 0 && T % 8 == 0 && G <= T) {
+      const int64_t per = T / 8;
+      pos = (b % 8) * per + b / 8;
+      end = (b % 8) * per + per;
+      stride = G / 8;
+    } else {
+      pos = b;
+      end = T;
+      stride = G;
+    }
+  }
+  __device__ bool first(WideTile *t, int) {
+    if (pos >= end) return false;
+    *t = wide_decode(a, (uint32_t)pos);
+    return true;
+  }
+  __device__ void fetch_ahead(int) {}
+  __device__ bool next(WideTile *t, int) {
+    pos += stride;
+    if (pos >= end) return false;
+    *t = wide_decode(a, (uint32_t)pos);
+    return true;
+  }
+  __device__ const ContractArgs &args(int) const { return a; }
+};
+
+struct QueueSeq {
+  const ContractArgs *descs;
+  const int64_t *prefix;
+  int ndesc;
+  unsigned long long *queue;
+  int64_t total;
+  int64_t *slot;    // [2] queue items, in LDS, by tile parity
+  int d[2] = {0, 0};  // step of the tile of each parity
+  __device__ int64_t read_slot(int par) const {
+    const int64_t v = slot[par];
+    return (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v) |
+           ((int64_t)__builtin_amdgcn_readfirstlane((int)(v >> 32)) << 32);
+  }
+  __device__ bool decode_item(int64_t item, WideTile *t, int par) {
+    if (item >= total) return false;
+    d[par] = uni(find_desc(prefix, ndesc, item));
+    *t = wide_decode(descs[d[par]], (uint32_t)(item - uni(prefix[d[par]])));
+    return true;
+  }
+  __device__ bool first(WideTile *t, int par) {
+    if (threadIdx.x == 0) slot[par] = (int64_t)atomicAdd(queue, 1ull);
+    __syncthreads();
+    return decode_item(read_slot(par), t, par);
+  }
+  // called by every thread before the barrier that precedes next(par)
+  __device__ void fetch_ahead(int par) {
+    if (threadIdx.x == 0) slot[par] = (int64_t)atomicAdd(queue, 1ull);
+  }
+  __device__ bool next(WideTile *t, int par) { return decode_item(read_slot(par), t, par); }
+  __device__ const ContractArgs &args(int par) const { return descs[d[par]]; }
+};
+
+template <bool SPLIT, typename O, int MODE, class Seq>
+__device__ __forceinline__ void wide_run(Seq &seq) {
+  // operand staging area: FP32 [256 columns][kF32Ld]; BF16X6 [3 parts][256][kB16Ld]
+  constexpr int kOpBytes = SPLIT ? 3 * 2 * kWB * kB16Ld * 2 : 2 * kWB * kF32Ld * 4;
+  static_assert(kOpBytes >= 4 * 16 * kStLd * 4, "epilogue staging fits in the operand area");
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kOpBytes];
+  __shared__ double red[4];
+  __shared__ int64_t rowoff[MODE == kModeFinalDeposit ? kWB : 1];
+  __shared__ int64_t coloff[MODE == kModeFinalDeposit ? kWB : 1];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int l16 = lane & 15, lg = lane >> 4;
+  // staging role of the wave: threads 0..127 own the X columns of the tile,
+  // 128..255 the Y columns (wave-uniform)
+  const bool roleX = uni(tid) < kWB;
+
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  // Branch-free prefetch: every lane loads (padding and overhanging columns
+  // read element 0), so all kWC loads of a chunk are in flight together; the
+  // invalid ones are zeroed only when the chunk is written to LDS.
+  float pre[kWC];
+  uint32_t okrow = 0;   // wave-uniform: term k of the chunk is live (k < count)
+  bool colok = true;    // this lane's operand column lies inside the operand
+  auto gload = [&](const ContractArgs &a, const WideTile &t, int ch) {
+    const WideGeom g = wide_geom(a, t.blk);
+    // lane k < 32 fetches list entry k of the chunk; entry k's byte offset
+    // then moves to a scalar register, and each load is a scalar base plus a
+    // 32-bit lane offset
+    const i32x2 *list = uni(reinterpret_cast<const i32x2 *>(a.lists)) + g.batch * uni(a.list_ld);
+    const i32x2 mine = gbl(list)[ch * kWC + (lane & (kWC - 1))];
+    const int myoff = roleX ? mine[0] : mine[1];
+    const char *srcb = reinterpret_cast<const char *>(roleX ? uni(a.X) : uni(a.Y));
+    const int64_t ld = roleX ? g.M : g.N;
+    const int64_t colv = (roleX ? g.m0 : g.n0) + (tid & (kWB - 1));
+    colok = colv < ld;
+    const uint32_t col4 = colok ? (uint32_t)colv * 4u : 0u;
+    const int nv = t.cnt - ch * kWC;   // live terms in this chunk (uniform)
+    okrow = nv >= kWC ? 0xffffffffu : (nv <= 0 ? 0u : (1u << nv) - 1u);
+#pragma unroll
+    for (int k = 0; k < kWC; ++k) {
+      const uint32_t o = (uint32_t)__builtin_amdgcn_readlane(myoff, k);
+      pre[k] = *(gptr<const float>)(gbl(srcb) + (o + col4));
+    }
+  };
+  auto val = [&](int k) { return (colok && ((okrow >> k) & 1u)) ? pre[k] : 0.0f; };
+  auto stage = [&]() {
+    if constexpr (!SPLIT) {
+      // term k of a 16-term group g sits at 16 g + 4 (k % 4) + (k % 16) / 4, so
+      // lane group lg reads terms {lg, lg+4, lg+8, lg+12} of the group at once
+      float *cp = reinterpret_cast<float *>(smem) + tid * kF32Ld;
+#pragma unroll
+      for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+          *reinterpret_cast<float4 *>(cp + 16 * g + 4 * p) =
+              make_float4(val(16 * g + p), val(16 * g + 4 + p), val(16 * g + 8 + p), val(16 * g + 12 + p));
+    } else {
+      __bf16 *bp = reinterpret_cast<__bf16 *>(smem);
+#pragma unroll
+      for (int o = 0; o < 4; ++o) {
+        bf16x8 h, m, l;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          __bf16 x0, x1, x2;
+          split3(val(8 * o + e), &x0, &x1, &x2);
+          h[e] = x0;
+          m[e] = x1;
+          l[e] = x2;
+        }
+        *reinterpret_cast<bf16x8 *>(bp + (0 * 2 * kWB + tid) * kB16Ld + 8 * o) = h;
+        *reinterpret_cast<bf16x8 *>(bp + (1 * 2 * kWB + tid) * kB16Ld + 8 * o) = m;
+        *reinterpret_cast<bf16x8 *>(bp + (2 * 2 * kWB + tid) * kB16Ld + 8 * o) = l;
+      }
+    }
+  };
+  // MFMA mapping: A operand = Y (MFMA row <-> n), B operand = X (MFMA column
+  // <-> m), so lane (l16, lg) accumulates 4 consecutive n of output row l16.
+  auto compute = [&]() {
+    if constexpr (!SPLIT) {
+      const float *px = reinterpret_cast<const float *>(smem) + (wm * kWT + l16) * kF32Ld + 4 * lg;
+      const float *py = reinterpret_cast<const float *>(smem) + (kWB + wn * kWT + l16) * kF32Ld + 4 * lg;
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        float xv[4][4], yv[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float4 v = *reinterpret_cast<const float4 *>(px + i * 16 * kF32Ld + 16 * g);
+          xv[i][0] = v.x; xv[i][1] = v.y; xv[i][2] = v.z; xv[i][3] = v.w;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float4 v = *reinterpret_cast<const float4 *>(py + j * 16 * kF32Ld + 16 * g);
+          yv[j][0] = v.x; yv[j][1] = v.y; yv[j][2] = v.z; yv[j][3] = v.w;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(yv[j][q], xv[i][q], acc[i][j], 0, 0, 0);
+      }
+    } else {
+      const __bf16 *bp = reinterpret_cast<const __bf16 *>(smem);
+      bf16x8 xv[4][3];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+          xv[i][p] = *reinterpret_cast<const bf16x8 *>(bp + (p * 2 * kWB + wm * kWT + i * 16 + l16) * kB16Ld + 8 * lg);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        bf16x8 yv[3];
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+          yv[p] = *reinterpret_cast<const bf16x8 *>(bp + (p * 2 * kWB + kWB + wn * kWT + j * 16 + l16) * kB16Ld +
+                                                    8 * lg);
+        // (part of Y, part of X) for the six products, smallest first
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yv[0], xv[i][2], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yv[2], xv[i][0], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yv[1], xv[i][1], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yv[0], xv[i][1], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yv[1], xv[i][0], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yv[0], xv[i][0], acc[i][j], 0, 0, 0);
+      }
+    }
+  };
+  // Writes the finished tile (all threads; the operand area is free).
+  auto epilogue = [&](const ContractArgs &a, const WideTile &t) {
+    const WideGeom g = wide_geom(a, t.blk);
+    const int64_t M = g.M, N = g.N;
+    if (MODE == kModeFinalDeposit) {
+      if (tid < kWB) rowoff[tid] = g.m0 + tid < M ? deposit(g.m0 + tid, a.posX, g.logM) : 0;
+      else coloff[tid - kWB] = g.n0 + (tid - kWB) < N ? deposit(g.n0 + (tid - kWB), a.posY, g.logN) : 0;
+      __syncthreads();
+    }
+    double msum = 0.0;
+    const int64_t mw = g.m0 + wm * kWT, nw = g.n0 + wn * kWT;
+    const gptr<O> Zb = gbl(uni(static_cast<O *>(a.Z))) + (MODE == kModeIntermediate ? g.batch * M * N : 0);
+    constexpr bool kStage = sizeof(O) == 4 && MODE != kModeFinalDeposit;
+    const double sc64 = uni(a.scale);
+    const float scf = MODE == kModeIntermediate ? 1.0f : (float)sc64;
+    const O scale = (O)sc64;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (kStage && mw + i * 16 + 16 <= M && nw + kWT <= N) {
+        float *st = reinterpret_cast<float *>(smem) + wave * 16 * kStLd;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          *reinterpret_cast<float4 *>(st + l16 * kStLd + j * 16 + 4 * lg) =
+              make_float4(acc[i][j][0] * scf, acc[i][j][1] * scf, acc[i][j][2] * scf, acc[i][j][3] * scf);
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        // 16 lanes per 64-float row, 4 rows per store instruction
+#pragma unroll
+        for (int rr = 0; rr < 16; rr += 4) {
+          const int row = rr + lg, c4 = l16 * 4;
+          const float4 v = *reinterpret_cast<const float4 *>(st + row * kStLd + c4);
+          *(gptr<f32x4>)((gptr<float>)Zb + (mw + i * 16 + row) * N + nw + c4) = f32x4{v.x, v.y, v.z, v.w};
+          if (MODE != kModeIntermediate) msum += ((double)v.x + (double)v.y) + ((double)v.z + (double)v.w);
+        }
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        continue;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t m = mw + i * 16 + l16;
+        const int64_t n = nw + j * 16 + 4 * lg;
+        if (m >= M || n >= N) continue;
+        if (MODE == kModeIntermediate) {
+          const gptr<float> Z = (gptr<float>)Zb + m * N + n;
+          if (n + 3 < N) *(gptr<f32x4>)Z = acc[i][j];
+          else
+            for (int r = 0; r < 4; ++r)
+              if (n + r < N) Z[r] = acc[i][j][r];
+        } else {
+          O v[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) v[r] = (O)acc[i][j][r] * scale;
+          if (MODE == kModeFinalBlocked) {
+            const gptr<O> Z = Zb + m * N + n;
+            for (int r = 0; r < 4; ++r)
+              if (n + r < N) Z[r] = v[r];
+          } else {
+            const int64_t ro = rowoff[m - g.m0];
+            for (int r = 0; r < 4; ++r)
+              if (n + r < N) Zb[ro + coloff[n + r - g.n0]] = v[r];
+          }
+          for (int r = 0; r < 4; ++r)
+            if (n + r < N) msum += (double)v[r];
+        }
+      }
+    }
+    double *partials = uni(a.partials);
+    if (MODE != kModeIntermediate && partials) {
+      const double tot = block_sum_f64(msum, red);
+      if (tid == 0) gbl(partials)[t.blk] = tot;
+    }
+  };
+
+  // ---- the pipelined tile sequence
+  int par = 0;
+  WideTile cur;
+  if (!seq.first(&cur, par)) return;
+  int c = 0;
+  gload(seq.args(par), cur, 0);
+  for (;;) {
+    const bool last = c == cur.nch - 1;
+    if (last) seq.fetch_ahead(par ^ 1);
+    __syncthreads();   // the operand area (and staging slices) are free
+    stage();
+    __syncthreads();
+    WideTile nxt = cur;
+    bool more = true;
+    if (!last) {
+      gload(seq.args(par), cur, c + 1);
+    } else {
+      more = seq.next(&nxt, par ^ 1);
+      if (more) gload(seq.args(par ^ 1), nxt, 0);
+    }
+    compute();
+    if (last) {
+      __syncthreads();   // every wave is done reading operands: stage the outputs
+      epilogue(seq.args(par), cur);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+      if (!more) break;
+      cur = nxt;
+      c = 0;
+      par ^= 1;
+    } else {
+      ++c;
+    }
+  }
+}
+
+// Occupancy target: two blocks per CU (8 waves).  Three FP32 blocks would fit
+// the LDS but not the registers without spilling, and measure slower.
+template <bool SPLIT> struct WideOcc { static constexpr int kWaves = 2; };
+
+template <bool SPLIT, typename O, int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WideOcc<SPLIT>::kWaves, WideOcc<SPLIT>::kWaves)))
+void k_wide(const ContractArgs a) {
+  StridedSeq seq(a);
+  wide_run<SPLIT, O, MODE>(seq);
+}
+
+template <bool SPLIT, int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WideOcc<SPLIT>::kWaves, WideOcc<SPLIT>::kWaves)))
+void k_wide_queue(const ContractArgs *__restrict__ descs,
+                                                    const int64_t *__restrict__ prefix, int ndesc,
+                                                    unsigned long long *queue, int64_t total) {
+  __shared__ int64_t slot[2];
+  QueueSeq seq{descs, prefix, ndesc, queue, total, slot};
+  wide_run<SPLIT, float, MODE>(seq);
+}
+// ---------------------------------------------------------------------------
+bool wide_fits(const ContractArgs &a) {
+  const int64_t x = (int64_t)2 * (a.nS + a.nRX) + a.logM, y = (int64_t)2 * (a.nS + a.nRY) + a.logN;
+  return x <= 30 && y <= 30;
+}
+
+// Blocks of a kernel that fit on the current device at once (cached).
+static int64_t resident_blocks(const void *kernel) {
+  static std::mutex mu;
+  static std::map<std::pair<const void *, int>, int64_t> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = cache.find({kernel, dev});
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  const int64_t v = (int64_t)(per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+  cache[{kernel, dev}] = v;
+  return v;
+}
+
+template <typename K>
+static Status launch_persistent(const char *nm, K kernel, const ContractArgs &a, hipStream_t s) {
+  int64_t G = resident_blocks(reinterpret_cast<const void *>(kernel));
+  if (G <= 0) return Status::fail(CQC_ERR_HIP, "occupancy query failed");
+  G = std::min<int64_t>(G, a.nblocks);
+  if (G >= 8) G -= G % 8;   // whole per-XCD ranges
+  return launch(nm, kernel, dim3((unsigned)G), dim3(256), 0, s, a);
+}
+
+template <bool SPLIT, typename O>
+static Status launch_wide_t(const ContractArgs &a, hipStream_t s) {
+  const char *nm = SPLIT ? "wide_bf16x6_128x128" : "wide_f32_128x128";
+  CQC_TRY(launch("label_list", k_label_list, dim3((unsigned)a.nbatch), dim3(256), 0, s, a));
+  if (a.mode == kModeFinalBlocked) return launch_persistent(nm, k_wide<SPLIT, O, kModeFinalBlocked>, a, s);
+  if (a.mode == kModeFinalDeposit) return launch_persistent(nm, k_wide<SPLIT, O, kModeFinalDeposit>, a, s);
+  return launch_persistent(nm, k_wide<SPLIT, float, kModeIntermediate>, a, s);
+}
+
+Status launch_contract_wide(bool split, bool out_double, const ContractArgs &a, hipStream_t s) {
+  if (!a.lists || !a.counts || a.nbatch < 1 || a.list_ld < wide_list_ld(a.nS))
+    return Status::fail(CQC_ERR_INVALID_ARG, "wide contraction without label-list workspace");
+  if (!wide_fits(a))
+    return Status::fail(CQC_ERR_UNSUPPORTED, "wide contraction: an operand exceeds 2^30 elements");
+  if (split) return out_double ? launch_wide_t<true, double>(a, s) : launch_wide_t<true, float>(a, s);
+  return out_double ? launch_wide_t<false, double>(a, s) : launch_wide_t<false, float>(a, s);
+}
+
+template <bool SPLIT>
+static Status launch_wide_queue_t(int mode, const QueueLaunch &q, hipStream_t s) {
+  const dim3 grid(q.grid), block(256);
+  const char *nm = SPLIT ? "wide_bf16x6_queue" : "wide_f32_queue";
+  CQC_TRY(launch("label_list_table", k_label_list_table, dim3((unsigned)q.btotal), block, 0, s, q.descs, q.bprefix,
+                 q.ndesc));
+  if (mode == kModeFinalBlocked)
+    return launch(nm, k_wide_queue<SPLIT, kModeFinalBlocked>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
+  if (mode == kModeFinalDeposit)
+    return launch(nm, k_wide_queue<SPLIT, kModeFinalDeposit>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
+  return launch(nm, k_wide_queue<SPLIT, kModeIntermediate>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
+}
+
+Status launch_contract_wide_queue(bool split, int mode, const QueueLaunch &q, hipStream_t s) {
+  if (!q.bprefix || q.btotal < 1) return Status::fail(CQC_ERR_INVALID_ARG, "wide queue without label-list table");
+  return split ? launch_wide_queue_t<true>(mode, q, s) : launch_wide_queue_t<false>(mode, q, s);
+}
+
+}  // namespace cqc

@@ -1,0 +1,113 @@
+// Device helpers shared by the contraction kernels (gfx950 only).
+#pragma once
+
+#include "kernels.hpp"
+
+namespace cqc {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct MfmaOp;
+// Accumulator layout of one 16x16 block (measured by k_selftest_mfma):
+//   FP32: lane l, register r holds row 4*(l/16) + r   (4 consecutive rows)
+//   FP64: lane l, register r holds row (l/16) + 4*r   (rows strided by 4)
+// of column l%16, where "row" is the index contributed by the A operand.
+template <> struct MfmaOp<float> {
+  using V = f32x4;
+  static constexpr bool kConsecutive = true;
+  static __device__ __forceinline__ V run(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct MfmaOp<double> {
+  using V = f64x4;
+  static constexpr bool kConsecutive = false;
+  static __device__ __forceinline__ V run(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+__device__ __forceinline__ int row_of(const DigitMapDev &m, int s, int r) {
+  int row = 0;
+#pragma unroll 1
+  for (int i = 0; i < m.n; ++i) {
+    const int v = ((m.srcmask >> i) & 1u) ? r : s;
+    const uint64_t w = i < 10 ? m.shifts[0] : m.shifts[1];
+    const int sh = (int)((w >> (6 * (i < 10 ? i : i - 10))) & 63);
+    row = (row << 2) | ((v >> sh) & 3);
+  }
+  return row;
+}
+
+__device__ inline int64_t deposit(int64_t v, const BitPos &pos, int nbits) {
+  int64_t out = 0;
+#pragma unroll 1
+  for (int j = 0; j < nbits; ++j) {
+    const uint64_t w = pos.w[0] * (j / 10 == 0) + pos.w[1] * (j / 10 == 1) + pos.w[2] * (j / 10 == 2) +
+                       pos.w[3] * (j / 10 == 3) + pos.w[4] * (j / 10 == 4);
+    out |= ((v >> j) & 1) << ((w >> (6 * (j % 10))) & 63);
+  }
+  return out;
+}
+
+// A row is live if any of its chunk flags is set.
+__device__ __forceinline__ int row_live(const int32_t *flags, int nch, int row) {
+  int any = 0;
+  for (int c = 0; c < nch; ++c) any |= flags[(int64_t)row * nch + c];
+  return any != 0;
+}
+
+// Spread consecutive logical blocks over one XCD: hardware dispatches block i
+// to XCD i % 8, so logical tile t lands on XCD t / (nblocks / 8) and tiles that
+// share an X row block share that XCD's L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
+  if (nblocks % 8) return bid;
+  return (bid % 8) * (nblocks / 8) + bid / 8;
+}
+
+template <typename T> __device__ __forceinline__ void load4(const T *p, T *v);
+template <> __device__ __forceinline__ void load4<float>(const float *p, float *v) {
+  float4 t = *reinterpret_cast<const float4 *>(p);
+  v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+}
+template <> __device__ __forceinline__ void load4<double>(const double *p, double *v) {
+  double2 a = reinterpret_cast<const double2 *>(p)[0];
+  double2 b = reinterpret_cast<const double2 *>(p)[1];
+  v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+
+template <typename T> __device__ __forceinline__ void store4(T *p, const T *v);
+template <> __device__ __forceinline__ void store4<float>(float *p, const float *v) {
+  *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+template <> __device__ __forceinline__ void store4<double>(double *p, const double *v) {
+  reinterpret_cast<double2 *>(p)[0] = make_double2(v[0], v[1]);
+  reinterpret_cast<double2 *>(p)[1] = make_double2(v[2], v[3]);
+}
+
+// Block-wide FP64 sum in a fixed order (wave butterfly, then waves 0..3).
+__device__ __forceinline__ double block_sum_f64(double v, double *red) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) t = ((red[0] + red[1]) + red[2]) + red[3];
+  __syncthreads();
+  return t;
+}
+
+// Largest d with prefix[d] <= item (the step a work-queue item belongs to).
+__device__ __forceinline__ int find_desc(const int64_t *prefix, int n, int64_t item) {
+  int lo = 0, hi = n - 1;   // largest d with prefix[d] <= item
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+}  // namespace cqc

@@ -50,7 +50,22 @@ struct ContractArgs {
   DigitMapDev mx, my;
   BitPos posX, posY;  // deposit mode: column bit -> output bit position
   double *partials;  // [nblocks] per-block FP64 sums of the written outputs, or null
+  // wide kernel only: live-label lists of every batch entry (written by the
+  // label-list pass of the same step)
+  int32_t *lists;    // [nbatch][list_ld] (byte offset of the X row, of the Y row) pairs,
+                     //   ascending s; padding (0, 0)
+  int32_t *counts;   // [nbatch] live labels
+  int32_t list_ld;   // pairs per batch entry: 4^nS rounded up to a multiple of 32
+  int64_t nbatch;
 };
+
+// Workspace of the label lists of a step run by the wide kernel.
+// Operands of the wide kernel are addressed with 32-bit byte offsets.
+constexpr int64_t kWideMaxOperandElems = int64_t(1) << 30;
+inline int32_t wide_list_ld(int nS) { return (int32_t)((((int64_t)1 << (2 * nS)) + 31) / 32 * 32); }
+inline size_t wide_list_bytes(int nS, int64_t nbatch) {
+  return (size_t)nbatch * (size_t)wide_list_ld(nS) * 8 + (size_t)nbatch * 4;
+}
 
 // Row flags are kept per (row, chunk of kFlagChunk columns): flag[r * nch + c]
 // says whether chunk c of row r has a non-zero element; a row is live if any
@@ -75,13 +90,21 @@ struct FlagArgs {
   int32_t is_double;
 };
 
-enum class Acc { F32, F64 };
+// Arithmetic of a plan.  BF16X6 keeps every tensor in FP32 and splits the
+// operands into three bfloat16 parts inside the wide kernel.
+enum class Acc { F32, F64, BF16X6 };
 
-// Tile configurations of the contraction kernel.
-enum TileCfg : int32_t { kTileL = 0, kTileM = 1, kTileS = 2, kTileT = 3, kTileCount = 4 };
+// Tile configurations of the contraction kernels: L, M, S, T select the
+// register-operand kernel (FP32 and FP64), W the LDS-staged wide kernel
+// (FP32 and BF16X6; the only one BF16X6 runs on).
+enum TileCfg : int32_t { kTileL = 0, kTileM = 1, kTileS = 2, kTileT = 3, kTileW = 4, kTileCount = 5 };
 struct TileShape { int bm, bn; };
 TileShape tile_shape(int cfg);
-int choose_tile(int logM, int logN);
+// Built-in rule (the autotuner's cache takes precedence where it has an entry).
+// wide_ok: both operands fit the wide kernel's addressing (wide_fits).
+int choose_tile(Acc acc, int nS, int logM, int logN, bool wide_ok);
+// Whether the arithmetic has a kernel with this tile configuration.
+bool tile_ok(Acc acc, int cfg);
 
 Status launch_row_flags(const FlagArgs &a, int64_t total_blocks, hipStream_t s);
 Status launch_mass_final(const double *partials, int64_t count, double *mass, hipStream_t s);
@@ -96,6 +119,8 @@ struct QueueLaunch {
   unsigned long long *queue;
   int64_t total;
   uint32_t grid;
+  const int64_t *bprefix;  // wide kernel: bprefix[d] = first batch entry of step d over the table
+  int64_t btotal;          //   and the total (one label-list block per batch entry)
 };
 Status launch_contract_queue(Acc acc, int mode, int cfg, bool small, const QueueLaunch &q, hipStream_t s);
 
@@ -110,6 +135,10 @@ Status launch_row_flags_table(const FlagDesc *descs, int32_t n, int64_t total_bl
                               unsigned long long *counters, int32_t n_counters, hipStream_t s);
 Status launch_mass_table(const MassDesc *descs, int32_t n, hipStream_t s);
 Status launch_contract(Acc acc, bool out_double, int cfg, const ContractArgs &a, hipStream_t s);
+Status launch_contract_wide(bool split, bool out_double, const ContractArgs &a, hipStream_t s);
+// Whether both operands of a step are within the wide kernel's 2^30-element addressing.
+bool wide_fits(const ContractArgs &a);
+Status launch_contract_wide_queue(bool split, int mode, const QueueLaunch &q, hipStream_t s);
 Status launch_convert(const void *src, bool src_double, void *dst, bool dst_double,
                       int64_t count, hipStream_t s);
 Status launch_selftest_mfma(void *out, hipStream_t s);

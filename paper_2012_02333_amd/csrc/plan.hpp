@@ -51,6 +51,10 @@ struct Step {
   DigitMap mx, my;
   int logM = 0, logN = 0;      // column bits of X and Y
   int64_t nbatch = 1;          // 4^(|RX|+|RY|)
+  // both operands hold at most 2^30 elements (the wide kernel's addressing)
+  bool wide_ok() const {
+    return 2 * (S.size() + RX.size()) + logM <= 30 && 2 * (S.size() + RY.size()) + logN <= 30;
+  }
 };
 
 // A plan over "output bits": for FD the bits are global qubits with output

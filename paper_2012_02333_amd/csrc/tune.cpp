@@ -5,7 +5,8 @@
 // cqc_autotune times every candidate tile shape and block-to-XCD mapping of
 // each class the given instances need, on the device, and records the
 // fastest; the planner consults the cache before its built-in rule.  The cache
-// can persist in a text file named by CQC_TUNE_CACHE (one class per line).
+// can persist in a text file named by CQC_TUNE_CACHE (one class per line);
+// with CQC_TUNE_VERBOSE set, every candidate's time is printed to stderr.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -117,6 +118,7 @@ static Status tune_step(const NetLayout &L, size_t si, char *ws, const std::vect
   a.nRY = (int)st.RY.size();
   a.mx = to_dev(st.mx);
   a.my = to_dev(st.my);
+  set_lists(L, si, ws, &a);
   bool od = L.acc == Acc::F64;
   if (!last) {
     a.mode = kModeIntermediate;
@@ -144,10 +146,12 @@ static Status tune_step(const NetLayout &L, size_t si, char *ws, const std::vect
   CQC_HIP_TRY(hipEventCreate(&e1));
   Choice best{-1, 0, 1e30};
   for (int cfg = 0; cfg < kTileCount; ++cfg) {
+    if (!tile_ok(L.acc, cfg)) continue;
     const TileShape sh = tile_shape(cfg);
     const int64_t M = int64_t(1) << st.logM, N = int64_t(1) << st.logN;
     // skip shapes that would leave most of every tile empty
-    if ((M < sh.bm && cfg != kTileS) || (N < sh.bn && cfg != kTileS)) continue;
+    if ((M < sh.bm || N < sh.bn) && cfg != kTileS && cfg != choose_tile(L.acc, a.nS, st.logM, st.logN, st.wide_ok())) continue;
+    if (cfg == kTileW && !st.wide_ok()) continue;
     for (int xcd = 0; xcd < 2; ++xcd) {
       a.tilesM = (int)((M + sh.bm - 1) / sh.bm);
       a.tilesN = (int)((N + sh.bn - 1) / sh.bn);
@@ -162,6 +166,9 @@ static Status tune_step(const NetLayout &L, size_t si, char *ws, const std::vect
       float ms = 0.f;
       CQC_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
       const double us = 1000.0 * ms / reps;
+      if (std::getenv("CQC_TUNE_VERBOSE"))
+        std::fprintf(stderr, "cqc_autotune step %zu acc %d mode %d logM %d logN %d nS %d batches %lld: tile %d xcd %d %.2f us\n",
+                     si, (int)L.acc, a.mode, st.logM, st.logN, a.nS, (long long)st.nbatch, cfg, xcd, us);
       if (us < best.us) best = Choice{cfg, xcd, us};
     }
   }

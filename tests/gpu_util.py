@@ -31,3 +31,10 @@ def elementwise_ok(p, ref, T, unit, terms):
     err = np.abs(np.asarray(p, dtype=np.float64) - ref)
     bad = np.nonzero(err > tol)[0]
     return bad.size == 0, (bad[:5], err[bad[:5]] if bad.size else None, tol[bad[:5]] if bad.size else None)
+
+
+def sum_terms(prec, t):
+    """Roundings an output of t terms goes through: the BF16X6 form adds six
+    partial products per term, and its three-part split drops products below
+    4 u |a b| per term (one more u-multiple of T_x)."""
+    return 6 * t + 1 if prec == "bf16x6" else t

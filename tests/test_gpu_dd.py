@@ -59,7 +59,8 @@ def _check_heaviest(bins, recs):
         expanded.add(best)
 
 
-@pytest.mark.parametrize("prec,dtype,tol", [("fp64", torch.float64, 1e-12), ("fp32", torch.float32, 1e-6)])
+@pytest.mark.parametrize("prec,dtype,tol", [("fp64", torch.float64, 1e-12), ("fp32", torch.float32, 1e-6),
+                                            ("bf16x6", torch.float32, 1e-6)])
 @pytest.mark.parametrize("shape,a,R", [(((4, 3), (1,), 4), 3, 4), (((3, 2, 3), (2, 2), 6), 4, 6),
                                        (((4, 4, 4), (1, 2), 4), 5, 5), (((3, 3), (2,), 4), 2, 12)])
 def test_dd_matches_oracle(shape, a, R, prec, dtype, tol):

@@ -1,9 +1,10 @@
 """GPU parity of the full-definition path against the FP64 oracle.
 
-Tolerances: relative L1 <= 1e-6 for the FP32 forms (the target accuracy),
-<= 1e-12 for the FP64 form; in addition every element must lie within the
-rounding bound 4 (t + 2) u T_x of any summation order of the t terms it adds,
-with T_x = 2^-K sum_l prod_c |E_c| computed by the oracle.
+Tolerances: relative L1 <= 1e-6 for the FP32 and BF16X6 forms (the target
+accuracy), <= 1e-12 for the FP64 form; in addition every element must lie
+within the rounding bound 4 (t + 2) u T_x of any summation order of the t terms
+it adds (t counts the six partial products per term of the BF16X6 form), with
+T_x = 2^-K sum_l prod_c |E_c| computed by the oracle.
 """
 import numpy as np
 import pytest
@@ -11,7 +12,7 @@ import torch
 
 import workloads as W
 from oracle import fd, metrics
-from tests.gpu_util import to_dev, oracle_inputs, abs_bound, elementwise_ok, U32, U64
+from tests.gpu_util import to_dev, oracle_inputs, abs_bound, elementwise_ok, sum_terms, U32, U64
 
 pytestmark = pytest.mark.gpu
 
@@ -25,12 +26,15 @@ def _gpu():
 
 def test_mfma_lane_layout():
     _gpu()
-    f, d = cqc.selftest_mfma()
+    f, d, b = cqc.selftest_mfma()
     i = np.arange(16)[:, None]
     j = np.arange(16)[None, :]
     ref = sum((i + 16 * k) * (1 + k + 4 * j) for k in range(4)).astype(np.float64)
     assert np.array_equal(f.numpy().astype(np.float64), ref)
     assert np.array_equal(d.numpy(), ref)
+    A = (np.arange(16)[:, None] + 3 * np.arange(32)[None, :]) % 7 - 3
+    B = (2 * np.arange(32)[:, None] + np.arange(16)[None, :]) % 5 - 2
+    assert np.array_equal(b.numpy().astype(np.float64), (A @ B).astype(np.float64))
 
 
 def _run(entries_np, wcut, dtype, prec, out_dtype=None):
@@ -48,7 +52,8 @@ def _inner_terms(wcut):
 
 
 @pytest.mark.parametrize("prec,dtype,tol,unit", [("fp64", torch.float64, 1e-12, U64),
-                                                 ("fp32", torch.float32, 1e-6, U32)])
+                                                 ("fp32", torch.float32, 1e-6, U32),
+                                                 ("bf16x6", torch.float32, 1e-6, U32)])
 @pytest.mark.parametrize("shape", [((4, 3), (1,), 4), ((5, 5), (2,), 6), ((3, 2, 3), (3, 3), 4),
                                    ((3, 3, 3), (2, 2), 6), ((2, 3, 3, 2), (1, 2, 2), 4),
                                    ((6, 6), (3,), 6), ((7, 7), (2,), 4)])
@@ -62,12 +67,13 @@ def test_fd_simulated_circuits(shape, prec, dtype, tol, unit):
     err = metrics.rel_l1(p, ref)
     print(f"{shape} {prec}: rel_l1={err:.3e}")
     assert err <= tol
-    ok, info = elementwise_ok(p, ref, abs_bound(e64, inst.cut), unit, _inner_terms(inst.cut))
+    ok, info = elementwise_ok(p, ref, abs_bound(e64, inst.cut), unit, sum_terms(prec, _inner_terms(inst.cut)))
     assert ok, info
     assert abs(mass - ref.sum()) <= 1e-6 * np.abs(ref).sum()
 
 
-@pytest.mark.parametrize("prec,dtype,unit", [("fp64", torch.float64, U64), ("fp32", torch.float32, U32)])
+@pytest.mark.parametrize("prec,dtype,unit", [("fp64", torch.float64, U64), ("fp32", torch.float32, U32),
+                                             ("bf16x6", torch.float32, U32)])
 @pytest.mark.parametrize("case", ["perm", "kron2", "kron3", "single", "triangle", "ragged",
                                   "zero_rows", "k0_f0"])
 def test_fd_random_structures(case, prec, dtype, unit):
@@ -96,7 +102,7 @@ def test_fd_random_structures(case, prec, dtype, unit):
     e64 = oracle_inputs(host)
     ref = fd.reconstruct(e64, cut)
     T = abs_bound(e64, cut)
-    ok, info = elementwise_ok(p, ref, T, unit, 4 ** cut.n_cuts)
+    ok, info = elementwise_ok(p, ref, T, unit, sum_terms(prec, 4 ** cut.n_cuts))
     assert ok, (case, info)
     tol = 1e-12 if prec == "fp64" else 1e-6
     assert metrics.rel_l1(p, ref) <= tol * metrics.kappa(e64, cut, np.abs(ref).sum())
@@ -111,7 +117,8 @@ def test_fd_c1_plain_fp64():
     assert abs(mass - 1.0) <= 1e-13
 
 
-@pytest.mark.parametrize("prec,dtype,tol", [("fp32", torch.float32, 1e-6), ("fp64", torch.float64, 1e-12)])
+@pytest.mark.parametrize("prec,dtype,tol", [("fp32", torch.float32, 1e-6), ("fp64", torch.float64, 1e-12),
+                                            ("bf16x6", torch.float32, 1e-6)])
 def test_fd_c2_full_vector(prec, dtype, tol):
     """n=24, K=2, two 13-qubit subcircuits: the headline shape, all 2^24 outputs."""
     _gpu()
@@ -124,28 +131,33 @@ def test_fd_c2_full_vector(prec, dtype, tol):
     print(f"c2 {prec}: rel_l1={err:.3e} mass={mass!r}")
     assert err <= tol
     T = native.reconstruct([np.abs(E) for E in e64], inst.cut)
-    ok, info = elementwise_ok(p, ref, T, U32 if prec == "fp32" else U64, 16)
+    ok, info = elementwise_ok(p, ref, T, U64 if prec == "fp64" else U32, sum_terms(prec, 16))
     assert ok, info
-    assert abs(mass - ref.sum()) <= 1e-9
+    # the mass is the FP64 sum of the written outputs
+    assert abs(mass - p.sum()) <= 1e-12 * np.abs(p).sum()
+    # FP32/FP64 roundings are unbiased and cancel in the sum; the BF16 matrix
+    # cores' are not, so there only the L1 bound holds
+    assert abs(mass - ref.sum()) <= (tol * np.abs(ref).sum() if prec == "bf16x6" else 1e-9)
 
 
-def test_fd_c3_sampled():
+@pytest.mark.parametrize("prec", ["fp32", "bf16x6"])
+def test_fd_c3_sampled(prec):
     """n=30, K=6, three subcircuits (2^30 outputs): sampled outputs against the
     oracle's per-output definition, plus the FP64 mass."""
     _gpu()
     inst = W.config_instance("c3")
     host, dev = to_dev(inst.entries, torch.float32)
     cut = cqc.CutMap.from_workload(inst.cut)
-    p, mass = cqc.reconstruct_fd(dev, cut, precision="fp32")
+    p, mass = cqc.reconstruct_fd(dev, cut, precision=prec)
     xs = W.sample_outputs(inst.n, 4096, seed=33)
     got = p[torch.from_numpy(xs).to("cuda")].cpu().numpy().astype(np.float64)
     e64 = oracle_inputs(host)
     ref = fd.reconstruct(e64, inst.cut, xs)
     err = metrics.rel_l1(got, ref)
-    print(f"c3 sampled rel_l1={err:.3e} mass={float(mass.cpu())!r}")
+    print(f"c3 {prec} sampled rel_l1={err:.3e} mass={float(mass.cpu())!r}")
     assert err <= 1e-6
     assert abs(float(mass.cpu()) - 1.0) <= 1e-5
-    ok, info = elementwise_ok(got, ref, abs_bound(e64, inst.cut, xs), U32, 64 + 64)
+    ok, info = elementwise_ok(got, ref, abs_bound(e64, inst.cut, xs), U32, sum_terms(prec, 64 + 64))
     assert ok, info
     del p
 
