@@ -1,19 +1,25 @@
-"""Throughput benchmark of the FD reconstruction hot path on one MI355X.
+"""Throughput benchmark of the cut-circuit reconstruction hot path on one MI355X.
 
-Default workload: n=24 seeded random U3+CZ circuit (depth 8) cut by K=2 wires
-into two 13-qubit subcircuits; entry tensors 16 x 2^11 and 16 x 2^13 from
-noiseless simulation; 2^24 output probabilities.  A step is one complete
-library call: entry row flags (early termination), the term sum on matrix
-cores, the single write of every output and the FP64 total mass.  The FP32
-form (metric) and the plain FP64 form run on the same inputs; output buffers
-rotate over >= 1 GiB so the 256 MB last-level cache cannot hold the writes.
+Default workload (the headline metric): n=24 seeded random U3+CZ circuit
+(depth 8) cut by K=2 wires into two 13-qubit subcircuits; entry tensors
+16 x 2^11 and 16 x 2^13 from noiseless simulation; 2^24 output probabilities.
+A step is one complete library call: entry row flags (early termination), the
+term sum on matrix cores, the single write of every output and the FP64 total
+mass.  The FP32 form (metric) and the plain FP64 form run on the same inputs;
+output buffers rotate over >= 1 GiB so the 256 MB last-level cache cannot hold
+the writes.
 
-Prints ONE JSON line.  `--config c3|c4|c5` measures the other workloads
-(extra lines, not the headline).
+Prints ONE JSON line.  `--config` selects another workload of the same family
+(its own line, same fields):
+  c3  FD fused chain, n=30, K=6, three 12-qubit subcircuits (FP32, BF16X6, FP64)
+  c4  DD, n=40, K=8, 2^20 bins per recursion, 5 recursions (FP32, FP64 bins)
+  c5  256 instances (n 12..24, K 1..4) forward + cross-entropy adjoint, one
+      graph-captured step
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -28,27 +34,36 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFS = 157.3
 METRIC = "FD reconstructed probs/s n=24,K=2: MFMA-FP32 vs plain FP64 at 1e-6 rel err"
 
+WORKLOAD = {
+    "c2": "FD n=24 K=2, two 13-qubit subcircuits, E 16x2^11 and 16x2^13",
+    "c3": "FD n=30 K=6, three 12-qubit subcircuits (fused chain), 4096 terms",
+    "c4": "DD n=40 K=8, four 12-qubit subcircuits, 2^20 bins per recursion, 5 recursions",
+    "c5": "256 FD instances n~U{12..24} K~U{1..4} 2-3 subcircuits: forward + cross-entropy adjoint",
+}
+
+# kernel sources whose change invalidates a committed HBM-counter record
+TRAFFIC_SOURCES = {
+    "c2": ["paper_2012_02333_amd/csrc/k_contract.hip", "paper_2012_02333_amd/csrc/kernels.hpp"],
+    "c3": ["paper_2012_02333_amd/csrc/k_wide.hip", "paper_2012_02333_amd/csrc/kernels.hpp"],
+}
+
 
 def _args():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="c2", choices=["c2", "c3"])
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default per config)")
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--calibrate", action="store_true",
-                    help="first run a plain 256 MiB device copy 10 times (reference for HBM counters)")
+                    help="first run kernels of known HBM traffic (reference for the counters)")
     return ap.parse_args()
 
 
-TRAFFIC_KERNEL_SOURCES = ["paper_2012_02333_amd/csrc/k_contract.hip", "paper_2012_02333_amd/csrc/kernels.hpp"]
-
-
-def kernel_source_hash():
-    import hashlib
+def kernel_source_hash(config):
     h = hashlib.sha256()
-    for rel in TRAFFIC_KERNEL_SOURCES:
+    for rel in TRAFFIC_SOURCES.get(config, []):
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -62,57 +77,311 @@ def recorded_traffic(config, kernel):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("source_sha") != kernel_source_hash() or rec.get("kernel") != kernel:
+    if rec.get("source_sha") != kernel_source_hash(config) or rec.get("kernel") != kernel:
         return None
     return rec.get("hbm_bytes_per_launch")
 
 
-def _time_steps(call, outs, steps, warmup, torch):
-    """Warm up, then time exactly `steps` calls, rotating output buffers."""
-    nb = len(outs)
+def _sync_time(fn, steps, warmup, torch):
+    """Warm up, then time exactly `steps` calls of fn(i) between synchronised events."""
     for i in range(warmup):
-        call.set_outputs([outs[i % nb]])
-        call.run()
+        fn(i)
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     t0.record()
     for i in range(steps):
-        call.set_outputs([outs[i % nb]])
-        call.run()
+        fn(i)
     t1.record()
     torch.cuda.synchronize()
     return t0.elapsed_time(t1) / steps
 
 
-def _kernel_time(call, outs, steps, cqc, torch):
-    """Per-kernel average duration from HIP events bracketing every launch."""
-    nb = len(outs)
+def _traced(fn, steps, cqc, torch):
+    """Per-kernel (launches, summed ms) from HIP events around every launch."""
     with cqc.trace() as tr:
         for i in range(steps):
-            call.set_outputs([outs[i % nb]])
-            call.run()
+            fn(i)
         torch.cuda.synchronize()
     return tr.result
 
 
-def _cpu_baseline(inst, e64, seconds):
-    """The oracle's C twin (plain per-output FP64 definition) on the host cores."""
-    from oracle import native, metrics  # noqa: F401  (CPU-baseline leg only)
-    n = inst.n
-    threads = native.max_threads()
-    p = native.reconstruct(e64, inst.cut)          # full vector once (also the parity reference)
+def _roof(bound, achieved, peak, unit, kernel, avg_ms, traffic):
+    return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
+            "traffic": traffic, "kernel": kernel, "kernel_avg_us": avg_ms * 1e3}
+
+
+def _line(cfg, metric, value, unit, steps, warmup, ms, dtype, config, roofline, higher=True, **extra):
+    out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
+           "ms_per_step": ms, "higher_is_better": higher, "scaling": "weak", "vs_baseline": None,
+           "dtype": dtype, "data": "synthetic", "config": dict(workload=WORKLOAD[cfg], **config),
+           "roofline": roofline}
+    out.update(extra)
+    return out
+
+
+def _cpu_rate(run_sample, unit_count, seconds, sample0):
+    """Time the oracle on growing samples until one takes >= seconds / 4, then
+    repeat it to about `seconds`; returns (rate, sample size, reps, elapsed)."""
+    size = sample0
+    while True:
+        t0 = time.perf_counter()
+        run_sample(size)
+        el = time.perf_counter() - t0
+        if el >= seconds / 4 or size >= unit_count:
+            break
+        size = min(unit_count, size * max(2, int(seconds / 4 / max(el, 1e-3))))
     reps, t0 = 0, time.perf_counter()
     while True:
-        native.reconstruct(e64, inst.cut)
+        run_sample(size)
         reps += 1
         el = time.perf_counter() - t0
-        if el >= seconds or reps >= 50:
+        if el >= seconds or reps >= 100000:
             break
-    rate = reps * (2 ** n) / el
-    return p, {"value": rate, "unit": "probs/s", "cores": threads, "kind": "oracle",
-               "sample": f"full 2^{n} vector x {reps} repetitions ({el:.1f} s), C/OpenMP FP64 "
-                         f"per-output definition"}
+    return reps * size / el, size, reps, el
+
+
+# ---------------------------------------------------------------------------
+def bench_fd(args, cfg, torch, cqc, W):
+    """c2 (headline) and c3: full-definition reconstruction of one instance."""
+    inst = W.config_instance(cfg)
+    n, K = inst.n, inst.K
+    cut = cqc.CutMap.from_workload(inst.cut)
+    e32_np = [E.astype(np.float32) for E in inst.entries]
+    e32 = [torch.from_numpy(E).cuda() for E in e32_np]
+    e64 = [torch.from_numpy(E).cuda() for E in inst.entries]
+    N = 2 ** n
+    steps = args.steps or (200 if cfg == "c2" else 10)
+    warmup = args.warmup if args.warmup is not None else (20 if cfg == "c2" else 3)
+
+    def measure(prec, ents, dt):
+        esz = 8 if dt == torch.float64 else 4
+        nbuf = max(2, min(16, (1 << 30) // (esz * N)))
+        outs = [torch.empty(N, dtype=dt, device="cuda") for _ in range(nbuf)]
+        call = cqc.FDCall(ents, cut, precision=prec, outs=[outs[0]])
+
+        def step(i):
+            call.set_outputs([outs[i % nbuf]])
+            call.run()
+        ms = _sync_time(step, steps, warmup, torch)
+        kt = _traced(step, steps, cqc, torch)
+        last = outs[(steps - 1) % nbuf]
+        sample = None
+        if n <= 26:
+            sample = last.double().cpu().numpy()
+        else:
+            xs = W.sample_outputs(n, 1 << 14, seed=7)
+            sample = (xs, last[torch.from_numpy(xs).cuda()].double().cpu().numpy())
+        res = {"value": N / (ms * 1e-3), "ms_per_step": ms, "kernels_ms": kt,
+               "mass": float(call.mass[0].cpu()), "output_buffers_rotated": nbuf}
+        del outs, call
+        torch.cuda.empty_cache()
+        return res, sample
+
+    r32, s32 = measure("fp32", e32, torch.float32)
+    rbf, sbf = measure("bf16x6", e32, torch.float32)
+    r64, s64 = measure("fp64", e64, torch.float64)
+
+    def dominant(kt, prefix=None):
+        items = [(k, v) for k, v in kt.items() if prefix is None or k.startswith(prefix)]
+        name, (cnt, tot) = max(items, key=lambda kv: kv[1][1])
+        return name, tot / cnt
+
+    in_bytes = sum(E.numel() * 4 for E in e32)
+    if cfg == "c2":
+        name, avg = dominant(r32["kernels_ms"])
+        roof = _roof("hbm", (4 * N + in_bytes) / (avg * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", name, avg,
+                     recorded_traffic(cfg, name))
+        name_b, avg_b = dominant(rbf["kernels_ms"])
+        roof_bf = _roof("hbm", (4 * N + in_bytes) / (avg_b * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", name_b, avg_b, None)
+    else:
+        # final contraction: 2 * (live terms) * 2^n flops; output written once
+        name, avg = dominant(r32["kernels_ms"], "wide_f32_final")
+        _, macs = cqc.cost(cut)
+        flops_final = 2.0 * 64 * N   # 4^3 shared labels of the last contraction x 2^30 outputs
+        roof = _roof("mfma", flops_final / (avg * 1e-3) / 1e12, FP32_PEAK_TFS, "TFLOP/s", name, avg,
+                     recorded_traffic(cfg, name))
+        roof["flops_per_launch"] = flops_final
+        roof["plan_flops_per_step"] = 2.0 * macs
+        name_b, avg_b = dominant(rbf["kernels_ms"], "wide_bf16x6_final")
+        roof_bf = _roof("hbm", (4 * N) / (avg_b * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", name_b, avg_b, None)
+
+    metric = METRIC if cfg == "c2" else "FD reconstructed probs/s n=30,K=6 fused chain: MFMA-FP32 at 1e-6 rel err"
+    out = _line(cfg, metric, r32["value"], "probs/s", steps, warmup, r32["ms_per_step"], "f32",
+                {"n": n, "K": K, "precision": "fp32", "seed": W.RECIPES[cfg]["seed"],
+                 "output_buffers_rotated": r32["output_buffers_rotated"]},
+                roof, mass=r32["mass"], kernels_ms=r32["kernels_ms"],
+                fp64_plain={k: r64[k] for k in ("value", "ms_per_step", "kernels_ms", "mass")},
+                bf16x6={**{k: rbf[k] for k in ("value", "ms_per_step", "kernels_ms", "mass")}, "roofline": roof_bf})
+    out["speedup_fp32_vs_fp64"] = r32["value"] / r64["value"]
+    out["speedup_bf16x6_vs_fp64"] = rbf["value"] / r64["value"]
+
+    if not args.no_cpu:
+        from oracle import native, metrics  # CPU-baseline leg only
+        e64_np = [E.astype(np.float64) for E in e32_np]
+        threads = native.max_threads()
+        if n <= 26:
+            ref = native.reconstruct(e64_np, inst.cut)
+            out["err_rel_l1_fp32"] = metrics.rel_l1(s32, ref)
+            out["err_rel_l1_bf16x6"] = metrics.rel_l1(sbf, ref)
+            out["fp64_plain"]["err_rel_l1"] = metrics.rel_l1(s64, native.reconstruct(inst.entries, inst.cut))
+            reps, t0 = 0, time.perf_counter()
+            while True:
+                native.reconstruct(e64_np, inst.cut)
+                reps += 1
+                el = time.perf_counter() - t0
+                if el >= args.cpu_seconds or reps >= 100000:
+                    break
+            out["cpu_baseline"] = {"value": reps * N / el, "unit": "probs/s", "cores": threads, "kind": "oracle",
+                                   "sample": f"full 2^{n} vector x {reps} repetitions ({el:.1f} s), C/OpenMP "
+                                             f"FP64 per-output definition"}
+        else:
+            xs, g32 = s32
+            ref = native.reconstruct(e64_np, inst.cut, xs)
+            out["err_rel_l1_fp32_sampled"] = metrics.rel_l1(g32, ref)
+            out["err_rel_l1_bf16x6_sampled"] = metrics.rel_l1(sbf[1], ref)
+            out["fp64_plain"]["err_rel_l1_sampled"] = metrics.rel_l1(
+                s64[1], native.reconstruct(inst.entries, inst.cut, xs))
+            rng = np.random.default_rng(11)
+            rate, size, reps, el = _cpu_rate(
+                lambda m: native.reconstruct(e64_np, inst.cut, np.sort(rng.integers(0, N, m))),
+                N, args.cpu_seconds, 4096)
+            out["cpu_baseline"] = {"value": rate, "unit": "probs/s", "cores": threads, "kind": "oracle",
+                                   "sample": f"{size} seeded random outputs x {reps} repetitions ({el:.1f} s), "
+                                             f"C/OpenMP FP64 per-output definition (4096 terms each)"}
+    return out
+
+
+# ---------------------------------------------------------------------------
+def bench_dd(args, torch, cqc, W):
+    """c4: dynamic definition, 5 recursions of 2^20 bins on an n=40 instance."""
+    inst = W.config_instance("c4")
+    cut = cqc.CutMap.from_workload(inst.cut)
+    a, R = W.DD_C4["n_active"], W.DD_C4["n_recursions"]
+    e32_np = [E.astype(np.float32) for E in inst.entries]
+    e32 = [torch.from_numpy(E).cuda() for E in e32_np]
+    steps = args.steps or 10
+    warmup = args.warmup if args.warmup is not None else 2
+    holder = {}
+
+    def step(i):
+        holder["r"] = cqc.reconstruct_dd(e32, cut, a, R, precision="fp32")
+    ms = _sync_time(step, steps, warmup, torch)
+    kt = _traced(step, steps, cqc, torch)
+    bins, recs = holder["r"]
+    nrec = len(recs)
+    per_call = {k: (v[0] / steps, v[1] / steps) for k, v in kt.items()}
+    name, (cnt, tot) = max(per_call.items(), key=lambda kv: kv[1][1])
+    avg = tot / cnt
+    # the dominant kernel's algorithmic bytes: the last contraction writes the
+    # 2^a FP64 bins and reads both merged operands once
+    alg = 8 * 2 ** a
+    roof = _roof("hbm", alg / (avg * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", name, avg, None)
+    roof["note"] = "latency-bound: about 2 us of roofline work per recursion"
+    bins_total = nrec * 2 ** a
+    out = _line("c4", "DD reconstructed bins/s n=40,K=8 (2^20 bins x 5 recursions, FP32 term sum, FP64 bins)",
+                bins_total / (ms * 1e-3), "bins/s", steps, warmup, ms, "f32",
+                {"n": inst.n, "K": inst.K, "n_active": a, "recursions": nrec, "precision": "fp32",
+                 "seed": W.RECIPES["c4"]["seed"]},
+                roof, us_per_recursion=1e3 * ms / nrec, kernels_ms_per_call=per_call,
+                records=[{"parent": r["parent"], "mass": r["mass"]} for r in recs])
+    if not args.no_cpu:
+        from oracle import dd, native  # CPU-baseline leg only
+        e64_np = [E.astype(np.float64) for E in e32_np]
+        role = [dd.ACTIVE if q < a else dd.MERGED for q in range(inst.n)]
+        t0 = time.perf_counter()
+        merged = dd.merge_entries(e64_np, inst.cut, role)
+        t_merge = time.perf_counter() - t0
+        g = bins[0].cpu().numpy()
+        rng = np.random.default_rng(12)
+        probe = np.sort(rng.choice(2 ** a, 256, replace=False))
+        ref = dd.bins_from_merged(merged, inst.cut, role, probe)
+        out["err_rel_l1_recursion1_sampled"] = float(np.abs(g[probe] - ref).sum() / np.abs(ref).sum())
+        rate, size, reps, el = _cpu_rate(
+            lambda m: dd.bins_from_merged(merged, inst.cut, role, np.sort(rng.choice(2 ** a, m, replace=False))),
+            2 ** a, args.cpu_seconds, 64)
+        out["cpu_baseline"] = {"value": rate, "unit": "bins/s", "cores": 1, "kind": "oracle",
+                               "sample": f"recursion 1: merge ({t_merge:.2f} s, not in the rate) then {size} "
+                                         f"seeded bins x {reps} repetitions ({el:.1f} s), numpy FP64 "
+                                         f"definition over 4^8 terms"}
+    return out
+
+
+# ---------------------------------------------------------------------------
+def bench_batch(args, torch, cqc, W):
+    """c5: 256 instances, forward + cross-entropy gradient + adjoint, one graph."""
+    insts = W.batch_instances(256)
+    cuts = [cqc.CutMap.from_workload(i.cut) for i in insts]
+    e32_np = [[E.astype(np.float32) for E in i.entries] for i in insts]
+    ents = [[torch.from_numpy(E).cuda() for E in e] for e in e32_np]
+    targets = [torch.from_numpy(W.dirichlet_target(i.n, 1000 + k).astype(np.float32)).cuda()
+               for k, i in enumerate(insts)]
+    batch = cqc.Batch(ents, cuts, precision="fp32")
+    grads_out = [torch.empty_like(t) for t in targets]
+    bwd = cqc.BackwardCall(ents, cuts, grads_out, precision="fp32")
+    floor = torch.tensor(1e-30, dtype=torch.float32, device="cuda")
+
+    def body():
+        batch.run()
+        for p, t, g in zip(batch.outs, targets, grads_out):
+            torch.div(t, torch.maximum(p, floor), out=g)
+            g.neg_()
+        bwd.run()
+    steps = args.steps or 20
+    warmup = args.warmup if args.warmup is not None else 3
+    body()
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        body()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=s):
+            body()
+    torch.cuda.synchronize()
+    ms = _sync_time(lambda i: graph.replay(), steps, warmup, torch)
+    kt = _traced(lambda i: body(), 3, cqc, torch)
+    outputs = sum(2 ** i.n for i in insts)
+    # roofline of the step: per instance the larger of its HBM time (write p,
+    # read p, t and G for the adjoint) and its FP32 matrix-core time
+    roof_s = 0.0
+    for c, i in zip(cuts, insts):
+        _, macs = cqc.cost(c)
+        byts = 4.0 * 2 ** i.n * 5
+        roof_s += max(byts / (HBM_PEAK_GBS * 1e9), 3 * 2 * macs / (FP32_PEAK_TFS * 1e12))
+    name, (cnt, tot) = max(kt.items(), key=lambda kv: kv[1][1])
+    roof = {"bound": "mixed", "achieved": roof_s * 1e3, "peak": ms, "unit": "ms per step (roofline vs measured)",
+            "frac": roof_s * 1e3 / ms, "traffic": None, "dominant_kernel": name,
+            "dominant_kernel_ms_per_step": tot / 3,
+            "note": "per instance max(HBM bytes / 8 TB/s, 3 x forward flops / 157.3 TF)"}
+    out = _line("c5", "batched FD forward + adjoint outputs/s (256 instances, n 12..24, K 1..4, graph replay)",
+                outputs / (ms * 1e-3), "probs/s", steps, warmup, ms, "f32",
+                {"instances": len(insts), "sum_2^n": outputs, "precision": "fp32", "seed": 5},
+                roof, kernels_ms_per_step={k: v[1] / 3 for k, v in kt.items()})
+    if not args.no_cpu:
+        from oracle import native, metrics  # CPU-baseline leg only
+        threads = native.max_threads()
+        order = sorted(range(len(insts)), key=lambda k: insts[k].n)
+        small = [k for k in order if insts[k].n <= 18][:64]
+        errs = []
+        for k in small[:8]:
+            ref = native.reconstruct([E.astype(np.float64) for E in e32_np[k]], insts[k].cut)
+            errs.append(metrics.rel_l1(batch.outs[k].double().cpu().numpy(), ref))
+        out["err_rel_l1_fp32_max_of_8"] = max(errs)
+        tot_out, reps, t0 = 0, 0, time.perf_counter()
+        while True:
+            for k in small:
+                native.reconstruct([E.astype(np.float64) for E in e32_np[k]], insts[k].cut)
+                tot_out += 2 ** insts[k].n
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= args.cpu_seconds or reps >= 100000:
+                break
+        out["cpu_baseline"] = {"value": tot_out / el, "unit": "probs/s", "cores": threads, "kind": "oracle",
+                               "sample": f"forward only: {len(small)} instances with n <= 18 x {reps} repetitions "
+                                         f"({el:.1f} s), C/OpenMP FP64 per-output definition"}
+    return out
 
 
 def main():
@@ -144,86 +413,12 @@ def main():
             torch.add(b, 1.0, out=c)
         torch.cuda.synchronize()
         del a, b, c
-    inst = W.config_instance(args.config)
-    n, K = inst.n, inst.K
-    cut = cqc.CutMap.from_workload(inst.cut)
-    e32_np = [E.astype(np.float32) for E in inst.entries]
-    e32 = [torch.from_numpy(E).cuda() for E in e32_np]
-    e64 = [torch.from_numpy(E).cuda() for E in inst.entries]
-    N = 2 ** n
-
-    nbuf32 = max(2, min(16, (1 << 30) // (4 * N)))
-    outs32 = [torch.empty(N, dtype=torch.float32, device="cuda") for _ in range(nbuf32)]
-    call32 = cqc.FDCall(e32, cut, precision="fp32", outs=[outs32[0]])
-    ms32 = _time_steps(call32, outs32, args.steps, args.warmup, torch)
-    kt32 = _kernel_time(call32, outs32, args.steps, cqc, torch)
-    p32 = outs32[(args.steps - 1) % nbuf32].double().cpu().numpy() if n <= 26 else None
-    mass32 = float(call32.mass[0].cpu())
-    del outs32, call32
-    torch.cuda.empty_cache()
-
-    fp64 = None
-    if args.config == "c2":
-        nbuf64 = max(2, min(16, (1 << 30) // (8 * N)))
-        outs64 = [torch.empty(N, dtype=torch.float64, device="cuda") for _ in range(nbuf64)]
-        call64 = cqc.FDCall(e64, cut, precision="fp64", outs=[outs64[0]])
-        ms64 = _time_steps(call64, outs64, args.steps, args.warmup, torch)
-        kt64 = _kernel_time(call64, outs64, args.steps, cqc, torch)
-        p64 = outs64[(args.steps - 1) % nbuf64].cpu().numpy()
-        fp64 = {"value": N / (ms64 * 1e-3), "ms_per_step": ms64, "kernels_ms": kt64}
-        del outs64, call64
-
-    # dominant kernel: the last contraction (writes every output once)
-    name, (cnt, tot) = max(kt32.items(), key=lambda kv: kv[1][1])
-    avg_ms = tot / cnt
-    in_bytes = sum(E.numel() * 4 for E in e32)
-    if args.config == "c2":
-        alg_bytes = 4 * N + in_bytes
-        roof = {"bound": "hbm", "achieved": alg_bytes / (avg_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s"}
+    if args.config in ("c2", "c3"):
+        out = bench_fd(args, args.config, torch, cqc, W)
+    elif args.config == "c4":
+        out = bench_dd(args, torch, cqc, W)
     else:
-        _, macs = cqc.cost(cut)
-        roof = {"bound": "mfma", "achieved": 2 * macs / (avg_ms * 1e-3) / 1e12, "peak": FP32_PEAK_TFS,
-                "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    tr = recorded_traffic(args.config, name)
-    roof["traffic"] = tr
-    roof["kernel"] = name
-    roof["kernel_avg_us"] = avg_ms * 1e3
-
-    out = {
-        "metric": METRIC if args.config == "c2" else f"FD reconstructed probs/s ({args.config})",
-        "value": N / (ms32 * 1e-3),
-        "unit": "probs/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms32,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": {"c2": "FD n=24 K=2, two 13-qubit subcircuits, E 16x2^11 and 16x2^13",
-                                "c3": "FD n=30 K=6, three 12-qubit subcircuits, 4096 terms"}[args.config],
-                   "n": n, "K": K, "precision": "fp32", "seed": W.RECIPES[args.config]["seed"],
-                   "output_buffers_rotated": nbuf32},
-        "roofline": roof,
-        "mass": mass32,
-        "kernels_ms": kt32,
-    }
-    if fp64:
-        out["fp64_plain"] = fp64
-        out["speedup_fp32_vs_fp64"] = out["value"] / fp64["value"]
-    if not args.no_cpu and n <= 26:
-        ref, cpu = _cpu_baseline(inst, [E.astype(np.float64) for E in e32_np], args.cpu_seconds)
-        from oracle import metrics
-        out["cpu_baseline"] = cpu
-        out["err_rel_l1_fp32"] = metrics.rel_l1(p32, ref)
-        if fp64:
-            from oracle import native
-            ref64 = native.reconstruct(inst.entries, inst.cut)
-            out["fp64_plain"]["err_rel_l1"] = metrics.rel_l1(p64, ref64)
+        out = bench_batch(args, torch, cqc, W)
     print(json.dumps(out), flush=True)
 
 

@@ -20,7 +20,7 @@ from . import _lib
 from ._lib import CqcError, PREC
 
 __all__ = ["CutMap", "reconstruct_fd", "reconstruct_dd", "reconstruct_backward", "FDCall", "Batch",
-           "ReconstructFD", "cost", "autotune", "trace", "CqcError", "selftest_mfma", "library_path"]
+           "ReconstructFD", "BackwardCall", "cost", "autotune", "trace", "CqcError", "selftest_mfma", "library_path"]
 
 _DT = {torch.float32: _lib.F32, torch.float64: _lib.F64}
 
@@ -242,6 +242,54 @@ def reconstruct_backward(entries, cut, grad_out, precision="fp32"):
                                           gptr, gents_pp, ws.data_ptr(), int(nb.value),
                                           _stream_ptr(dev)))
     return grads
+
+
+class BackwardCall:
+    """A prepared adjoint call over many instances: dL/dE_c of every instance
+    for the given dL/dp buffers.  Workspace and gradient buffers are allocated
+    once; run() enqueues kernels only (graph-capturable)."""
+
+    def __init__(self, entries_list, cuts, grad_outs, precision="fp32"):
+        if isinstance(cuts, CutMap):
+            cuts, entries_list, grad_outs = [cuts], [entries_list], [grad_outs]
+        self.cuts = list(cuts)
+        self.entries_list = [list(e) for e in entries_list]
+        in_dt = _check_entries(self.entries_list[0], self.cuts[0])
+        for e, c, g in zip(self.entries_list, self.cuts, grad_outs):
+            _check_entries(e, c, in_dt)
+            if g.dtype != in_dt or not g.is_contiguous() or g.numel() != 2 ** c.n:
+                raise ValueError("grad_out must be a contiguous [2^n] tensor of the entry dtype")
+        self.grad_outs = list(grad_outs)
+        self.prec = PREC[precision]
+        self.in_t = _DT[in_dt]
+        dev = self.entries_list[0][0].device
+        self.device = dev
+        n = len(self.cuts)
+        self.grads = [[torch.empty_like(E) for E in e] for e in self.entries_list]
+        self._insts = (_lib.CqcInstance * n)()
+        self._keep = []
+        for i, (c, ents) in enumerate(zip(self.cuts, self.entries_list)):
+            ptrs = (ctypes.c_void_p * len(ents))(*[E.data_ptr() for E in ents])
+            self._keep.append(ptrs)
+            self._insts[i] = _lib.CqcInstance(c.c, ptrs, None, None)
+        self._gout = (ctypes.c_void_p * n)(*[g.data_ptr() for g in self.grad_outs])
+        rows = []
+        for gl in self.grads:
+            r = (ctypes.c_void_p * len(gl))(*[g.data_ptr() for g in gl])
+            self._keep.append(r)
+            rows.append(ctypes.cast(r, ctypes.POINTER(ctypes.c_void_p)))
+        self._gents = (ctypes.POINTER(ctypes.c_void_p) * n)(*rows)
+        nb = ctypes.c_size_t(0)
+        _lib.check(_lib.lib().cqc_backward_workspace_size(self._insts, n, self.in_t, self.prec,
+                                                           ctypes.byref(nb)))
+        self.ws_bytes = int(nb.value)
+        self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=dev)   # owned
+
+    def run(self):
+        _lib.check(_lib.lib().cqc_reconstruct_backward(self._insts, len(self.cuts), self.in_t, self.prec,
+                                                        self._gout, self._gents, self.ws.data_ptr(),
+                                                        self.ws_bytes, _stream_ptr(self.device)))
+        return self.grads
 
 
 class ReconstructFD(torch.autograd.Function):

@@ -528,11 +528,12 @@ static Status launch_persistent(const char *nm, K kernel, const ContractArgs &a,
 
 template <bool SPLIT, typename O>
 static Status launch_wide_t(const ContractArgs &a, hipStream_t s) {
-  const char *nm = SPLIT ? "wide_bf16x6_128x128" : "wide_f32_128x128";
+  const char *fin = SPLIT ? "wide_bf16x6_final" : "wide_f32_final";
+  const char *mid = SPLIT ? "wide_bf16x6_inter" : "wide_f32_inter";
   CQC_TRY(launch("label_list", k_label_list, dim3((unsigned)a.nbatch), dim3(256), 0, s, a));
-  if (a.mode == kModeFinalBlocked) return launch_persistent(nm, k_wide<SPLIT, O, kModeFinalBlocked>, a, s);
-  if (a.mode == kModeFinalDeposit) return launch_persistent(nm, k_wide<SPLIT, O, kModeFinalDeposit>, a, s);
-  return launch_persistent(nm, k_wide<SPLIT, float, kModeIntermediate>, a, s);
+  if (a.mode == kModeFinalBlocked) return launch_persistent(fin, k_wide<SPLIT, O, kModeFinalBlocked>, a, s);
+  if (a.mode == kModeFinalDeposit) return launch_persistent(fin, k_wide<SPLIT, O, kModeFinalDeposit>, a, s);
+  return launch_persistent(mid, k_wide<SPLIT, float, kModeIntermediate>, a, s);
 }
 
 Status launch_contract_wide(bool split, bool out_double, const ContractArgs &a, hipStream_t s) {
