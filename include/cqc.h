@@ -26,9 +26,10 @@
  *   - Values are never clamped: negative reconstructed probabilities (possible
  *     with finite-shot entries, Section 3.2.3) are returned as they are.
  *   - Early termination (Section 4.2): a label assignment whose factor row in
- *     some E_c is entirely +0/-0 is skipped.  With finite entries this changes
- *     nothing; with Inf/NaN in another factor the skipped product would have
- *     been NaN.
+ *     some E_c is entirely +0/-0 may be skipped (it is where a step's term sum
+ *     is long enough for the work to matter).  With finite entries this
+ *     changes nothing; with Inf/NaN in another factor the skipped product
+ *     would have been NaN.
  *   - Thread safety: functions are re-entrant; concurrent calls must use
  *     distinct workspaces.
  */

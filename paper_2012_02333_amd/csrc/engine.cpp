@@ -69,6 +69,16 @@ NetLayout layout_net(const Plan &plan, Acc acc, size_t base) {
   return L;
 }
 
+bool needs_flags(const NetLayout &L, bool skip_final) {
+  const Plan &p = L.plan;
+  if (p.single) return true;   // the flag pass also writes the unit operand
+  for (size_t i = 0; i < p.steps.size(); ++i) {
+    if (i + 1 == p.steps.size() && skip_final) break;
+    if (p.steps[i].S.size() > 2 || L.acc == Acc::BF16X6 || L.tile[i] == kTileW) return true;
+  }
+  return false;
+}
+
 void set_lists(const NetLayout &L, size_t step, char *ws, ContractArgs *a) {
   const Step &st = L.plan.steps[step];
   a->nbatch = st.nbatch;
@@ -107,7 +117,8 @@ Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &en
     if (T.entry >= 0) tptr[t] = entries[T.entry];
     else tptr[t] = ws + L.t_off[t];
   }
-  if (compute_entry_flags) {
+  const bool need_flags = needs_flags(L, skip_final);
+  if (compute_entry_flags && need_flags) {
     FlagArgs fa;
     std::memset(&fa, 0, sizeof(fa));
     int64_t blocks = 0;
@@ -139,8 +150,10 @@ Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &en
     std::memset(&a, 0, sizeof(a));
     a.X = tptr[st.x];
     a.Y = tptr[st.y];
-    a.flagX = reinterpret_cast<const int32_t *>(ws + L.f_off[st.x]);
-    a.flagY = reinterpret_cast<const int32_t *>(ws + L.f_off[st.y]);
+    if (need_flags) {
+      a.flagX = reinterpret_cast<const int32_t *>(ws + L.f_off[st.x]);
+      a.flagY = reinterpret_cast<const int32_t *>(ws + L.f_off[st.y]);
+    }
     a.nchX = p.tensors[st.x].entry >= 0 ? (int)flag_chunks(p.tensors[st.x].cols()) : 1;
     a.nchY = p.tensors[st.y].entry >= 0 ? (int)flag_chunks(p.tensors[st.y].cols()) : 1;
     a.logM = st.logM;

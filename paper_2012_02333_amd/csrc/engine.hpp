@@ -33,6 +33,10 @@ Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &en
                hipStream_t s, bool skip_final = false);
 
 DigitMapDev to_dev(const DigitMap &m);
+// Whether any step (all but the last if skip_final) compacts its terms by the
+// entry row flags (general and wide kernels; every BF16X6 step).  Without them
+// the small kernel keeps every term and the flag pass is skipped.
+bool needs_flags(const NetLayout &L, bool skip_final);
 // Points a step's arguments at its label-list workspace (wide kernel).
 void set_lists(const NetLayout &L, size_t step, char *ws, ContractArgs *a);
 // Tile shape and XCD mapping recorded by the autotuner for a step's shape class.

@@ -18,9 +18,9 @@
 // of one m and stores them as one 16-byte vector (16 lanes cover 64 contiguous
 // bytes of an output row).  The FP64 accumulator strides its rows by 4, so the
 // FP64 form swaps the operands (MFMA row <-> m): 16 lanes then hold 16
-// consecutive n of one row and store 128 contiguous bytes per register.  The last step scales by 2^-K (exact) and reduces
-// the FP64 sum of everything it wrote: per-block partials, then the last
-// block to finish adds the partials in block order.
+// consecutive n of one row and store 128 contiguous bytes per register.
+// The last step scales by 2^-K (exact) and reduces the FP64 sum of everything
+// it wrote: per-block partials, added in block order by k_mass_final.
 #include "kdev.hpp"
 
 namespace cqc {
@@ -113,7 +113,7 @@ __device__ __forceinline__ void contract_tile(const ContractArgs &a, uint32_t bl
     if (s < nSv) {
       rx = row_of(a.mx, s, rX);
       ry = row_of(a.my, s, rY);
-      live = row_live(a.flagX, a.nchX, rx) & row_live(a.flagY, a.nchY, ry);
+      live = a.flagX ? row_live(a.flagX, a.nchX, rx) & row_live(a.flagY, a.nchY, ry) : 1;
     }
     const unsigned long long bal = __ballot(live);
     const int pre = __popcll(bal & ((1ull << lane) - 1ull));
@@ -270,6 +270,9 @@ __device__ __forceinline__ void contract_small_tile(const ContractArgs &a, uint3
   // Operands are loaded for the full term list s = 0..4^|S|-1 at once (term
   // s = 4q + lane/16 in quad q), in parallel with the row-flag check; only if
   // some term turns out dead are they reloaded from the compacted live list.
+  // Without row flags (flagX null) every term is kept: a term whose operand
+  // slices are zero in this tile adds exact zeros, and at most 16 terms cost
+  // nothing next to the output writes.
   const int nSv = 1 << (2 * a.nS);
   int2 rrq[4];
 #pragma unroll
@@ -298,7 +301,9 @@ __device__ __forceinline__ void contract_small_tile(const ContractArgs &a, uint3
   };
   load_ops();
   __shared__ int cnt_sh;
-  if (wave == 0) {
+  if (!a.flagX) {
+    if (tid == 0) cnt_sh = nSv;
+  } else if (wave == 0) {
     int live = 0, rx = 0, ry = 0;
     if (lane < nSv) {
       rx = row_of(a.mx, lane, rX);

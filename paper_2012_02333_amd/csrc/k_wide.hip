@@ -74,7 +74,8 @@ __device__ __forceinline__ void label_list(const ContractArgs &a, int64_t batch)
     if (s < nSv) {
       rx = row_of(a.mx, s, rX);
       ry = row_of(a.my, s, rY);
-      live = row_live(a.flagX, a.nchX, rx) & row_live(a.flagY, a.nchY, ry);
+      // without row flags (plans whose other steps need none) every term is live
+      live = a.flagX ? row_live(a.flagX, a.nchX, rx) & row_live(a.flagY, a.nchY, ry) : 1;
     }
     const unsigned long long bal = __ballot(live);
     const int pre = __popcll(bal & ((1ull << lane) - 1ull));

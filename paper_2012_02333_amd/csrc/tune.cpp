@@ -107,8 +107,10 @@ static Status tune_step(const NetLayout &L, size_t si, char *ws, const std::vect
     tptr[t] = p.tensors[t].entry >= 0 ? ents[p.tensors[t].entry] : ws + L.t_off[t];
   a.X = tptr[st.x];
   a.Y = tptr[st.y];
-  a.flagX = reinterpret_cast<const int32_t *>(ws + L.f_off[st.x]);
-  a.flagY = reinterpret_cast<const int32_t *>(ws + L.f_off[st.y]);
+  if (needs_flags(L, false)) {
+    a.flagX = reinterpret_cast<const int32_t *>(ws + L.f_off[st.x]);
+    a.flagY = reinterpret_cast<const int32_t *>(ws + L.f_off[st.y]);
+  }
   a.nchX = p.tensors[st.x].entry >= 0 ? (int)flag_chunks(p.tensors[st.x].cols()) : 1;
   a.nchY = p.tensors[st.y].entry >= 0 ? (int)flag_chunks(p.tensors[st.y].cols()) : 1;
   a.logM = st.logM;

@@ -184,3 +184,30 @@ def test_fd_mixed_dtypes(in_dt, out_dt, prec):
     assert p.dtype == out_dt
     ref = fd.reconstruct(oracle_inputs(host), inst.cut)
     assert metrics.rel_l1(p.cpu().numpy().astype(np.float64), ref) <= 1e-6
+
+
+@pytest.mark.parametrize("prec,shape", [("fp32", ((6, 6), (2,), 6)), ("fp64", ((4, 4), (3,), 6)),
+                                        ("bf16x6", ((6, 6), (3,), 6)), ("fp32", ((4, 4), (3,), 6))])
+def test_fd_mass_fresh_across_calls(prec, shape):
+    """The FP64 mass is reduced inside the last contraction (the block that
+    finishes last adds every block's partial) and the ticket counter must be
+    left at zero: the same prepared call, run again after the entries are
+    scaled by 2 in place, must report exactly twice the mass (outputs scale
+    exactly by 2, and the partials are added in the same order)."""
+    _gpu()
+    own, bridges, layers = shape
+    inst = W.make_instance(own, bridges, layers, seed=21)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    host, dev = to_dev(inst.entries, dt)
+    cut = cqc.CutMap.from_workload(inst.cut)
+    call = cqc.FDCall(dev, cut, precision=prec)
+    masses = []
+    for rep in range(3):
+        call.run()
+        torch.cuda.synchronize()
+        p = call.outs[0].double().cpu().numpy()
+        m = float(call.mass[0].cpu())
+        assert abs(m - p.sum()) <= 1e-12 * np.abs(p).sum(), (rep, m, p.sum())
+        masses.append(m)
+        dev[0].mul_(2.0)
+    assert masses[1] == 2.0 * masses[0] and masses[2] == 2.0 * masses[1], masses
