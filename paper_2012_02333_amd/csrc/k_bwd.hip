@@ -64,9 +64,19 @@ __device__ __forceinline__ void load4m(const T *p, int64_t c, int64_t lim, T *v)
   }
 }
 
+// Operand prefetch (two register sets) where the registers allow it: FP32
+// with up to 4 label blocks; occupancy targets of four waves per SIMD for the
+// one-label-block form, two for the others (no constraint without prefetch).
+template <typename T, int SB> struct BwdCfg {
+  static constexpr bool kPF = sizeof(T) == 4 && SB <= 4;
+  static constexpr int kWaves = !kPF ? 1 : (SB == 1 ? 4 : 2);
+};
+
 // grid: x = (((p * RXn + rX) * sSuper + ss) * mTiles + mt), p = (rY, k-chunk)
 template <typename T, int SB, int MB>
-__global__ __launch_bounds__(256) void k_bwd_x(const BwdArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BwdCfg<T, SB>::kWaves, 8)))
+void k_bwd_x(const BwdArgs a) {
+  constexpr bool PF = BwdCfg<T, SB>::kPF;
   using Op = BOp<T>;
   using V = typename Op::V;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -100,28 +110,47 @@ __global__ __launch_bounds__(256) void k_bwd_x(const BwdArgs a) {
   for (int i = 0; i < SB; ++i)
 #pragma unroll
     for (int j = 0; j < MB; ++j) acc[i][j] = V{0, 0, 0, 0};
-  for (int64_t n0 = k0; n0 < k1; n0 += 16) {
+  // operands of the next 16 inner indices are loaded while the current ones
+  // are on the matrix cores (two register sets, alternating)
+  T av[PF ? 2 : 1][SB][4], bv[PF ? 2 : 1][MB][4];
+  auto load = [&](int buf, int64_t n0) {
     const int64_t c = n0 + 4 * lg;
-    T av[SB][4], bv[MB][4];
 #pragma unroll
     for (int sb = 0; sb < SB; ++sb) {
-      if (sok[sb]) load4m<T>(Y + (int64_t)yrow[sb] * N, c, k1, av[sb]);
+      if (sok[sb]) load4m<T>(Y + (int64_t)yrow[sb] * N, c, k1, av[buf][sb]);
       else
-        for (int t = 0; t < 4; ++t) av[sb][t] = 0;
+        for (int t = 0; t < 4; ++t) av[buf][sb][t] = 0;
     }
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
       const int64_t m = mw + mb * 16 + l16;
-      if (m < M) load4m<T>(dZ + m * N, c, k1, bv[mb]);
+      if (m < M) load4m<T>(dZ + m * N, c, k1, bv[buf][mb]);
       else
-        for (int t = 0; t < 4; ++t) bv[mb][t] = 0;
+        for (int t = 0; t < 4; ++t) bv[buf][mb][t] = 0;
     }
+  };
+  auto mfma = [&](int buf) {
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
       for (int sb = 0; sb < SB; ++sb)
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) acc[sb][mb] = Op::run(av[sb][t], bv[mb][t], acc[sb][mb]);
+        for (int mb = 0; mb < MB; ++mb) acc[sb][mb] = Op::run(av[buf][sb][t], bv[buf][mb][t], acc[sb][mb]);
+  };
+  if constexpr (PF) {
+    if (k0 < k1) load(0, k0);
+    for (int64_t n0 = k0; n0 < k1; n0 += 32) {
+      const bool two = n0 + 16 < k1;
+      if (two) load(PF ? 1 : 0, n0 + 16);
+      mfma(0);
+      if (n0 + 32 < k1) load(0, n0 + 32);
+      if (two) mfma(PF ? 1 : 0);
+    }
+  } else {
+    for (int64_t n0 = k0; n0 < k1; n0 += 16) {
+      load(0, n0);
+      mfma(0);
+    }
   }
   T *part = static_cast<T *>(a.part) + p * a.rowsX * M;
 #pragma unroll
@@ -139,7 +168,9 @@ __global__ __launch_bounds__(256) void k_bwd_x(const BwdArgs a) {
 
 // grid: x = (((p * RYn + rY) * sSuper + ss) * nTiles + nt), p = (rX, k-chunk over m)
 template <typename T, int SB, int NB>
-__global__ __launch_bounds__(256) void k_bwd_y(const BwdArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BwdCfg<T, SB>::kWaves, 8)))
+void k_bwd_y(const BwdArgs a) {
+  constexpr bool PF = BwdCfg<T, SB>::kPF;
   using Op = BOp<T>;
   using V = typename Op::V;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -172,27 +203,44 @@ __global__ __launch_bounds__(256) void k_bwd_y(const BwdArgs a) {
   for (int i = 0; i < SB; ++i)
 #pragma unroll
     for (int j = 0; j < NB; ++j) acc[i][j] = V{0, 0, 0, 0};
-  for (int64_t m0 = k0; m0 < k1; m0 += 16) {
+  T av[PF ? 2 : 1][SB][4], bv[PF ? 2 : 1][NB][4];
+  auto load = [&](int buf, int64_t m0) {
     const int64_t c = m0 + 4 * lg;
-    T av[SB][4], bv[NB][4];
 #pragma unroll
     for (int sb = 0; sb < SB; ++sb) {
-      if (sok[sb]) load4m<T>(X + (int64_t)xrow[sb] * M, c, k1, av[sb]);
+      if (sok[sb]) load4m<T>(X + (int64_t)xrow[sb] * M, c, k1, av[buf][sb]);
       else
-        for (int t = 0; t < 4; ++t) av[sb][t] = 0;
+        for (int t = 0; t < 4; ++t) av[buf][sb][t] = 0;
     }
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       const int64_t n = nw + nb * 16 + l16;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) bv[nb][t] = (n < N && c + t < k1) ? dZ[(c + t) * N + n] : (T)0;
+      for (int t = 0; t < 4; ++t) bv[buf][nb][t] = (n < N && c + t < k1) ? dZ[(c + t) * N + n] : (T)0;
     }
+  };
+  auto mfma = [&](int buf) {
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
       for (int sb = 0; sb < SB; ++sb)
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[sb][nb] = Op::run(av[sb][t], bv[nb][t], acc[sb][nb]);
+        for (int nb = 0; nb < NB; ++nb) acc[sb][nb] = Op::run(av[buf][sb][t], bv[buf][nb][t], acc[sb][nb]);
+  };
+  if constexpr (PF) {
+    if (k0 < k1) load(0, k0);
+    for (int64_t m0 = k0; m0 < k1; m0 += 32) {
+      const bool two = m0 + 16 < k1;
+      if (two) load(PF ? 1 : 0, m0 + 16);
+      mfma(0);
+      if (m0 + 32 < k1) load(0, m0 + 32);
+      if (two) mfma(PF ? 1 : 0);
+    }
+  } else {
+    for (int64_t m0 = k0; m0 < k1; m0 += 16) {
+      load(0, m0);
+      mfma(0);
+    }
   }
   T *part = static_cast<T *>(a.part) + p * a.rowsY * N;
 #pragma unroll
@@ -208,15 +256,44 @@ __global__ __launch_bounds__(256) void k_bwd_y(const BwdArgs a) {
     }
 }
 
-// out[i] = scale * sum_{p < P} part[p][i], partials added in ascending p.
-template <typename T, typename O>
+// out[i] = scale * sum_{p < P} part[p][i].  With G = 8, eight threads share
+// an output: thread g adds the g-th of eight consecutive ranges of partials in
+// ascending p, then the range sums are added in range order (for few outputs
+// and many partials: eight times the loads in flight); with G = 1 one thread
+// adds all P in ascending p.  Either order is fixed for a given P.
+template <typename T, typename O, int G>
 __global__ __launch_bounds__(256) void k_bwd_reduce(const T *part, int64_t count, int64_t P,
                                                     double scale, O *out) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
-       i += (int64_t)gridDim.x * blockDim.x) {
+  constexpr int W = 256 / G;   // outputs per block and pass
+  __shared__ T sums[G][W + 1];
+  const int g = threadIdx.x / W, j = threadIdx.x % W;
+  const int64_t per = (P + G - 1) / G;
+  const int64_t p0 = g * per, p1 = P < p0 + per ? P : p0 + per;
+  for (int64_t base = (int64_t)blockIdx.x * W; base < count; base += (int64_t)gridDim.x * W) {
+    const int64_t i = base + j;
     T s = 0;
-    for (int64_t p = 0; p < P; ++p) s += part[p * count + i];
-    out[i] = (O)(s * (T)scale);
+    if (i < count) {
+      int64_t p = p0;
+      for (; p + 4 <= p1; p += 4) {
+        const T v0 = part[p * count + i], v1 = part[(p + 1) * count + i];
+        const T v2 = part[(p + 2) * count + i], v3 = part[(p + 3) * count + i];
+        s += v0; s += v1; s += v2; s += v3;
+      }
+      for (; p < p1; ++p) s += part[p * count + i];
+    }
+    if (G == 1) {
+      if (i < count) out[i] = (O)(s * (T)scale);
+      continue;
+    }
+    sums[g][j] = s;
+    __syncthreads();
+    if (g == 0 && i < count) {
+      T t = sums[0][j];
+#pragma unroll
+      for (int q = 1; q < G; ++q) t += sums[q][j];
+      out[i] = (O)(t * (T)scale);
+    }
+    __syncthreads();
   }
 }
 
@@ -273,18 +350,26 @@ Status launch_bwd(Acc acc, const BwdArgs &a, bool which_y, hipStream_t s) {
   return acc == Acc::F32 ? launch_bwd_t<float>(a, which_y, s) : launch_bwd_t<double>(a, which_y, s);
 }
 
+template <typename T, typename O>
+static Status launch_reduce_t(const void *part, int64_t count, int64_t P, double scale, void *out, hipStream_t s) {
+  const T *pp = static_cast<const T *>(part);
+  O *o = static_cast<O *>(out);
+  const dim3 b(256);
+  if (count < (int64_t(1) << 18) && P >= 16) {
+    const dim3 g((unsigned)std::max<int64_t>(1, std::min<int64_t>((count + 31) / 32, 16384)));
+    return launch("bwd_reduce", k_bwd_reduce<T, O, 8>, g, b, 0, s, pp, count, P, scale, o);
+  }
+  const dim3 g((unsigned)std::max<int64_t>(1, std::min<int64_t>((count + 255) / 256, 16384)));
+  return launch("bwd_reduce", k_bwd_reduce<T, O, 1>, g, b, 0, s, pp, count, P, scale, o);
+}
+
 Status launch_bwd_reduce(Acc acc, const void *part, int64_t count, int64_t P, double scale,
                          void *out, bool out_double, hipStream_t s) {
-  const int64_t blocks = std::min<int64_t>((count + 255) / 256, 8192);
-  const dim3 g((unsigned)std::max<int64_t>(blocks, 1)), b(256);
-  if (acc == Acc::F32) {
-    const float *pp = static_cast<const float *>(part);
-    return out_double ? launch("bwd_reduce", k_bwd_reduce<float, double>, g, b, 0, s, pp, count, P, scale, static_cast<double *>(out))
-                      : launch("bwd_reduce", k_bwd_reduce<float, float>, g, b, 0, s, pp, count, P, scale, static_cast<float *>(out));
-  }
-  const double *pp = static_cast<const double *>(part);
-  return out_double ? launch("bwd_reduce", k_bwd_reduce<double, double>, g, b, 0, s, pp, count, P, scale, static_cast<double *>(out))
-                    : launch("bwd_reduce", k_bwd_reduce<double, float>, g, b, 0, s, pp, count, P, scale, static_cast<float *>(out));
+  if (acc == Acc::F32)
+    return out_double ? launch_reduce_t<float, double>(part, count, P, scale, out, s)
+                      : launch_reduce_t<float, float>(part, count, P, scale, out, s);
+  return out_double ? launch_reduce_t<double, double>(part, count, P, scale, out, s)
+                    : launch_reduce_t<double, float>(part, count, P, scale, out, s);
 }
 
 Status launch_gather_blocked(Acc acc, const void *src, void *dst, int logM, int logN,
