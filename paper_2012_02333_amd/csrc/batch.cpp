@@ -33,6 +33,7 @@ struct cqc_batch_s {
   struct Group {
     int level, mode, cfg;
     bool small;
+    cqc::Acc acc;   // arithmetic of the group's steps
     const cqc::ContractArgs *descs;
     const int64_t *prefix;
     int32_t ndesc;
@@ -59,6 +60,7 @@ struct BatchBuild {
   struct G {
     int level, mode, cfg;
     bool small;
+    Acc acc;
     std::vector<std::pair<double, ContractArgs>> steps;  // (cost, args)
   };
   std::vector<G> groups;
@@ -67,7 +69,7 @@ struct BatchBuild {
 };
 
 static int queue_cfg(Acc acc, const Step &st) {
-  const int c = choose_tile(acc, (int)st.S.size(), st.logM, st.logN, st.wide_ok());
+  const int c = choose_tile(step_acc(acc, st.wide_ok()), (int)st.S.size(), st.logM, st.logN, st.wide_ok());
   return c == kTileT ? kTileS : c;
 }
 
@@ -79,7 +81,7 @@ static Status build_batch(const cqc_instance *inst, int32_t n_inst, cqc_dtype in
   const bool acc_double = B.acc == Acc::F64;
   if ((out_t == CQC_F64) != acc_double)
     return Status::fail(CQC_ERR_UNSUPPORTED, "batched calls need the output dtype of the precision");
-  std::map<std::tuple<int, int, int, int>, size_t> gidx;
+  std::map<std::tuple<int, int, int, int, int>, size_t> gidx;
   for (int32_t i = 0; i < n_inst; ++i) {
     const FdInstancePlan &ip = B.plans[i];
     const NetLayout &L = ip.net;
@@ -168,7 +170,8 @@ static Status build_batch(const cqc_instance *inst, int32_t n_inst, cqc_dtype in
         }
       }
       const bool small = a.nS <= 2;
-      auto key = std::make_tuple(level, (int)a.mode, cfg, (int)small);
+      const Acc sa = step_acc(B.acc, st.wide_ok());
+      auto key = std::make_tuple(level, (int)a.mode, cfg, (int)small, (int)sa);
       auto it = gidx.find(key);
       if (it == gidx.end()) {
         it = gidx.emplace(key, B.groups.size()).first;
@@ -177,6 +180,7 @@ static Status build_batch(const cqc_instance *inst, int32_t n_inst, cqc_dtype in
         g.mode = a.mode;
         g.cfg = cfg;
         g.small = small;
+        g.acc = sa;
         B.groups.push_back(g);
       }
       const double cost = (double)a.nblocks * std::ldexp(1.0, 2 * a.nS) * sh.bm * sh.bn;
@@ -246,7 +250,7 @@ static Status batch_run(cqc_batch_s *b, hipStream_t s) {
     q.grid = (uint32_t)std::min<int64_t>(G.total, kQueueGrid);
     q.bprefix = G.bprefix;
     q.btotal = G.btotal;
-    CQC_TRY(launch_contract_queue(b->acc, G.mode, G.cfg, G.small, q, s));
+    CQC_TRY(launch_contract_queue(G.acc, G.mode, G.cfg, G.small, q, s));
   }
   if (b->n_mass > 0) CQC_TRY(launch_mass_table(b->mass_descs, b->n_mass, s));
   return Status::ok();
@@ -297,6 +301,7 @@ static Status batch_create(const cqc_instance *inst, int32_t n_inst, cqc_dtype i
     bg.mode = G.mode;
     bg.cfg = G.cfg;
     bg.small = G.small;
+    bg.acc = G.acc;
     bg.descs = reinterpret_cast<const ContractArgs *>(ws + B.desc_off[g]);
     bg.prefix = reinterpret_cast<const int64_t *>(ws + B.prefix_off[g]);
     bg.ndesc = (int32_t)descs.size();

@@ -36,7 +36,7 @@ NetLayout layout_net(const Plan &plan, Acc acc, size_t base) {
   }
   int64_t max_final_blocks = 1;
   for (const auto &st : plan.steps) {
-    int cfg = choose_tile(acc, (int)st.S.size(), st.logM, st.logN, st.wide_ok());
+    int cfg = choose_tile(step_acc(acc, st.wide_ok()), (int)st.S.size(), st.logM, st.logN, st.wide_ok());
     TileShape sh = tile_shape(cfg);
     int64_t tm = ((int64_t(1) << st.logM) + sh.bm - 1) / sh.bm;
     int64_t tn = ((int64_t(1) << st.logN) + sh.bn - 1) / sh.bn;
@@ -166,8 +166,9 @@ Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &en
     set_lists(L, i, ws, &a);
     const int mode = !last ? kModeIntermediate : (is_blocked(p, st) ? kModeFinalBlocked : kModeFinalDeposit);
     const bool od = last ? out_double : L.acc == Acc::F64;
+    const Acc sa = step_acc(L.acc, st.wide_ok());
     int cfg = L.tile[i], xcd = 0;
-    if (!tuned_choice(L.acc, mode, a.nS <= 2, st.logM, st.logN, a.nS, od, &cfg, &xcd) || !tile_ok(L.acc, cfg)) {
+    if (!tuned_choice(sa, mode, a.nS <= 2, st.logM, st.logN, a.nS, od, &cfg, &xcd) || !tile_ok(sa, cfg)) {
       cfg = L.tile[i];
       // the wide kernel's tiles of one operand row block share that block's
       // operand columns: keep them on one XCD (and its L2)
@@ -183,7 +184,7 @@ Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &en
       a.Z = ws + L.t_off[st.z];
       a.flagZ = reinterpret_cast<int32_t *>(ws + L.f_off[st.z]);
       a.scale = 1.0;
-      CQC_TRY(launch_contract(L.acc, L.acc == Acc::F64, cfg, a, s));
+      CQC_TRY(launch_contract(sa, L.acc == Acc::F64, cfg, a, s));
     } else {
       a.Z = out;
       a.scale = std::ldexp(1.0, -p.K);
@@ -200,7 +201,7 @@ Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &en
         a.posY = pack_pos(py);
       }
       if (mass) a.partials = reinterpret_cast<double *>(ws + L.partials_off);
-      CQC_TRY(launch_contract(L.acc, out_double, cfg, a, s));
+      CQC_TRY(launch_contract(sa, out_double, cfg, a, s));
       if (mass) CQC_TRY(launch_mass_final(a.partials, a.nblocks, mass, s));
     }
   }

@@ -19,17 +19,17 @@
 // persistent blocks of four waves (2 x 2), each owning a 128 x 128 output tile
 // at a time and walking a sequence of tiles (a contiguous range per XCD, so
 // the tiles that share operand columns share an L2; or an atomic work queue
-// over many steps).  Terms are consumed 32 at a time: every thread owns one
-// operand column of the tile (threads 0..127 the X columns, 128..255 the Y
-// columns) and loads that column's 32 term values into registers one chunk
-// ahead - across tile boundaries, so the next tile's first operands are in
-// flight while the current tile computes and stores - then writes them to LDS
-// with the term index fastest, so that each lane fetches a whole matrix-core
+// over many steps).  Terms are consumed 32 at a time: each wave loads 16 terms
+// of one operand, each lane two adjacent columns of them, two chunks ahead -
+// across tile boundaries, so the next tile's first operands are in flight
+// while the current tile computes and stores - and writes them to LDS with
+// the term index fastest, so that each lane fetches a whole matrix-core
 // operand with one 16-byte LDS read.  The epilogue stages each 16-row slice of
 // a wave tile through LDS and writes whole 256-byte row segments.
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <type_traits>
 
 #include "kdev.hpp"
 
@@ -37,6 +37,7 @@ namespace cqc {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int i32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 namespace {
 constexpr int kWB = 128;        // block tile edge (m and n)
@@ -58,14 +59,16 @@ __device__ __forceinline__ void split3(float a, __bf16 *h, __bf16 *m, __bf16 *l)
   *l = (__bf16)r2;
 }
 
-// ---- label lists: one block per batch entry of a step; entries are the byte
-// offsets of the two operand rows (operands hold at most 2^30 elements)
+// ---- label lists: one block per batch entry of a step; per batch entry the
+// byte offsets of the live terms' X rows, then of their Y rows (operands hold
+// at most 2^30 elements)
 __device__ __forceinline__ void label_list(const ContractArgs &a, int64_t batch) {
   __shared__ int wcnt[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int rX = (int)(batch >> (2 * a.nRY));
   const int rY = (int)(batch & ((int64_t(1) << (2 * a.nRY)) - 1));
-  int2 *L = reinterpret_cast<int2 *>(a.lists) + batch * a.list_ld;
+  uint32_t *Lx = reinterpret_cast<uint32_t *>(a.lists) + batch * 2 * a.list_ld;   // X row offsets
+  uint32_t *Ly = Lx + a.list_ld;                                                     // Y row offsets
   const int nSv = 1 << (2 * a.nS);
   int total = 0;
   for (int s0 = 0; s0 < nSv; s0 += 256) {
@@ -84,15 +87,17 @@ __device__ __forceinline__ void label_list(const ContractArgs &a, int64_t batch)
     int base = 0;
     for (int w = 0; w < wave; ++w) base += wcnt[w];
     const int cnt = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
-    if (live)
-      L[total + base + pre] = make_int2((int)((uint32_t)rx << (a.logM + 2)), (int)((uint32_t)ry << (a.logN + 2)));
+    if (live) {
+      Lx[total + base + pre] = (uint32_t)rx << (a.logM + 2);
+      Ly[total + base + pre] = (uint32_t)ry << (a.logN + 2);
+    }
     total += cnt;
     __syncthreads();   // wcnt is rewritten by the next chunk
   }
   // pad to whole chunks (one chunk of padding if nothing is live) with row 0
   // (a valid address; the terms are masked by the count)
   const int padded = total == 0 ? kWC : (total + kWC - 1) / kWC * kWC;
-  for (int k = total + tid; k < padded; k += 256) L[k] = make_int2(0, 0);
+  for (int k = total + tid; k < padded; k += 256) Lx[k] = Ly[k] = 0u;
   if (tid == 0) {
     a.counts[batch] = total;
     if (a.flagZ) a.flagZ[batch] = total > 0;
@@ -122,6 +127,12 @@ __device__ __forceinline__ double uni(double v) { return __builtin_bit_cast(doub
 // integer is generic to the compiler, which would emit flat accesses).
 template <typename T> using gptr = __attribute__((address_space(1))) T *;
 template <typename T> __device__ __forceinline__ gptr<T> gbl(T *p) { return (gptr<T>)p; }
+// Constant-address-space view of data that no wave writes during the kernel
+// (label lists and counts, written by the preceding label-list pass): uniform
+// loads through it become scalar loads, which are waited for on the scalar
+// counter - not behind this wave's outstanding output stores.
+template <typename T> using cptr = __attribute__((address_space(4))) const T *;
+template <typename T> __device__ __forceinline__ cptr<T> cst(const T *p) { return (cptr<T>)gbl(p); }
 
 // ---- a tile of a step: its block index and chunk count; the geometry is
 // recomputed from the step's arguments where it is needed (few scalars live)
@@ -129,6 +140,7 @@ struct WideTile {
   uint32_t blk;
   int nch;   // chunks of kWC terms (at least one)
   int cnt;   // live terms
+  int d;     // step of the tile (work-queue launches; 0 otherwise)
 };
 
 struct WideGeom {
@@ -155,13 +167,14 @@ __device__ __forceinline__ WideGeom wide_geom(const ContractArgs &a, uint32_t bl
 
 __device__ __forceinline__ WideTile wide_decode(const ContractArgs &a, uint32_t blk) {
   const WideGeom g = wide_geom(a, blk);
-  const int cnt = uni(gbl(uni(a.counts))[g.batch]);
-  return WideTile{blk, cnt == 0 ? 1 : (cnt + kWC - 1) / kWC, cnt};
+  const int cnt = cst(uni(a.counts))[g.batch];
+  return WideTile{blk, cnt == 0 ? 1 : (cnt + kWC - 1) / kWC, cnt, 0};
 }
 
 // Tile sequences of a block.  Strided: one step, tiles of a contiguous range
-// per XCD (hardware places block b on XCD b % 8).  Queue: many steps, the next
-// item is fetched by thread 0 one tile ahead into a parity slot of LDS.
+// per XCD (hardware places block b on XCD b % 8).  Queue: many steps; a new
+// tile is fetched by thread 0 into one of two LDS slots (alternating) before a
+// barrier, and decoded by every thread after it.
 struct StridedSeq {
   const ContractArgs &a;
   int64_t pos, end, stride;
@@ -178,19 +191,19 @@ struct StridedSeq {
       stride = G;
     }
   }
-  __device__ bool first(WideTile *t, int) {
+  __device__ bool first(WideTile *t) {
     if (pos >= end) return false;
     *t = wide_decode(a, (uint32_t)pos);
     return true;
   }
-  __device__ void fetch_ahead(int) {}
+  __device__ void fetch(int) {}
   __device__ bool next(WideTile *t, int) {
     pos += stride;
     if (pos >= end) return false;
     *t = wide_decode(a, (uint32_t)pos);
     return true;
   }
-  __device__ const ContractArgs &args(int) const { return a; }
+  __device__ const ContractArgs &args(const WideTile &) const { return a; }
 };
 
 struct QueueSeq {
@@ -199,30 +212,30 @@ struct QueueSeq {
   int ndesc;
   unsigned long long *queue;
   int64_t total;
-  int64_t *slot;    // [2] queue items, in LDS, by tile parity
-  int d[2] = {0, 0};  // step of the tile of each parity
-  __device__ int64_t read_slot(int par) const {
-    const int64_t v = slot[par];
+  int64_t *slot;    // [2] fetched queue items, in LDS
+  __device__ int64_t read_slot(int sp) const {
+    const int64_t v = slot[sp];
     return (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v) |
            ((int64_t)__builtin_amdgcn_readfirstlane((int)(v >> 32)) << 32);
   }
-  __device__ bool decode_item(int64_t item, WideTile *t, int par) {
+  __device__ bool decode_item(int64_t item, WideTile *t) {
     if (item >= total) return false;
-    d[par] = uni(find_desc(prefix, ndesc, item));
-    *t = wide_decode(descs[d[par]], (uint32_t)(item - uni(prefix[d[par]])));
+    const int d = uni(find_desc(prefix, ndesc, item));
+    *t = wide_decode(descs[d], (uint32_t)(item - uni(prefix[d])));
+    t->d = d;
     return true;
   }
-  __device__ bool first(WideTile *t, int par) {
-    if (threadIdx.x == 0) slot[par] = (int64_t)atomicAdd(queue, 1ull);
+  __device__ bool first(WideTile *t) {
+    if (threadIdx.x == 0) slot[0] = (int64_t)atomicAdd(queue, 1ull);
     __syncthreads();
-    return decode_item(read_slot(par), t, par);
+    return decode_item(read_slot(0), t);
   }
-  // called by every thread before the barrier that precedes next(par)
-  __device__ void fetch_ahead(int par) {
-    if (threadIdx.x == 0) slot[par] = (int64_t)atomicAdd(queue, 1ull);
+  // by every thread, before the barrier that precedes next(sp)
+  __device__ void fetch(int sp) {
+    if (threadIdx.x == 0) slot[sp] = (int64_t)atomicAdd(queue, 1ull);
   }
-  __device__ bool next(WideTile *t, int par) { return decode_item(read_slot(par), t, par); }
-  __device__ const ContractArgs &args(int par) const { return descs[d[par]]; }
+  __device__ bool next(WideTile *t, int sp) { return decode_item(read_slot(sp), t); }
+  __device__ const ContractArgs &args(const WideTile &t) const { return descs[t.d]; }
 };
 
 template <bool SPLIT, typename O, int MODE, class Seq>
@@ -238,9 +251,12 @@ __device__ __forceinline__ void wide_run(Seq &seq) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int l16 = lane & 15, lg = lane >> 4;
-  // staging role of the wave: threads 0..127 own the X columns of the tile,
-  // 128..255 the Y columns (wave-uniform)
-  const bool roleX = uni(tid) < kWB;
+  // staging role of the wave (wave-uniform): waves 0 and 2 stage X, 1 and 3
+  // stage Y; waves 0 and 1 the first 16 terms of a chunk, 2 and 3 the last 16;
+  // lane l owns the two adjacent operand columns 2l and 2l + 1 of the tile
+  const int wv = uni(wave);
+  const bool roleX = (wv & 1) == 0;
+  const int half = wv >> 1;
 
   f32x4 acc[4][4];
 #pragma unroll
@@ -251,59 +267,71 @@ __device__ __forceinline__ void wide_run(Seq &seq) {
   // Branch-free prefetch: every lane loads (padding and overhanging columns
   // read element 0), so all kWC loads of a chunk are in flight together; the
   // invalid ones are zeroed only when the chunk is written to LDS.
-  float pre[kWC];
-  uint32_t okrow = 0;   // wave-uniform: term k of the chunk is live (k < count)
-  bool colok = true;    // this lane's operand column lies inside the operand
-  auto gload = [&](const ContractArgs &a, const WideTile &t, int ch) {
+  constexpr int kH = kWC / 2;      // terms per staging wave and chunk
+  float pre[2][kH][2];
+  uint32_t okrow[2] = {0u, 0u};    // wave-uniform: term k of this wave's half is live
+  bool colok[2][2] = {{true, true}, {true, true}};   // this lane's two columns lie inside the operand
+  auto gload = [&](auto B, const ContractArgs &a, const WideTile &t, int ch) {
+    constexpr int b = decltype(B)::value;
     const WideGeom g = wide_geom(a, t.blk);
-    // lane k < 32 fetches list entry k of the chunk; entry k's byte offset
-    // then moves to a scalar register, and each load is a scalar base plus a
-    // 32-bit lane offset
-    const i32x2 *list = uni(reinterpret_cast<const i32x2 *>(a.lists)) + g.batch * uni(a.list_ld);
-    const i32x2 mine = gbl(list)[ch * kWC + (lane & (kWC - 1))];
-    const int myoff = roleX ? mine[0] : mine[1];
+    // the row offsets of this wave's terms come in by scalar loads; each load
+    // is a scalar base plus a 32-bit lane offset and fetches two columns
+    // (one wave instruction: 512 contiguous bytes of an operand row)
+    const int32_t ld32 = uni(a.list_ld);
+    const cptr<uint32_t> offs = cst(reinterpret_cast<const uint32_t *>(uni(a.lists))) +
+                                (g.batch * 2 + (roleX ? 0 : 1)) * ld32 + ch * kWC + half * kH;
     const char *srcb = reinterpret_cast<const char *>(roleX ? uni(a.X) : uni(a.Y));
     const int64_t ld = roleX ? g.M : g.N;
-    const int64_t colv = (roleX ? g.m0 : g.n0) + (tid & (kWB - 1));
-    colok = colv < ld;
-    const uint32_t col4 = colok ? (uint32_t)colv * 4u : 0u;
-    const int nv = t.cnt - ch * kWC;   // live terms in this chunk (uniform)
-    okrow = nv >= kWC ? 0xffffffffu : (nv <= 0 ? 0u : (1u << nv) - 1u);
+    const int64_t colv = (roleX ? g.m0 : g.n0) + 2 * lane;
+    colok[b][0] = colv < ld;
+    colok[b][1] = colv + 1 < ld;
+    const int nv = t.cnt - ch * kWC - half * kH;   // live terms of this wave's half (uniform)
+    okrow[b] = nv >= kH ? 0xffffu : (nv <= 0 ? 0u : (1u << nv) - 1u);
+    // ld is a power of two >= 2 (steps with a one-column operand do not run
+    // here): both columns are inside or both outside
+    const uint32_t col4 = colok[b][1] ? (uint32_t)colv * 4u : 0u;
 #pragma unroll
-    for (int k = 0; k < kWC; ++k) {
-      const uint32_t o = (uint32_t)__builtin_amdgcn_readlane(myoff, k);
-      pre[k] = *(gptr<const float>)(gbl(srcb) + (o + col4));
+    for (int k = 0; k < kH; ++k) {
+      const f32x2 v = *(gptr<const f32x2>)(gbl(srcb) + (offs[k] + col4));
+      pre[b][k][0] = v[0];
+      pre[b][k][1] = v[1];
     }
   };
-  auto val = [&](int k) { return (colok && ((okrow >> k) & 1u)) ? pre[k] : 0.0f; };
-  auto stage = [&]() {
+  auto stage = [&](auto B) {
+    constexpr int b = decltype(B)::value;
+    auto val = [&](int k, int j) { return (colok[b][j] && ((okrow[b] >> k) & 1u)) ? pre[b][k][j] : 0.0f; };
+    const int col0 = (roleX ? 0 : kWB) + 2 * lane;   // first of this lane's two LDS operand columns
     if constexpr (!SPLIT) {
       // term k of a 16-term group g sits at 16 g + 4 (k % 4) + (k % 16) / 4, so
-      // lane group lg reads terms {lg, lg+4, lg+8, lg+12} of the group at once
-      float *cp = reinterpret_cast<float *>(smem) + tid * kF32Ld;
+      // lane group lg reads terms {lg, lg+4, lg+8, lg+12} of the group at once;
+      // this wave's half is group `half`
 #pragma unroll
-      for (int g = 0; g < 2; ++g)
+      for (int j = 0; j < 2; ++j) {
+        float *cp = reinterpret_cast<float *>(smem) + (col0 + j) * kF32Ld + 16 * half;
 #pragma unroll
         for (int p = 0; p < 4; ++p)
-          *reinterpret_cast<float4 *>(cp + 16 * g + 4 * p) =
-              make_float4(val(16 * g + p), val(16 * g + 4 + p), val(16 * g + 8 + p), val(16 * g + 12 + p));
+          *reinterpret_cast<float4 *>(cp + 4 * p) = make_float4(val(p, j), val(4 + p, j), val(8 + p, j), val(12 + p, j));
+      }
     } else {
       __bf16 *bp = reinterpret_cast<__bf16 *>(smem);
 #pragma unroll
-      for (int o = 0; o < 4; ++o) {
-        bf16x8 h, m, l;
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          __bf16 x0, x1, x2;
-          split3(val(8 * o + e), &x0, &x1, &x2);
-          h[e] = x0;
-          m[e] = x1;
-          l[e] = x2;
+        for (int o = 0; o < 2; ++o) {
+          bf16x8 h, m, l;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            __bf16 x0, x1, x2;
+            split3(val(8 * o + e, j), &x0, &x1, &x2);
+            h[e] = x0;
+            m[e] = x1;
+            l[e] = x2;
+          }
+          const int pos = 16 * half + 8 * o;
+          *reinterpret_cast<bf16x8 *>(bp + (0 * 2 * kWB + col0 + j) * kB16Ld + pos) = h;
+          *reinterpret_cast<bf16x8 *>(bp + (1 * 2 * kWB + col0 + j) * kB16Ld + pos) = m;
+          *reinterpret_cast<bf16x8 *>(bp + (2 * 2 * kWB + col0 + j) * kB16Ld + pos) = l;
         }
-        *reinterpret_cast<bf16x8 *>(bp + (0 * 2 * kWB + tid) * kB16Ld + 8 * o) = h;
-        *reinterpret_cast<bf16x8 *>(bp + (1 * 2 * kWB + tid) * kB16Ld + 8 * o) = m;
-        *reinterpret_cast<bf16x8 *>(bp + (2 * 2 * kWB + tid) * kB16Ld + 8 * o) = l;
-      }
     }
   };
   // MFMA mapping: A operand = Y (MFMA row <-> n), B operand = X (MFMA column
@@ -436,41 +464,79 @@ __device__ __forceinline__ void wide_run(Seq &seq) {
     }
   };
 
-  // ---- the pipelined tile sequence
-  int par = 0;
-  WideTile cur;
-  if (!seq.first(&cur, par)) return;
-  int c = 0;
-  gload(seq.args(par), cur, 0);
-  for (;;) {
-    const bool last = c == cur.nch - 1;
-    if (last) seq.fetch_ahead(par ^ 1);
-    __syncthreads();   // the operand area (and staging slices) are free
-    stage();
+  // ---- the pipelined item sequence.  An item is (tile, chunk); the operands
+  // of item q+2 are loaded while item q is on the matrix cores, into the
+  // register set item q has just left.  Loads are issued on every item (a
+  // repeat of the current item's past the end of the sequence), so the wait
+  // for an item's operands always has the next item's loads and a whole item
+  // of matrix-core work after it - any output stores of the tile before have
+  // drained by then, instead of being waited for (loads and stores share one
+  // in-order completion counter).
+  struct Item { WideTile t; int c; bool ok; };
+  Item q0;
+  if (!seq.first(&q0.t)) return;
+  q0.c = 0;
+  q0.ok = true;
+  int sp = 1;   // next fetch slot (the first tile came through slot 0)
+  auto item_args = [&](const Item &x) -> const ContractArgs & { return seq.args(x.t); };
+  gload(std::integral_constant<int, 0>{}, item_args(q0), q0.t, 0);
+  Item q1 = q0;
+  if (q1.c + 1 < q1.t.nch) {
+    ++q1.c;
+  } else {
+    seq.fetch(sp);
     __syncthreads();
-    WideTile nxt = cur;
-    bool more = true;
-    if (!last) {
-      gload(seq.args(par), cur, c + 1);
-    } else {
-      more = seq.next(&nxt, par ^ 1);
-      if (more) gload(seq.args(par ^ 1), nxt, 0);
+    q1.ok = seq.next(&q1.t, sp);
+    sp ^= 1;
+    q1.c = 0;
+  }
+  {
+    const WideTile lt = q1.ok ? q1.t : q0.t;   // one load site (a repeat past the end)
+    gload(std::integral_constant<int, 1>{}, seq.args(lt), lt, q1.ok ? q1.c : q0.c);
+  }
+  Item q2 = q1;   // advanced to item q+2 inside each step
+  // Items are taken in pairs (register set 0, then 1) and the sequence may
+  // only end after the second: a block with an odd item count finishes with
+  // an empty item (q0.ok false) that loads a repeat and computes nothing.
+  // An exit after the first would join the loop header on a path where only
+  // set 0's loads are in flight, and the compiler would then drain every load
+  // before staging set 0 on every iteration.
+  auto step = [&](auto B) -> bool {
+    // advancing q2 starts a new tile: fetch it before the barrier
+    const bool new_tile = q2.ok && q2.c + 1 == q2.t.nch;
+    if (new_tile) seq.fetch(sp);
+    __syncthreads();   // the operand area (and staging slices) are free
+    stage(B);
+    __syncthreads();
+    if (q2.ok) {
+      if (new_tile) {
+        q2.ok = seq.next(&q2.t, sp);
+        sp ^= 1;
+        q2.c = 0;
+      } else {
+        ++q2.c;
+      }
     }
-    compute();
-    if (last) {
+    const WideTile lt = q2.ok ? q2.t : q0.t;     // one load site (a repeat past the end)
+    gload(B, seq.args(lt), lt, q2.ok ? q2.c : q0.c);
+    if (q0.ok) compute();
+    if (q0.ok && q0.c == q0.t.nch - 1) {
       __syncthreads();   // every wave is done reading operands: stage the outputs
-      epilogue(seq.args(par), cur);
+      epilogue(item_args(q0), q0.t);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-      if (!more) break;
-      cur = nxt;
-      c = 0;
-      par ^= 1;
-    } else {
-      ++c;
     }
+    if (decltype(B)::value == 1 && !q1.ok) return false;
+    if (q1.ok) q0 = q1;
+    else q0.ok = false;   // keeps the last real tile for the empty item's loads
+    q1 = q2;
+    return true;
+  };
+  for (;;) {
+    step(std::integral_constant<int, 0>{});
+    if (!step(std::integral_constant<int, 1>{})) break;
   }
 }
 
@@ -497,7 +563,7 @@ void k_wide_queue(const ContractArgs *__restrict__ descs,
 // ---------------------------------------------------------------------------
 bool wide_fits(const ContractArgs &a) {
   const int64_t x = (int64_t)2 * (a.nS + a.nRX) + a.logM, y = (int64_t)2 * (a.nS + a.nRY) + a.logN;
-  return x <= 30 && y <= 30;
+  return x <= 30 && y <= 30 && a.logM >= 1 && a.logN >= 1;
 }
 
 // Blocks of a kernel that fit on the current device at once (cached).
@@ -541,7 +607,7 @@ Status launch_contract_wide(bool split, bool out_double, const ContractArgs &a, 
   if (!a.lists || !a.counts || a.nbatch < 1 || a.list_ld < wide_list_ld(a.nS))
     return Status::fail(CQC_ERR_INVALID_ARG, "wide contraction without label-list workspace");
   if (!wide_fits(a))
-    return Status::fail(CQC_ERR_UNSUPPORTED, "wide contraction: an operand exceeds 2^30 elements");
+    return Status::fail(CQC_ERR_UNSUPPORTED, "wide contraction: an operand has one column or exceeds 2^30 elements");
   if (split) return out_double ? launch_wide_t<true, double>(a, s) : launch_wide_t<true, float>(a, s);
   return out_double ? launch_wide_t<false, double>(a, s) : launch_wide_t<false, float>(a, s);
 }

@@ -52,8 +52,8 @@ struct ContractArgs {
   double *partials;  // [nblocks] per-block FP64 sums of the written outputs, or null
   // wide kernel only: live-label lists of every batch entry (written by the
   // label-list pass of the same step)
-  int32_t *lists;    // [nbatch][list_ld] (byte offset of the X row, of the Y row) pairs,
-                     //   ascending s; padding (0, 0)
+  int32_t *lists;    // [nbatch][2][list_ld] byte offsets of the live terms' X rows, then of
+                     //   their Y rows, ascending s; padding 0
   int32_t *counts;   // [nbatch] live labels
   int32_t list_ld;   // pairs per batch entry: 4^nS rounded up to a multiple of 32
   int64_t nbatch;
@@ -105,6 +105,10 @@ TileShape tile_shape(int cfg);
 int choose_tile(Acc acc, int nS, int logM, int logN, bool wide_ok);
 // Whether the arithmetic has a kernel with this tile configuration.
 bool tile_ok(Acc acc, int cfg);
+// Arithmetic a step of a plan runs in: a BF16X6 step the wide kernel cannot
+// take (an operand with one column: a matrix-vector product, no matrix-core
+// work to win) runs the FP32 form.
+inline Acc step_acc(Acc acc, bool wide_ok) { return acc == Acc::BF16X6 && !wide_ok ? Acc::F32 : acc; }
 
 Status launch_row_flags(const FlagArgs &a, int64_t total_blocks, hipStream_t s);
 Status launch_mass_final(const double *partials, int64_t count, double *mass, hipStream_t s);

@@ -52,8 +52,10 @@ struct Step {
   int logM = 0, logN = 0;      // column bits of X and Y
   int64_t nbatch = 1;          // 4^(|RX|+|RY|)
   // both operands hold at most 2^30 elements (the wide kernel's addressing)
+  // and have at least two columns (its paired column loads)
   bool wide_ok() const {
-    return 2 * (S.size() + RX.size()) + logM <= 30 && 2 * (S.size() + RY.size()) + logN <= 30;
+    return 2 * (S.size() + RX.size()) + logM <= 30 && 2 * (S.size() + RY.size()) + logN <= 30 && logM >= 1 &&
+           logN >= 1;
   }
 };
 

@@ -141,6 +141,7 @@ static Status tune_step(const NetLayout &L, size_t si, char *ws, const std::vect
       a.posY = pack_pos(py);
     }
   }
+  const Acc sa = step_acc(L.acc, st.wide_ok());
   const int64_t work = (int64_t(1) << (st.logM + st.logN)) * st.nbatch;
   const int reps = work >= (int64_t(1) << 24) ? 10 : 30;
   hipEvent_t e0, e1;
@@ -148,11 +149,11 @@ static Status tune_step(const NetLayout &L, size_t si, char *ws, const std::vect
   CQC_HIP_TRY(hipEventCreate(&e1));
   Choice best{-1, 0, 1e30};
   for (int cfg = 0; cfg < kTileCount; ++cfg) {
-    if (!tile_ok(L.acc, cfg)) continue;
+    if (!tile_ok(sa, cfg)) continue;
     const TileShape sh = tile_shape(cfg);
     const int64_t M = int64_t(1) << st.logM, N = int64_t(1) << st.logN;
     // skip shapes that would leave most of every tile empty
-    if ((M < sh.bm || N < sh.bn) && cfg != kTileS && cfg != choose_tile(L.acc, a.nS, st.logM, st.logN, st.wide_ok())) continue;
+    if ((M < sh.bm || N < sh.bn) && cfg != kTileS && cfg != choose_tile(sa, a.nS, st.logM, st.logN, st.wide_ok())) continue;
     if (cfg == kTileW && !st.wide_ok()) continue;
     for (int xcd = 0; xcd < 2; ++xcd) {
       a.tilesM = (int)((M + sh.bm - 1) / sh.bm);
@@ -160,9 +161,9 @@ static Status tune_step(const NetLayout &L, size_t si, char *ws, const std::vect
       a.nblocks = (int64_t)a.tilesM * a.tilesN * st.nbatch;
       if (xcd && a.nblocks % 8) continue;
       a.xcd_remap = xcd;
-      CQC_TRY(launch_contract(L.acc, od, cfg, a, s));  // warm-up
+      CQC_TRY(launch_contract(sa, od, cfg, a, s));  // warm-up
       CQC_HIP_TRY(hipEventRecord(e0, s));
-      for (int r = 0; r < reps; ++r) CQC_TRY(launch_contract(L.acc, od, cfg, a, s));
+      for (int r = 0; r < reps; ++r) CQC_TRY(launch_contract(sa, od, cfg, a, s));
       CQC_HIP_TRY(hipEventRecord(e1, s));
       CQC_HIP_TRY(hipEventSynchronize(e1));
       float ms = 0.f;
@@ -177,7 +178,7 @@ static Status tune_step(const NetLayout &L, size_t si, char *ws, const std::vect
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (best.cfg >= 0)
-    record(Key((int)L.acc, a.mode, (int)(a.nS <= 2), st.logM, st.logN, a.nS, (int)od), best);
+    record(Key((int)sa, a.mode, (int)(a.nS <= 2), st.logM, st.logN, a.nS, (int)od), best);
   return Status::ok();
 }
 
