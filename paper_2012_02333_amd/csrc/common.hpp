@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstdint>
 #include <string>
@@ -41,24 +42,33 @@ struct Status {
     if (!s_.good()) return s_;       \
   } while (0)
 
-// Kernel launch tracing (events around launches when enabled).
+// Kernel launch tracing.  When enabled, the start and stop events are part of
+// the dispatch itself (recorded when the kernel begins and ends), so a traced
+// duration is the kernel's own run time without the launch gap around it.
 bool trace_on();
-void trace_begin(const char *name, hipStream_t s, hipEvent_t *start);
-void trace_end(const char *name, hipStream_t s, hipEvent_t start);
+bool trace_events(hipEvent_t *start, hipEvent_t *stop);
+void trace_push(const char *name, hipEvent_t start, hipEvent_t stop);
 
 // Launch helper: traces when enabled, checks the launch error.
 template <typename Kernel, typename... Args>
 Status launch(const char *name, Kernel k, dim3 grid, dim3 block, size_t shmem,
               hipStream_t s, Args... args) {
   if (grid.x == 0 || grid.y == 0 || grid.z == 0) return Status::ok();
-  hipEvent_t ev = nullptr;
-  if (trace_on()) trace_begin(name, s, &ev);
-  hipLaunchKernelGGL(k, grid, block, shmem, s, args...);
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (trace_on() && trace_events(&ev0, &ev1))
+    hipExtLaunchKernelGGL(k, grid, block, (uint32_t)shmem, s, ev0, ev1, 0u, args...);
+  else
+    hipLaunchKernelGGL(k, grid, block, shmem, s, args...);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess)
+  if (e != hipSuccess) {
+    if (ev0) {
+      (void)hipEventDestroy(ev0);
+      (void)hipEventDestroy(ev1);
+    }
     return Status::fail(CQC_ERR_HIP, std::string("launch ") + name + ": " +
                                          hipGetErrorString(e));
-  if (ev) trace_end(name, s, ev);
+  }
+  if (ev0) trace_push(name, ev0, ev1);
   return Status::ok();
 }
 

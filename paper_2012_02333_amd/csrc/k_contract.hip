@@ -21,6 +21,8 @@
 // consecutive n of one row and store 128 contiguous bytes per register.
 // The last step scales by 2^-K (exact) and reduces the FP64 sum of everything
 // it wrote: per-block partials, added in block order by k_mass_final.
+#include <type_traits>
+
 #include "kdev.hpp"
 
 namespace cqc {
@@ -421,6 +423,113 @@ __device__ __forceinline__ void contract_small_tile(const ContractArgs &a, uint3
   }
 }
 
+
+// Two-tile strips for the 64 x 256 FP32 tile with FP32 output and every term
+// kept (no row flags): a block takes two vertically adjacent tiles, loads the Y operands
+// once and issues the X loads of the second tile before the first tile's
+// output stores, so that wait never covers stores.  Half as many blocks
+// start together, which spreads the operand fetch at the start of the launch
+// over the first tile's stores.  One partial mass per tile, as in the
+// one-tile kernel.
+constexpr int kStripRows = 2;
+
+template <typename O, int MODE>
+__device__ __forceinline__ void contract_small_strip(const ContractArgs &a, uint32_t strip) {
+  static_assert(sizeof(O) == 4, "staged float4 stores: FP32 output only");
+  constexpr int R = kStripRows, BM = 64, BN = 256, TN = 64, SLD = TN + 4;
+  using Op = MfmaOp<float>;
+  using V = typename Op::V;
+  __shared__ float stage[4 * 16 * SLD];
+  __shared__ double red[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t tilesN = (uint32_t)a.tilesN, groups = (uint32_t)a.tilesM / R;
+  const uint32_t per_batch = groups * tilesN;
+  const uint32_t batch = strip / per_batch;
+  const uint32_t rem = strip - batch * per_batch;
+  const uint32_t g = rem / tilesN, tn = rem - g * tilesN;
+  const int rX = (int)(batch >> (2 * a.nRY));
+  const int rY = (int)(batch & ((1u << (2 * a.nRY)) - 1u));
+  const int64_t M = int64_t(1) << a.logM, N = int64_t(1) << a.logN;
+  const int64_t nw = (int64_t)tn * BN + wave * TN;
+  const float *X = static_cast<const float *>(a.X);
+  const float *Y = static_cast<const float *>(a.Y);
+  const int l16 = lane & 15, lg = lane >> 4;
+  const int nSv = 1 << (2 * a.nS);
+  int2 rrq[4];   // term 4q + lane/16 (rows -1: past the term count)
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int sq = 4 * q + lg;
+    rrq[q] = sq < nSv ? make_int2(row_of(a.mx, sq, rX), row_of(a.my, sq, rY)) : make_int2(-1, -1);
+  }
+  float ay[4][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const bool kok = rrq[q].x >= 0;
+    const float *yr = Y + (int64_t)(kok ? rrq[q].y : 0) * N;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) ay[q][j] = kok ? yr[nw + j * 16 + l16] : 0.f;
+  }
+  float bx[R][4][4];
+  auto load_x = [&](int r) {
+    const int64_t mw = (int64_t)(g * R + r) * BM;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const bool kok = rrq[q].x >= 0;
+      const float *xr = X + (int64_t)(kok ? rrq[q].x : 0) * M;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) bx[r][i][q] = kok ? xr[mw + i * 16 + l16] : 0.f;
+    }
+  };
+  load_x(0);
+  float *st = stage + wave * 16 * SLD;
+  const float sc = MODE == kModeIntermediate ? 1.0f : (float)a.scale;
+  O *Zb = MODE == kModeIntermediate ? static_cast<O *>(a.Z) + (int64_t)batch * M * N : static_cast<O *>(a.Z);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (r + 1 < R) load_x(r + 1);
+    const uint32_t tm = g * R + r;
+    const int64_t mw = (int64_t)tm * BM;
+    double msum = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      V acc[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[j] = V{0, 0, 0, 0};
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j] = Op::run(ay[q][j], bx[r][i][q], acc[j]);
+      // stage the 16 x 64 slice, then write whole 256-byte row segments
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        *reinterpret_cast<float4 *>(st + l16 * SLD + j * 16 + 4 * lg) =
+            make_float4(acc[j][0] * sc, acc[j][1] * sc, acc[j][2] * sc, acc[j][3] * sc);
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#pragma unroll
+      for (int rr = 0; rr < 16; rr += 4) {
+        const int row = rr + lane / 16, col = (lane % 16) * 4;
+        const float4 v = *reinterpret_cast<const float4 *>(st + row * SLD + col);
+        *reinterpret_cast<float4 *>(Zb + (mw + i * 16 + row) * N + nw + col) = v;
+        if (MODE != kModeIntermediate) msum += ((double)v.x + (double)v.y) + ((double)v.z + (double)v.w);
+      }
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    }
+    if (MODE == kModeIntermediate) {
+      if (a.flagZ && tm == 0 && tn == 0 && tid == 0) a.flagZ[batch] = nSv > 0;
+    } else if (a.partials) {
+      const double tot = block_sum_f64(msum, red);
+      if (tid == 0) a.partials[(int64_t)batch * a.tilesM * a.tilesN + (int64_t)tm * tilesN + tn] = tot;
+    }
+  }
+}
+
+template <typename O, int MODE>
+__global__ __launch_bounds__(256) void k_contract_strip(const ContractArgs a) {
+  const int64_t ns = a.nblocks / kStripRows;
+  const uint32_t s = a.xcd_remap ? (uint32_t)xcd_remap(blockIdx.x, ns) : blockIdx.x;
+  contract_small_strip<O, MODE>(a, s);
+}
+
 // ---- launch wrappers: one step per launch, or a work queue over many steps
 template <typename T, typename O, int BM, int BN, int WM, int WN, int MODE, bool SMALL>
 __global__ __launch_bounds__(256) void k_contract(const ContractArgs a) {
@@ -601,6 +710,13 @@ int choose_tile(Acc acc, int nS, int logM, int logN, bool wide_ok) {
 template <typename T, typename O, int MODE, bool SMALL>
 static Status launch_contract_ms(int cfg, const ContractArgs &a, hipStream_t s) {
   const dim3 grid((unsigned)a.nblocks), block(256);
+  if constexpr (SMALL && std::is_same<T, float>::value && std::is_same<O, float>::value &&
+                MODE != kModeFinalDeposit) {
+    // every term kept and whole tiles in pairs of rows: two-tile strips
+    if (cfg == kTileL && !a.flagX && a.logN >= 8 && a.logM >= 7)
+      return launch("contract_small_strip_64x256", k_contract_strip<O, MODE>,
+                    dim3((unsigned)(a.nblocks / kStripRows)), block, 0, s, a);
+  }
   switch (cfg) {
     case kTileL: return launch(SMALL ? "contract_small_64x256" : "contract_64x256", k_contract<T, O, 64, 256, 1, 4, MODE, SMALL>, grid, block, 0, s, a);
     case kTileM: return launch(SMALL ? "contract_small_32x128" : "contract_32x128", k_contract<T, O, 32, 128, 1, 4, MODE, SMALL>, grid, block, 0, s, a);

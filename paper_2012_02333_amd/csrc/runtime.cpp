@@ -32,19 +32,21 @@ TraceState &trace() {
 
 bool trace_on() { return trace().on; }
 
-void trace_begin(const char *name, hipStream_t s, hipEvent_t *start) {
-  (void)name;
+bool trace_events(hipEvent_t *start, hipEvent_t *stop) {
+  *start = *stop = nullptr;
   if (hipEventCreate(start) != hipSuccess) {
     *start = nullptr;
-    return;
+    return false;
   }
-  (void)hipEventRecord(*start, s);
+  if (hipEventCreate(stop) != hipSuccess) {
+    (void)hipEventDestroy(*start);
+    *start = *stop = nullptr;
+    return false;
+  }
+  return true;
 }
 
-void trace_end(const char *name, hipStream_t s, hipEvent_t start) {
-  hipEvent_t stop;
-  if (hipEventCreate(&stop) != hipSuccess) return;
-  (void)hipEventRecord(stop, s);
+void trace_push(const char *name, hipEvent_t start, hipEvent_t stop) {
   std::lock_guard<std::mutex> g(trace().mu);
   trace().pending.push_back({name, start, stop});
 }

@@ -211,3 +211,49 @@ def test_fd_mass_fresh_across_calls(prec, shape):
         masses.append(m)
         dev[0].mul_(2.0)
     assert masses[1] == 2.0 * masses[0] and masses[2] == 2.0 * masses[1], masses
+
+
+def _traced_fd(dev, cut, **kw):
+    with cqc.trace() as tr:
+        p, mass = cqc.reconstruct_fd(dev, cut, **kw)
+        torch.cuda.synchronize()
+    return p, mass, tr.result
+
+
+@pytest.mark.parametrize("out_dt", [torch.float32, torch.float64])
+def test_fd_small_k_two_tile_strips(out_dt):
+    """Two 9-qubit subcircuits, two cuts (16 terms over 512 x 512 outputs):
+    with FP32 output the FP32 small-term contraction runs as two-tile strips
+    (Y operands loaded once per strip); FP32 and FP64 outputs, element by
+    element."""
+    _gpu()
+    cut = W.CutMap(18, [9, 9], [0, 0], [1, 1], list(range(18)))
+    host, dev = to_dev(W.random_entries(cut, seed=61), torch.float32)
+    p, mass, kt = _traced_fd(dev, cqc.CutMap.from_workload(cut), precision="fp32", out_dtype=out_dt)
+    # FP64 output keeps the one-tile kernel (its stores are not staged)
+    assert ("contract_small_strip_64x256" in kt) == (out_dt == torch.float32), kt
+    e64 = oracle_inputs(host)
+    ref = fd.reconstruct(e64, cut)
+    got = p.double().cpu().numpy()
+    assert metrics.rel_l1(got, ref) <= 1e-6
+    ok, info = elementwise_ok(got, ref, abs_bound(e64, cut), U32, sum_terms("fp32", 16))
+    assert ok, info
+    assert abs(float(mass.cpu()) - ref.sum()) <= 1e-6 * np.abs(ref).sum()
+
+
+def test_fd_small_k_strip_chain():
+    """Three 8-qubit subcircuits in a chain, two cuts per boundary: both
+    contractions have 16 terms; the first writes a batched intermediate
+    (16 batches of 256 x 256) through the two-tile strips."""
+    _gpu()
+    cut = W.CutMap(24, [8, 8, 8], [0, 0, 1, 1], [1, 1, 2, 2], list(range(24)))
+    host, dev = to_dev(W.random_entries(cut, seed=62), torch.float32)
+    p, mass, kt = _traced_fd(dev, cqc.CutMap.from_workload(cut), precision="fp32")
+    assert "contract_small_strip_64x256" in kt, kt
+    xs = W.sample_outputs(24, 4096, seed=62)
+    got = p[torch.from_numpy(xs).to("cuda")].double().cpu().numpy()
+    e64 = oracle_inputs(host)
+    ref = fd.reconstruct(e64, cut, xs)
+    assert metrics.rel_l1(got, ref) <= 1e-6
+    ok, info = elementwise_ok(got, ref, abs_bound(e64, cut, xs), U32, sum_terms("fp32", 16 + 16))
+    assert ok, info
