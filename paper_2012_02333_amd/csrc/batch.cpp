@@ -69,7 +69,7 @@ struct BatchBuild {
 };
 
 static int queue_cfg(Acc acc, const Step &st) {
-  const int c = choose_tile(step_acc(acc, st.wide_ok()), (int)st.S.size(), st.logM, st.logN, st.wide_ok());
+  const int c = choose_tile(step_acc(acc, st.wide_ok(), (int)st.S.size()), (int)st.S.size(), st.logM, st.logN, st.wide_ok());
   return c == kTileT ? kTileS : c;
 }
 
@@ -170,7 +170,7 @@ static Status build_batch(const cqc_instance *inst, int32_t n_inst, cqc_dtype in
         }
       }
       const bool small = a.nS <= 2;
-      const Acc sa = step_acc(B.acc, st.wide_ok());
+      const Acc sa = step_acc(B.acc, st.wide_ok(), (int)st.S.size());
       auto key = std::make_tuple(level, (int)a.mode, cfg, (int)small, (int)sa);
       auto it = gidx.find(key);
       if (it == gidx.end()) {

@@ -36,7 +36,7 @@ NetLayout layout_net(const Plan &plan, Acc acc, size_t base) {
   }
   int64_t max_final_blocks = 1;
   for (const auto &st : plan.steps) {
-    int cfg = choose_tile(step_acc(acc, st.wide_ok()), (int)st.S.size(), st.logM, st.logN, st.wide_ok());
+    int cfg = choose_tile(step_acc(acc, st.wide_ok(), (int)st.S.size()), (int)st.S.size(), st.logM, st.logN, st.wide_ok());
     TileShape sh = tile_shape(cfg);
     int64_t tm = ((int64_t(1) << st.logM) + sh.bm - 1) / sh.bm;
     int64_t tn = ((int64_t(1) << st.logN) + sh.bn - 1) / sh.bn;
@@ -74,7 +74,7 @@ bool needs_flags(const NetLayout &L, bool skip_final) {
   if (p.single) return true;   // the flag pass also writes the unit operand
   for (size_t i = 0; i < p.steps.size(); ++i) {
     if (i + 1 == p.steps.size() && skip_final) break;
-    if (p.steps[i].S.size() > 2 || L.acc == Acc::BF16X6 || L.tile[i] == kTileW) return true;
+    if (p.steps[i].S.size() > 2 || L.tile[i] == kTileW) return true;
   }
   return false;
 }
@@ -166,7 +166,7 @@ Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &en
     set_lists(L, i, ws, &a);
     const int mode = !last ? kModeIntermediate : (is_blocked(p, st) ? kModeFinalBlocked : kModeFinalDeposit);
     const bool od = last ? out_double : L.acc == Acc::F64;
-    const Acc sa = step_acc(L.acc, st.wide_ok());
+    const Acc sa = step_acc(L.acc, st.wide_ok(), (int)st.S.size());
     int cfg = L.tile[i], xcd = 0;
     if (!tuned_choice(sa, mode, a.nS <= 2, st.logM, st.logN, a.nS, od, &cfg, &xcd) || !tile_ok(sa, cfg)) {
       cfg = L.tile[i];

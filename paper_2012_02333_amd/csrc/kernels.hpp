@@ -105,10 +105,14 @@ TileShape tile_shape(int cfg);
 int choose_tile(Acc acc, int nS, int logM, int logN, bool wide_ok);
 // Whether the arithmetic has a kernel with this tile configuration.
 bool tile_ok(Acc acc, int cfg);
-// Arithmetic a step of a plan runs in: a BF16X6 step the wide kernel cannot
-// take (an operand with one column: a matrix-vector product, no matrix-core
-// work to win) runs the FP32 form.
-inline Acc step_acc(Acc acc, bool wide_ok) { return acc == Acc::BF16X6 && !wide_ok ? Acc::F32 : acc; }
+// Arithmetic a step of a plan runs in.  A BF16X6 step runs the FP32 form
+// where the split has nothing to win: an operand the wide kernel cannot take
+// (one column: a matrix-vector product), or at most 16 terms (nS <= 2 shared
+// cuts; such a step is bound by its output writes, and FP32 products are at
+// least as accurate as the six BF16 ones).
+inline Acc step_acc(Acc acc, bool wide_ok, int nS) {
+  return acc == Acc::BF16X6 && (!wide_ok || nS <= 2) ? Acc::F32 : acc;
+}
 
 Status launch_row_flags(const FlagArgs &a, int64_t total_blocks, hipStream_t s);
 Status launch_mass_final(const double *partials, int64_t count, double *mass, hipStream_t s);

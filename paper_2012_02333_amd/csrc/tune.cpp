@@ -141,7 +141,7 @@ static Status tune_step(const NetLayout &L, size_t si, char *ws, const std::vect
       a.posY = pack_pos(py);
     }
   }
-  const Acc sa = step_acc(L.acc, st.wide_ok());
+  const Acc sa = step_acc(L.acc, st.wide_ok(), (int)st.S.size());
   const int64_t work = (int64_t(1) << (st.logM + st.logN)) * st.nbatch;
   const int reps = work >= (int64_t(1) << 24) ? 10 : 30;
   hipEvent_t e0, e1;
