@@ -314,18 +314,25 @@ def bench_batch(args, torch, cqc, W):
     cuts = [cqc.CutMap.from_workload(i.cut) for i in insts]
     e32_np = [[E.astype(np.float32) for E in i.entries] for i in insts]
     ents = [[torch.from_numpy(E).cuda() for E in e] for e in e32_np]
-    targets = [torch.from_numpy(W.dirichlet_target(i.n, 1000 + k).astype(np.float32)).cuda()
-               for k, i in enumerate(insts)]
-    batch = cqc.Batch(ents, cuts, precision="fp32")
-    grads_out = [torch.empty_like(t) for t in targets]
-    bwd = cqc.BackwardCall(ents, cuts, grads_out, precision="fp32")
-    floor = torch.tensor(1e-30, dtype=torch.float32, device="cuda")
+    # every instance's p, target and dL/dp are slices of one flat buffer, so
+    # the cross-entropy gradient dL/dp = -t / max(p, 1e-30) of all instances
+    # is two elementwise launches (the negated targets are input data)
+    sizes = [2 ** i.n for i in insts]
+    total = sum(sizes)
+    p_flat = torch.empty(total, dtype=torch.float32, device="cuda")
+    g_flat = torch.empty(total, dtype=torch.float32, device="cuda")
+    tmp_flat = torch.empty(total, dtype=torch.float32, device="cuda")
+    negt_flat = torch.from_numpy(np.concatenate(
+        [-W.dirichlet_target(i.n, 1000 + k).astype(np.float32) for k, i in enumerate(insts)])).cuda()
+    outs = list(torch.split(p_flat, sizes))
+    grads_out = list(torch.split(g_flat, sizes))
+    batch = cqc.Batch(ents, cuts, precision="fp32", outs=outs)
+    bwd = cqc.BatchBackward(batch, grads_out)
 
     def body():
         batch.run()
-        for p, t, g in zip(batch.outs, targets, grads_out):
-            torch.div(t, torch.maximum(p, floor), out=g)
-            g.neg_()
+        torch.clamp_min(p_flat, 1e-30, out=tmp_flat)
+        torch.div(negt_flat, tmp_flat, out=g_flat)
         bwd.run()
     steps = args.steps or 20
     warmup = args.warmup if args.warmup is not None else 3

@@ -129,6 +129,35 @@ int cqc_batch_create(const cqc_instance *inst, int32_t n_inst, cqc_dtype in_t, c
 int cqc_batch_run(cqc_batch batch, hipStream_t stream);
 int cqc_batch_destroy(cqc_batch batch);
 
+/* Adjoint of a prepared batch (the gradient of Section 3.2.3's linear map;
+ * the paper has no gradients): for every instance i, dL/dE_c for each entry
+ * tensor from dL/dp, in a fixed small number of launches.  The forward
+ * operands are the converted entries and intermediate tensors that the
+ * batch's last cqc_batch_run left in the batch's workspace: a run must follow
+ * a cqc_batch_run of the same batch on the same stream, with that workspace
+ * unmodified in between.
+ * grad_out[i]: DEVICE [2^n_i] dL/dp in global output order, dtype of the
+ * batch's outputs.  grad_entries[i][c]: DEVICE, layout and dtype of instance
+ * i's entry tensor c; every element is written (no accumulation).  Both are
+ * bound at creation, like the batch's pointers.
+ * cqc_batch_backward_create plans every instance's adjoint steps, writes its
+ * tables into `workspace` (at least cqc_batch_backward_workspace_size()
+ * bytes, 256-byte aligned, separate from the batch's, kept allocated and
+ * unmodified while the handle exists) and synchronises `stream` once.
+ * cqc_batch_backward_run enqueues only kernel launches (no host
+ * synchronisation, no allocation), so it may be captured into a HIP graph
+ * together with cqc_batch_run.  Results are bitwise reproducible (split-K
+ * partials are added in a fixed order).  An FP64 batch runs the FP64 adjoint;
+ * FP32 and BF16X6 batches run the FP32 one.
+ * cqc_batch_backward_destroy frees the host-side handle only. */
+typedef struct cqc_batch_bwd_s *cqc_batch_bwd;
+int cqc_batch_backward_workspace_size(cqc_batch batch, size_t *bytes);
+int cqc_batch_backward_create(cqc_batch batch, const void *const *grad_out,
+                              void *const *const *grad_entries, void *workspace, size_t ws_bytes,
+                              hipStream_t stream, cqc_batch_bwd *out);
+int cqc_batch_backward_run(cqc_batch_bwd b, hipStream_t stream);
+int cqc_batch_backward_destroy(cqc_batch_bwd b);
+
 /* Dynamic definition (Algorithm 1, Section 4.3).
  * Recursion 1 makes `first_active` (or, if NULL, the first n_active qubits in
  * output order) active; every later recursion picks, among all bins produced

@@ -19,7 +19,7 @@ import torch
 from . import _lib
 from ._lib import CqcError, PREC
 
-__all__ = ["CutMap", "reconstruct_fd", "reconstruct_dd", "reconstruct_backward", "FDCall", "Batch",
+__all__ = ["CutMap", "reconstruct_fd", "reconstruct_dd", "reconstruct_backward", "FDCall", "Batch", "BatchBackward",
            "ReconstructFD", "BackwardCall", "cost", "autotune", "trace", "CqcError", "selftest_mfma", "library_path"]
 
 _DT = {torch.float32: _lib.F32, torch.float64: _lib.F64}
@@ -178,6 +178,53 @@ class Batch(FDCall):
         h = getattr(self, "_h", None)
         if h:
             _lib.lib().cqc_batch_destroy(h)
+            self._h = None
+
+
+class BatchBackward:
+    """Adjoint of a prepared Batch (cqc_batch_backward_create): dL/dE for every
+    instance from dL/dp, using the forward tensors the batch's last run left
+    in its workspace.  grads_out[i] (dL/dp, the batch's output dtype) and the
+    entry gradients are bound at construction; run() enqueues a fixed handful
+    of kernel launches (graph-capturable) and must follow batch.run() on the
+    same stream."""
+
+    def __init__(self, batch, grads_out):
+        if len(grads_out) != batch.n_inst:
+            raise ValueError("one dL/dp per instance")
+        for g, o in zip(grads_out, batch.outs):
+            if g.shape != o.shape or g.dtype != o.dtype or g.device != o.device or not g.is_contiguous():
+                raise ValueError("each dL/dp must match its instance's output (shape, dtype, device, contiguous)")
+        self.batch = batch
+        self.grads_out = list(grads_out)
+        self.grads = [[torch.empty_like(E) for E in e] for e in batch.entries_list]
+        n = batch.n_inst
+        self._gout = (ctypes.c_void_p * n)(*[g.data_ptr() for g in self.grads_out])
+        rows = []
+        for gl in self.grads:
+            r = (ctypes.c_void_p * len(gl))(*[g.data_ptr() for g in gl])
+            rows.append(r)
+        self._rows = rows
+        self._gents = (ctypes.POINTER(ctypes.c_void_p) * n)(
+            *[ctypes.cast(r, ctypes.POINTER(ctypes.c_void_p)) for r in rows])
+        nb = ctypes.c_size_t(0)
+        _lib.check(_lib.lib().cqc_batch_backward_workspace_size(batch._h, ctypes.byref(nb)))
+        self.ws_bytes = int(nb.value)
+        self.ws = torch.zeros(max(self.ws_bytes, 256), dtype=torch.uint8, device=batch.device)
+        h = ctypes.c_void_p(0)
+        s = torch.cuda.current_stream(batch.device).cuda_stream
+        _lib.check(_lib.lib().cqc_batch_backward_create(batch._h, self._gout, self._gents, self.ws.data_ptr(),
+                                                        self.ws_bytes, s, ctypes.byref(h)))
+        self._h = h
+
+    def run(self, stream=None):
+        s = stream if stream is not None else torch.cuda.current_stream(self.batch.device).cuda_stream
+        _lib.check(_lib.lib().cqc_batch_backward_run(self._h, s))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.lib().cqc_batch_backward_destroy(h)
             self._h = None
 
 

@@ -19,6 +19,8 @@ EXPORTS = [
     "cqc_backward_workspace_size", "cqc_reconstruct_backward", "cqc_cost", "cqc_autotune",
     "cqc_trace_enable", "cqc_trace_read", "cqc_status_string", "cqc_last_error_detail",
     "cqc_version", "cqc_selftest_mfma", "cqc_batch_create", "cqc_batch_run", "cqc_batch_destroy",
+    "cqc_batch_backward_workspace_size", "cqc_batch_backward_create", "cqc_batch_backward_run",
+    "cqc_batch_backward_destroy",
 ]
 
 
@@ -86,6 +88,10 @@ def lib():
                                    P(vp)]
     L.cqc_batch_run.argtypes = [vp, vp]
     L.cqc_batch_destroy.argtypes = [vp]
+    L.cqc_batch_backward_workspace_size.argtypes = [vp, P(sz)]
+    L.cqc_batch_backward_create.argtypes = [vp, P(vp), P(P(vp)), vp, sz, vp, P(vp)]
+    L.cqc_batch_backward_run.argtypes = [vp, vp]
+    L.cqc_batch_backward_destroy.argtypes = [vp]
     for name in EXPORTS:
         f = getattr(L, name)
         if f.restype is None or f.restype is ctypes.c_int:

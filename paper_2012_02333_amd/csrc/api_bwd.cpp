@@ -15,12 +15,6 @@
 
 namespace cqc {
 
-struct BwdSide {
-  int64_t kChunk = 16;
-  int32_t kChunks = 1;
-  int64_t P = 1;
-};
-
 struct BwdInstancePlan {
   CutInfo cut;
   NetLayout net;
@@ -33,9 +27,10 @@ struct BwdInstancePlan {
   size_t end = 0;
 };
 
-static BwdSide choose_side(int64_t inner, int64_t rest, int64_t out_elems, int64_t dz_elems, size_t esz) {
+BwdSide choose_bwd_side(int64_t inner, int64_t rest, int64_t out_elems, int64_t dz_elems, size_t esz,
+                        double min_budget) {
   BwdSide s;
-  const double budget = std::max(32.0 * (1 << 20), 0.25 * (double)dz_elems * (double)esz);
+  const double budget = std::max(min_budget, 0.25 * (double)dz_elems * (double)esz);
   int64_t kc = 128;
   if (kc > inner) kc = (inner + 15) / 16 * 16;
   while (true) {
@@ -101,8 +96,8 @@ static Status plan_bwd_instance(const cqc_instance &in, const void *gout, void *
     const int64_t M = int64_t(1) << st.logM, N = int64_t(1) << st.logN;
     const int64_t dz = st.nbatch * M * N;
     const int64_t RXn = int64_t(1) << (2 * st.RX.size()), RYn = int64_t(1) << (2 * st.RY.size());
-    BwdSide bx = choose_side(N, RYn, X.rows() * M, dz, esz);
-    BwdSide by = choose_side(M, RXn, Y.rows() * N, dz, esz);
+    BwdSide bx = choose_bwd_side(N, RYn, X.rows() * M, dz, esz, 32.0 * (1 << 20));
+    BwdSide by = choose_bwd_side(M, RXn, Y.rows() * N, dz, esz, 32.0 * (1 << 20));
     ip.sx.push_back(bx);
     ip.sy.push_back(by);
     part = std::max(part, esz * (size_t)(bx.P * X.rows() * M));

@@ -18,7 +18,50 @@ struct BwdArgs {
   int64_t rowsX, rowsY;
 };
 
+// Split-K choice of one side of an adjoint step: inner-dimension chunk, chunks
+// per rest-label value and partial count P = rest * chunks, the smallest
+// chunk (from 128) whose partials fit max(min_budget, dz bytes / 4).
+struct BwdSide {
+  int64_t kChunk = 16;
+  int32_t kChunks = 1;
+  int64_t P = 1;
+};
+BwdSide choose_bwd_side(int64_t inner, int64_t rest, int64_t out_elems, int64_t dz_elems, size_t esz,
+                        double min_budget);
+
+// Batched adjoint tables (device memory).
+struct BwdReduceDesc {    // out[i] = scale * sum_{p < P} part[p][i], i < count
+  const void *part;       // [P][count], Acc dtype
+  void *out;              // [count], FP64 if out_double else FP32
+  int64_t count, P;
+  double scale;
+  int32_t out_double;
+};
+struct BwdGatherDesc {    // dst[m * N + n] = src[rowoff(m) + coloff(n)], Acc dtype
+  const void *src;
+  void *dst;
+  int32_t logM, logN;
+  BitPos px, py;
+};
+struct BwdQueue {         // one persistent launch over many steps of one kernel shape
+  bool y;                 // dY side (else dX)
+  int sb;                 // label blocks of 16 per block tile (bwd_sb)
+  const BwdArgs *descs;
+  const int64_t *prefix;  // [ndesc + 1] first item of each step
+  int ndesc;
+  unsigned long long *queue;   // zeroed by the run's prep launch
+  int64_t total;
+  uint32_t grid;
+};
+
+int bwd_sb(int nS);
+int64_t bwd_blocks(const BwdArgs &a, bool which_y);
 Status launch_bwd(Acc acc, const BwdArgs &a, bool which_y, hipStream_t s);
+Status launch_bwd_queue(Acc acc, const BwdQueue &q, hipStream_t s);
+Status launch_bwd_reduce_table(Acc acc, const BwdReduceDesc *descs, const int64_t *start, int ndesc,
+                               int64_t blocks, hipStream_t s);
+Status launch_bwd_prep(Acc acc, const BwdGatherDesc *descs, const int64_t *start, int ndesc, int64_t blocks,
+                       unsigned long long *counters, int ncounters, hipStream_t s);
 Status launch_bwd_reduce(Acc acc, const void *part, int64_t count, int64_t P, double scale,
                          void *out, bool out_double, hipStream_t s);
 Status launch_gather_blocked(Acc acc, const void *src, void *dst, int logM, int logN,

@@ -11,12 +11,13 @@
 // column, k <-> the inner index; each lane takes 4 consecutive inner indices
 // with one 16-byte load and feeds them to 4 MFMAs (inner index 4*(lane/16)+t
 // in MFMA t, the same for both operands).
+#include <algorithm>
+
 #include "bwd.hpp"
+#include "kdev.hpp"
 
 namespace cqc {
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 template <typename T> struct BOp;
 template <> struct BOp<float> {
@@ -74,8 +75,7 @@ template <typename T, int SB> struct BwdCfg {
 
 // grid: x = (((p * RXn + rX) * sSuper + ss) * mTiles + mt), p = (rY, k-chunk)
 template <typename T, int SB, int MB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BwdCfg<T, SB>::kWaves, 8)))
-void k_bwd_x(const BwdArgs a) {
+__device__ __forceinline__ void bwd_x_block(const BwdArgs &a, int64_t blk) {
   constexpr bool PF = BwdCfg<T, SB>::kPF;
   using Op = BOp<T>;
   using V = typename Op::V;
@@ -85,7 +85,7 @@ void k_bwd_x(const BwdArgs a) {
   const int RYn = 1 << (2 * a.nRY), RXn = 1 << (2 * a.nRX), SN = 1 << (2 * a.nS);
   const int sSuper = (SN + 16 * SB - 1) / (16 * SB);
   const int64_t mTiles = (M + 64 * MB - 1) / (64 * MB);
-  int64_t b = blockIdx.x;
+  int64_t b = blk;
   const int64_t mt = b % mTiles; b /= mTiles;
   const int ss = (int)(b % sSuper); b /= sSuper;
   const int rX = (int)(b % RXn); b /= RXn;
@@ -168,8 +168,7 @@ void k_bwd_x(const BwdArgs a) {
 
 // grid: x = (((p * RYn + rY) * sSuper + ss) * nTiles + nt), p = (rX, k-chunk over m)
 template <typename T, int SB, int NB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BwdCfg<T, SB>::kWaves, 8)))
-void k_bwd_y(const BwdArgs a) {
+__device__ __forceinline__ void bwd_y_block(const BwdArgs &a, int64_t blk) {
   constexpr bool PF = BwdCfg<T, SB>::kPF;
   using Op = BOp<T>;
   using V = typename Op::V;
@@ -179,7 +178,7 @@ void k_bwd_y(const BwdArgs a) {
   const int RYn = 1 << (2 * a.nRY), SN = 1 << (2 * a.nS);
   const int sSuper = (SN + 16 * SB - 1) / (16 * SB);
   const int64_t nTiles = (N + 64 * NB - 1) / (64 * NB);
-  int64_t b = blockIdx.x;
+  int64_t b = blk;
   const int64_t nt = b % nTiles; b /= nTiles;
   const int ss = (int)(b % sSuper); b /= sSuper;
   const int rY = (int)(b % RYn); b /= RYn;
@@ -256,6 +255,38 @@ void k_bwd_y(const BwdArgs a) {
     }
 }
 
+template <typename T, int SB, int MB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BwdCfg<T, SB>::kWaves, 8)))
+void k_bwd_x(const BwdArgs a) {
+  bwd_x_block<T, SB, MB>(a, blockIdx.x);
+}
+
+template <typename T, int SB, int NB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BwdCfg<T, SB>::kWaves, 8)))
+void k_bwd_y(const BwdArgs a) {
+  bwd_y_block<T, SB, NB>(a, blockIdx.x);
+}
+
+// Many adjoint steps of one shape in one persistent launch: blocks take
+// (step, block) items from an atomic counter; descs[d] in device memory,
+// prefix[d] = first item of step d, queue zeroed before the launch.
+template <typename T, int SB, int MB, bool Y>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BwdCfg<T, SB>::kWaves, 8)))
+void k_bwd_queue(const BwdArgs *descs, const int64_t *prefix, int ndesc, unsigned long long *queue,
+                 int64_t total) {
+  __shared__ int64_t item;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) item = (int64_t)atomicAdd(queue, 1ull);
+    __syncthreads();
+    const int64_t it = item;
+    if (it >= total) return;
+    const int d = find_desc(prefix, ndesc, it);
+    if (Y) bwd_y_block<T, SB, MB>(descs[d], it - prefix[d]);
+    else bwd_x_block<T, SB, MB>(descs[d], it - prefix[d]);
+  }
+}
+
 // out[i] = scale * sum_{p < P} part[p][i].  With G = 8, eight threads share
 // an output: thread g adds the g-th of eight consecutive ranges of partials in
 // ascending p, then the range sums are added in range order (for few outputs
@@ -319,6 +350,59 @@ __global__ __launch_bounds__(256) void k_gather_blocked(const T *src, T *dst, in
   }
 }
 
+// Batched adjoint: every reduction of one level in one launch.  Block b
+// belongs to descriptor d with start[d] <= b < start[d + 1]; its 256 threads
+// each add one output's P partials in ascending p (a fixed order).
+template <typename T>
+__global__ __launch_bounds__(256) void k_bwd_reduce_table(const BwdReduceDesc *descs, const int64_t *start,
+                                                          int ndesc, int64_t blocks) {
+  for (int64_t b = blockIdx.x; b < blocks; b += gridDim.x) {
+    const int d = find_desc(start, ndesc, b);
+    const BwdReduceDesc &D = descs[d];
+    const int64_t i = (b - start[d]) * 256 + threadIdx.x;
+    if (i >= D.count) continue;
+    const T *part = static_cast<const T *>(D.part);
+    T acc = 0;
+    int64_t p = 0;
+    for (; p + 4 <= D.P; p += 4) {
+      const T v0 = part[p * D.count + i], v1 = part[(p + 1) * D.count + i];
+      const T v2 = part[(p + 2) * D.count + i], v3 = part[(p + 3) * D.count + i];
+      acc += v0; acc += v1; acc += v2; acc += v3;
+    }
+    for (; p < D.P; ++p) acc += part[p * D.count + i];
+    const T v = acc * (T)D.scale;
+    if (D.out_double) static_cast<double *>(D.out)[i] = (double)v;
+    else static_cast<float *>(D.out)[i] = (float)v;
+  }
+}
+
+// First launch of a batched adjoint run: zeroes the queue counters of the
+// run's persistent launches (a kernel, not a memset, so the run can be
+// captured in a graph) and gathers every instance's dL/dp that is not in
+// blocked order: dst[m * N + n] = src[rowoff(m) + coloff(n)].
+template <typename T>
+__global__ __launch_bounds__(256) void k_bwd_prep(const BwdGatherDesc *descs, const int64_t *start, int ndesc,
+                                                  int64_t blocks, unsigned long long *counters, int ncounters) {
+  if (blockIdx.x == 0 && (int)threadIdx.x < ncounters) counters[threadIdx.x] = 0ull;
+  for (int64_t b = blockIdx.x; b < blocks; b += gridDim.x) {
+    const int d = find_desc(start, ndesc, b);
+    const BwdGatherDesc &D = descs[d];
+    const int64_t i = (b - start[d]) * 256 + threadIdx.x;
+    if (i >= (int64_t(1) << (D.logM + D.logN))) continue;
+    const int64_t m = i >> D.logN, n = i & ((int64_t(1) << D.logN) - 1);
+    int64_t addr = 0;
+    for (int j = 0; j < D.logM; ++j) {
+      const uint64_t w = D.px.w[j / 10];
+      addr |= ((m >> j) & 1) << ((w >> (6 * (j % 10))) & 63);
+    }
+    for (int j = 0; j < D.logN; ++j) {
+      const uint64_t w = D.py.w[j / 10];
+      addr |= ((n >> j) & 1) << ((w >> (6 * (j % 10))) & 63);
+    }
+    static_cast<T *>(D.dst)[i] = static_cast<const T *>(D.src)[addr];
+  }
+}
+
 static int sb_for(int nS) { return nS <= 2 ? 1 : (nS == 3 ? 4 : 16); }
 
 template <typename T>
@@ -348,6 +432,56 @@ static Status launch_bwd_t(const BwdArgs &a, bool which_y, hipStream_t s) {
 
 Status launch_bwd(Acc acc, const BwdArgs &a, bool which_y, hipStream_t s) {
   return acc == Acc::F32 ? launch_bwd_t<float>(a, which_y, s) : launch_bwd_t<double>(a, which_y, s);
+}
+
+int bwd_sb(int nS) { return sb_for(nS); }
+
+int64_t bwd_blocks(const BwdArgs &a, bool which_y) {
+  const int SN = 1 << (2 * a.nS);
+  const int SB = sb_for(a.nS);
+  const int sSuper = (SN + 16 * SB - 1) / (16 * SB);
+  const int64_t M = int64_t(1) << a.logM, N = int64_t(1) << a.logN;
+  const int64_t RXn = int64_t(1) << (2 * a.nRX), RYn = int64_t(1) << (2 * a.nRY);
+  const int B = SB == 16 ? 1 : 4;
+  if (!which_y) return (RYn * a.kChunks) * RXn * sSuper * ((M + 64 * B - 1) / (64 * B));
+  return (RXn * a.kChunks) * RYn * sSuper * ((N + 64 * B - 1) / (64 * B));
+}
+
+template <typename T>
+static Status launch_bwd_queue_t(const BwdQueue &q, hipStream_t s) {
+  const dim3 g(q.grid), b(256);
+  const char *nm = q.y ? "bwd_y_queue" : "bwd_x_queue";
+  if (q.y) {
+    if (q.sb == 1) return launch(nm, k_bwd_queue<T, 1, 4, true>, g, b, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
+    if (q.sb == 4) return launch(nm, k_bwd_queue<T, 4, 4, true>, g, b, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
+    return launch(nm, k_bwd_queue<T, 16, 1, true>, g, b, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
+  }
+  if (q.sb == 1) return launch(nm, k_bwd_queue<T, 1, 4, false>, g, b, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
+  if (q.sb == 4) return launch(nm, k_bwd_queue<T, 4, 4, false>, g, b, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
+  return launch(nm, k_bwd_queue<T, 16, 1, false>, g, b, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
+}
+
+Status launch_bwd_queue(Acc acc, const BwdQueue &q, hipStream_t s) {
+  if (q.total <= 0) return Status::ok();
+  return acc == Acc::F32 ? launch_bwd_queue_t<float>(q, s) : launch_bwd_queue_t<double>(q, s);
+}
+
+Status launch_bwd_reduce_table(Acc acc, const BwdReduceDesc *descs, const int64_t *start, int ndesc,
+                               int64_t blocks, hipStream_t s) {
+  if (blocks <= 0) return Status::ok();
+  const dim3 g((unsigned)std::min<int64_t>(blocks, 16384)), b(256);
+  if (acc == Acc::F32)
+    return launch("bwd_reduce_table", k_bwd_reduce_table<float>, g, b, 0, s, descs, start, ndesc, blocks);
+  return launch("bwd_reduce_table", k_bwd_reduce_table<double>, g, b, 0, s, descs, start, ndesc, blocks);
+}
+
+Status launch_bwd_prep(Acc acc, const BwdGatherDesc *descs, const int64_t *start, int ndesc, int64_t blocks,
+                       unsigned long long *counters, int ncounters, hipStream_t s) {
+  if (ncounters > 256) return Status::fail(CQC_ERR_UNSUPPORTED, "too many queue counters");
+  const dim3 g((unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks, 16384))), b(256);
+  if (acc == Acc::F32)
+    return launch("bwd_prep", k_bwd_prep<float>, g, b, 0, s, descs, start, ndesc, blocks, counters, ncounters);
+  return launch("bwd_prep", k_bwd_prep<double>, g, b, 0, s, descs, start, ndesc, blocks, counters, ncounters);
 }
 
 template <typename T, typename O>
