@@ -255,16 +255,130 @@ __device__ __forceinline__ void bwd_y_block(const BwdArgs &a, int64_t blk) {
     }
 }
 
+// 64 label rows x 256 outputs per block (four waves of 64), the label rows'
+// 32-index slices staged in LDS once per block (double-buffered) instead of
+// loaded by every wave; the dL/dZ operand per wave from global memory, one
+// 16-index half ahead.  Y: the dY side (label rows of X over m, dZ columns);
+// else the dX side (label rows of Y over n, dZ rows).
+template <bool YS>
+__device__ __forceinline__ void bwd_block_staged(const BwdArgs &a, int64_t blk) {
+  constexpr int SB = 4, OB = 4, KS = 32, LD = KS + 4;
+  using Op = BOp<float>;
+  using V = typename Op::V;
+  __shared__ float ls[2][64][LD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, lg = lane >> 4;
+  const int64_t M = int64_t(1) << a.logM, N = int64_t(1) << a.logN;
+  const int RYn = 1 << (2 * a.nRY), RXn = 1 << (2 * a.nRX), SN = 1 << (2 * a.nS);
+  const int sSuper = (SN + 16 * SB - 1) / (16 * SB);
+  const int64_t OUT = YS ? N : M, INNER = YS ? M : N;
+  const int64_t oTiles = (OUT + 64 * OB - 1) / (64 * OB);
+  int64_t b = blk;
+  const int64_t ot = b % oTiles; b /= oTiles;
+  const int ss = (int)(b % sSuper); b /= sSuper;
+  const int rO = (int)(b % (YS ? RYn : RXn)); b /= (YS ? RYn : RXn);
+  const int64_t p = b;
+  const int rI = (int)(p / a.kChunks), kc = (int)(p % a.kChunks);
+  const int rX = YS ? rI : rO, rY = YS ? rO : rI;
+  const int64_t k0 = (int64_t)kc * a.kChunk;
+  const int64_t k1 = INNER < k0 + a.kChunk ? INNER : k0 + a.kChunk;
+  const int64_t ow = ot * 64 * OB + wave * 16 * OB;
+  const float *L = static_cast<const float *>(YS ? a.X : a.Y);
+  const float *dZ = static_cast<const float *>(a.dZ) + ((int64_t)rX * RYn + rY) * M * N;
+  // staging: thread t owns label row t >> 2, eight inner indices at 8 (t & 3)
+  const int sr = tid >> 2, sq = tid & 3;
+  const int s_st = ss * 64 + sr;
+  const bool st_ok = s_st < SN;
+  const float *lrow = L + (int64_t)(st_ok ? brow_of(YS ? a.mx : a.my, s_st, YS ? rX : rY) : 0) * INNER;
+  float g[8];
+  auto gload = [&](int64_t n0) {
+    const int64_t c = n0 + 8 * sq;
+    load4m<float>(lrow, c, k1, g);
+    load4m<float>(lrow, c + 4, k1, g + 4);
+    if (!st_ok)
+      for (int e = 0; e < 8; ++e) g[e] = 0.f;
+  };
+  auto sstore = [&](int buf) {
+    *reinterpret_cast<float4 *>(&ls[buf][sr][8 * sq]) = make_float4(g[0], g[1], g[2], g[3]);
+    *reinterpret_cast<float4 *>(&ls[buf][sr][8 * sq + 4]) = make_float4(g[4], g[5], g[6], g[7]);
+  };
+  float bv[2][OB][4];
+  auto bload = [&](int h, int64_t n0) {
+    const int64_t c = n0 + 4 * lg;
+#pragma unroll
+    for (int ob = 0; ob < OB; ++ob) {
+      const int64_t o = ow + ob * 16 + l16;
+      if (!YS) {
+        if (o < OUT) load4m<float>(dZ + o * N, c, k1, bv[h][ob]);
+        else
+          for (int t = 0; t < 4; ++t) bv[h][ob][t] = 0.f;
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) bv[h][ob][t] = (o < OUT && c + t < k1) ? dZ[(c + t) * N + o] : 0.f;
+      }
+    }
+  };
+  V acc[SB][OB];
+#pragma unroll
+  for (int i = 0; i < SB; ++i)
+#pragma unroll
+    for (int j = 0; j < OB; ++j) acc[i][j] = V{0, 0, 0, 0};
+  auto half = [&](int cur, int h) {
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) {
+      const float4 q = *reinterpret_cast<const float4 *>(&ls[cur][sb * 16 + l16][16 * h + 4 * lg]);
+      const float av[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int ob = 0; ob < OB; ++ob) acc[sb][ob] = Op::run(av[t], bv[h][ob][t], acc[sb][ob]);
+    }
+  };
+  if (k0 < k1) {
+    gload(k0);
+    sstore(0);
+    bload(0, k0);
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int64_t n0 = k0; n0 < k1; n0 += KS) {
+    const bool more = n0 + KS < k1;
+    const bool h1 = n0 + 16 < k1;
+    if (more) gload(n0 + KS);
+    if (h1) bload(1, n0 + 16);
+    half(cur, 0);
+    if (more) bload(0, n0 + KS);
+    if (h1) half(cur, 1);
+    if (more) sstore(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+  float *part = static_cast<float *>(a.part) + p * (YS ? a.rowsY : a.rowsX) * OUT;
+#pragma unroll
+  for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+    for (int ob = 0; ob < OB; ++ob) {
+      const int64_t o = ow + ob * 16 + l16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int s = (ss * SB + sb) * 16 + 4 * lg + r;
+        if (s < SN && o < OUT) part[(int64_t)brow_of(YS ? a.my : a.mx, s, rO) * OUT + o] = acc[sb][ob][r];
+      }
+    }
+}
+
 template <typename T, int SB, int MB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BwdCfg<T, SB>::kWaves, 8)))
 void k_bwd_x(const BwdArgs a) {
-  bwd_x_block<T, SB, MB>(a, blockIdx.x);
+  if constexpr (sizeof(T) == 4 && SB == 4 && MB == 4) bwd_block_staged<false>(a, blockIdx.x);
+  else bwd_x_block<T, SB, MB>(a, blockIdx.x);
 }
 
 template <typename T, int SB, int NB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BwdCfg<T, SB>::kWaves, 8)))
 void k_bwd_y(const BwdArgs a) {
-  bwd_y_block<T, SB, NB>(a, blockIdx.x);
+  if constexpr (sizeof(T) == 4 && SB == 4 && NB == 4) bwd_block_staged<true>(a, blockIdx.x);
+  else bwd_y_block<T, SB, NB>(a, blockIdx.x);
 }
 
 // Many adjoint steps of one shape in one persistent launch: blocks take
@@ -282,8 +396,12 @@ void k_bwd_queue(const BwdArgs *descs, const int64_t *prefix, int ndesc, unsigne
     const int64_t it = item;
     if (it >= total) return;
     const int d = find_desc(prefix, ndesc, it);
-    if (Y) bwd_y_block<T, SB, MB>(descs[d], it - prefix[d]);
-    else bwd_x_block<T, SB, MB>(descs[d], it - prefix[d]);
+    if constexpr (sizeof(T) == 4 && SB == 4 && MB == 4) {
+      bwd_block_staged<Y>(descs[d], it - prefix[d]);
+    } else {
+      if (Y) bwd_y_block<T, SB, MB>(descs[d], it - prefix[d]);
+      else bwd_x_block<T, SB, MB>(descs[d], it - prefix[d]);
+    }
   }
 }
 
@@ -403,7 +521,12 @@ __global__ __launch_bounds__(256) void k_bwd_prep(const BwdGatherDesc *descs, co
   }
 }
 
-static int sb_for(int nS) { return nS <= 2 ? 1 : (nS == 3 ? 4 : 16); }
+// Label blocks of 16 per block tile.  Three and four shared cuts take 64
+// labels per tile: with 256 every wave of a block loads the same 256 operand
+// rows per inner step, and the operand traffic, not the matrix cores, sets the
+// time (measured 1.5x slower than 64 at four cuts, where dL/dZ is read four
+// times instead of once).  Five and more keep 256 (dL/dZ would be read 16 times).
+static int sb_for(int nS) { return nS <= 2 ? 1 : (nS <= 4 ? 4 : 16); }
 
 template <typename T>
 static Status launch_bwd_t(const BwdArgs &a, bool which_y, hipStream_t s) {

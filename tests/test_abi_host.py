@@ -119,3 +119,17 @@ def test_cost_eq14():
     assert a.value == 4 ** 6 * (2 ** 18 + 2 ** 30)
     # library plan: A-B over 3 labels into 64 x 2^18, then 2^18 x 2^12 over 3 labels
     assert b.value == 64 * 64 * 2 ** 18 + 64 * 2 ** 30
+
+
+def test_batch_backward_rejects_null_handles():
+    """The batched adjoint's entry points refuse a null batch, handle or output
+    pointer with CQC_ERR_INVALID_ARG before touching any device memory."""
+    L = _lib.lib()
+    nb = ctypes.c_size_t(0)
+    assert L.cqc_batch_backward_workspace_size(None, ctypes.byref(nb)) == 1
+    assert L.cqc_batch_backward_create(None, None, None, None, 0, None, None) == 1
+    h = ctypes.c_void_p(0)
+    assert L.cqc_batch_backward_create(None, None, None, None, 0, None, ctypes.byref(h)) == 1
+    assert L.cqc_batch_backward_run(None, None) == 1
+    assert L.cqc_batch_backward_destroy(None) == 0
+    assert L.cqc_batch_run(None, None) != 0
