@@ -21,6 +21,7 @@ struct cqc_batch_s {
   struct Group {
     int level, mode, cfg;
     bool small;
+    bool strip;     // two-tile strips of the FP32 small-term kernel
     cqc::Acc acc;   // arithmetic of the group's steps
     const cqc::ContractArgs *descs;
     const int64_t *prefix;

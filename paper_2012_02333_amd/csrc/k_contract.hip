@@ -431,7 +431,6 @@ __device__ __forceinline__ void contract_small_tile(const ContractArgs &a, uint3
 // start together, which spreads the operand fetch at the start of the launch
 // over the first tile's stores.  One partial mass per tile, as in the
 // one-tile kernel.
-constexpr int kStripRows = 2;
 
 template <typename O, int MODE>
 __device__ __forceinline__ void contract_small_strip(const ContractArgs &a, uint32_t strip) {
@@ -520,6 +519,21 @@ __device__ __forceinline__ void contract_small_strip(const ContractArgs &a, uint
       const double tot = block_sum_f64(msum, red);
       if (tid == 0) a.partials[(int64_t)batch * a.tilesM * a.tilesN + (int64_t)tm * tilesN + tn] = tot;
     }
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_contract_strip_queue(const ContractArgs *descs, const int64_t *prefix,
+                                                              int ndesc, unsigned long long *queue, int64_t total) {
+  __shared__ int64_t item;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) item = (int64_t)atomicAdd(queue, 1ull);
+    __syncthreads();
+    const int64_t it = item;
+    if (it >= total) return;
+    const int d = find_desc(prefix, ndesc, it);
+    contract_small_strip<float, MODE>(descs[d], (uint32_t)(it - prefix[d]));
   }
 }
 
@@ -740,6 +754,17 @@ static Status launch_queue_t(int cfg, const QueueLaunch &q, hipStream_t s) {
     case kTileM: return launch(nm, k_contract_queue<T, T, 32, 128, 1, 4, MODE, SMALL>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
     default: return launch(nm, k_contract_queue<T, T, 16, 64, 1, 4, MODE, SMALL>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
   }
+}
+
+Status launch_contract_strip_queue(int mode, const QueueLaunch &q, hipStream_t s) {
+  const dim3 grid(q.grid), block(256);
+  if (mode == kModeIntermediate)
+    return launch("contract_strip_queue", k_contract_strip_queue<kModeIntermediate>, grid, block, 0, s, q.descs,
+                  q.prefix, q.ndesc, q.queue, q.total);
+  if (mode == kModeFinalBlocked)
+    return launch("contract_strip_queue", k_contract_strip_queue<kModeFinalBlocked>, grid, block, 0, s, q.descs,
+                  q.prefix, q.ndesc, q.queue, q.total);
+  return Status::fail(CQC_ERR_UNSUPPORTED, "two-tile strips need blocked or intermediate output");
 }
 
 template <typename T, int MODE>

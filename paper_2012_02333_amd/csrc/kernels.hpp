@@ -131,6 +131,11 @@ struct QueueLaunch {
   int64_t btotal;          //   and the total (one label-list block per batch entry)
 };
 Status launch_contract_queue(Acc acc, int mode, int cfg, bool small, const QueueLaunch &q, hipStream_t s);
+// Two-tile strips of the 64 x 256 FP32 small-term kernel (FP32 output, blocked
+// or intermediate mode, no row flags): a step of nblocks tiles is nblocks /
+// kStripRows queue items.
+constexpr int kStripRows = 2;
+Status launch_contract_strip_queue(int mode, const QueueLaunch &q, hipStream_t s);
 
 // Batched row flags (descriptor table in device memory, block_start = prefix)
 // and per-instance mass reductions; the flag pass also zeroes `counters`.

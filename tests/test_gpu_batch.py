@@ -100,3 +100,28 @@ def test_batch_graph_replay():
         for k in range(len(eager)):
             assert torch.equal(batch.outs[k], eager[k]), (rep, k)
         assert torch.equal(batch.mass, eager_mass), rep
+
+
+def test_batch_strips_equal_single_calls():
+    """Instances whose small-term steps run as two-tile strips in the batch
+    (FP32, no row flags: two subcircuits with two cuts, a chain with two cuts
+    per boundary) next to one whose plan needs row flags (three cuts): every
+    output bit for bit the one-instance call's, and the strip queue ran."""
+    _gpu()
+    C = W.CutMap
+    cuts_w = [C(18, [9, 9], [0, 0], [1, 1], list(range(18))),
+              C(24, [8, 8, 8], [0, 0, 1, 1], [1, 1, 2, 2], list(range(24))),
+              C(16, [8, 8], [0, 0, 0], [1, 1, 1], list(range(16))),
+              C(17, [8, 9], [0], [1], list(range(17)))]
+    ents = [[torch.from_numpy(E.astype(np.float32)).cuda() for E in W.random_entries(c, seed=700 + i)]
+            for i, c in enumerate(cuts_w)]
+    cuts = [cqc.CutMap.from_workload(c) for c in cuts_w]
+    batch = cqc.Batch(ents, cuts, precision="fp32")
+    with cqc.trace() as tr:
+        batch.run()
+        torch.cuda.synchronize()
+    assert "contract_strip_queue" in tr.result, tr.result
+    for k in range(len(cuts)):
+        p1, m1 = cqc.reconstruct_fd(ents[k], cuts[k], precision="fp32")
+        assert torch.equal(batch.outs[k], p1), k
+        assert abs(float(batch.mass[k]) - float(m1)) <= 1e-12 * max(1.0, abs(float(m1))), k
