@@ -42,7 +42,8 @@ struct BatchBuild {
 };
 
 static int queue_cfg(Acc acc, const Step &st) {
-  const int c = choose_tile(step_acc(acc, st.wide_ok(), (int)st.S.size()), (int)st.S.size(), st.logM, st.logN, st.wide_ok());
+  const int c = choose_tile(step_acc(acc, st.wide_ok(), (int)st.S.size()), (int)st.S.size(), st.logM, st.logN, st.wide_ok(),
+                            st.nbatch);
   return c == kTileT ? kTileS : c;
 }
 

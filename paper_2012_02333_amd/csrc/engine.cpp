@@ -36,7 +36,8 @@ NetLayout layout_net(const Plan &plan, Acc acc, size_t base) {
   }
   int64_t max_final_blocks = 1;
   for (const auto &st : plan.steps) {
-    int cfg = choose_tile(step_acc(acc, st.wide_ok(), (int)st.S.size()), (int)st.S.size(), st.logM, st.logN, st.wide_ok());
+    int cfg = choose_tile(step_acc(acc, st.wide_ok(), (int)st.S.size()), (int)st.S.size(), st.logM, st.logN,
+                          st.wide_ok(), st.nbatch);
     TileShape sh = tile_shape(cfg);
     int64_t tm = ((int64_t(1) << st.logM) + sh.bm - 1) / sh.bm;
     int64_t tn = ((int64_t(1) << st.logN) + sh.bn - 1) / sh.bn;

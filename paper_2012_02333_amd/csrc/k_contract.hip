@@ -710,11 +710,15 @@ bool tile_ok(Acc acc, int cfg) {
   return true;
 }
 
-int choose_tile(Acc acc, int nS, int logM, int logN, bool wide_ok) {
+int choose_tile(Acc acc, int nS, int logM, int logN, bool wide_ok, int64_t nbatch) {
   const int64_t M = int64_t(1) << logM, N = int64_t(1) << logN;
   if (acc == Acc::BF16X6) return kTileW;
-  // long term sums over large tiles are compute-bound: LDS-staged operands
-  if (acc == Acc::F32 && wide_ok && nS >= 3 && M >= 128 && N >= 128) return kTileW;
+  // long term sums over large tiles are compute-bound: LDS-staged operands, on
+  // steps with at least 256 tiles of 128 x 128 (fewer leave most of the chip
+  // idle on the persistent kernel: the 64 x 256 register kernel then wins, e.g.
+  // 2^20 dynamic-definition bins, measured 25% faster per query)
+  if (acc == Acc::F32 && wide_ok && nS >= 3 && M >= 128 && N >= 128 && M * N * nbatch >= (int64_t(1) << 22))
+    return kTileW;
   if (M >= 64 && N >= 256) return kTileL;
   if (N < 64 && M >= 256) return kTileT;
   if (M >= 32 && N >= 128) return kTileM;

@@ -102,7 +102,9 @@ struct TileShape { int bm, bn; };
 TileShape tile_shape(int cfg);
 // Built-in rule (the autotuner's cache takes precedence where it has an entry).
 // wide_ok: both operands fit the wide kernel's addressing (wide_fits).
-int choose_tile(Acc acc, int nS, int logM, int logN, bool wide_ok);
+// nbatch: batch entries of the step (the wide kernel needs enough 128 x 128
+// tiles over all of them to fill the chip).
+int choose_tile(Acc acc, int nS, int logM, int logN, bool wide_ok, int64_t nbatch);
 // Whether the arithmetic has a kernel with this tile configuration.
 bool tile_ok(Acc acc, int cfg);
 // Arithmetic a step of a plan runs in.  A BF16X6 step runs the FP32 form

@@ -153,7 +153,7 @@ static Status tune_step(const NetLayout &L, size_t si, char *ws, const std::vect
     const TileShape sh = tile_shape(cfg);
     const int64_t M = int64_t(1) << st.logM, N = int64_t(1) << st.logN;
     // skip shapes that would leave most of every tile empty
-    if ((M < sh.bm || N < sh.bn) && cfg != kTileS && cfg != choose_tile(sa, a.nS, st.logM, st.logN, st.wide_ok())) continue;
+    if ((M < sh.bm || N < sh.bn) && cfg != kTileS && cfg != choose_tile(sa, a.nS, st.logM, st.logN, st.wide_ok(), st.nbatch)) continue;
     if (cfg == kTileW && !st.wide_ok()) continue;
     for (int xcd = 0; xcd < 2; ++xcd) {
       a.tilesM = (int)((M + sh.bm - 1) / sh.bm);

@@ -1,6 +1,8 @@
 """GPU parity of the LDS-staged wide contraction kernel (FP32 and BF16X6 forms)
 on the shapes that reach it: long term sums (three or more shared cut labels)
-over operands at least 128 columns wide, and any shape in the BF16X6 form.
+over operands at least 128 columns wide with at least 2^22 outputs per step
+(fewer run the register kernel in FP32: the same cases then check that one),
+and any shape in the BF16X6 form.
 
 Cases cover more live labels than one 256-label compaction chunk, chunks left
 partial by early termination, scattered (bit-deposit) output orders, chained
@@ -111,4 +113,47 @@ def test_bf16x6_split_is_exact_enough():
     e64 = oracle_inputs(host)
     ref = fd.reconstruct(e64, cut)
     ok, info = elementwise_ok(p.double().cpu().numpy(), ref, abs_bound(e64, cut), U32, sum_terms("bf16x6", 64))
+    assert ok, info
+
+
+def _wide_ran(kt, final=True):
+    return any(k.startswith("wide_f32_final" if final else "wide_f32_inter") for k in kt)
+
+
+def test_wide_fp32_pair_at_2p22_outputs():
+    """Two 11-qubit subcircuits, three cuts: 2^22 outputs reach the FP32 wide
+    kernel; sampled outputs against the oracle, plus the FP64 mass."""
+    _gpu()
+    cut = W.CutMap(22, [11, 11], [0, 0, 0], [1, 1, 1], list(range(22)))
+    host, dev = to_dev(W.random_entries(cut, seed=47), torch.float32)
+    with cqc.trace() as tr:
+        p, mass = cqc.reconstruct_fd(dev, cqc.CutMap.from_workload(cut), precision="fp32")
+        torch.cuda.synchronize()
+    assert _wide_ran(tr.result), tr.result
+    xs = W.sample_outputs(22, 4096, seed=47)
+    got = p[torch.from_numpy(xs).to("cuda")].double().cpu().numpy()
+    e64 = oracle_inputs(host)
+    ref = fd.reconstruct(e64, cut, xs)
+    assert metrics.rel_l1(got, ref) <= 1e-6
+    ok, info = elementwise_ok(got, ref, abs_bound(e64, cut, xs), U32, sum_terms("fp32", 64))
+    assert ok, info
+
+
+def test_wide_fp32_chain_intermediate_and_final():
+    """Three 8-qubit subcircuits, three cuts per boundary: the intermediate
+    (64 batches of 256 x 256) and the final contraction (2^24 outputs) both run
+    on the FP32 wide kernel; sampled outputs against the oracle."""
+    _gpu()
+    cut = W.CutMap(24, [8, 8, 8], [0, 0, 0, 1, 1, 1], [1, 1, 1, 2, 2, 2], list(range(24)))
+    host, dev = to_dev(W.random_entries(cut, seed=48), torch.float32)
+    with cqc.trace() as tr:
+        p, mass = cqc.reconstruct_fd(dev, cqc.CutMap.from_workload(cut), precision="fp32")
+        torch.cuda.synchronize()
+    assert _wide_ran(tr.result) and _wide_ran(tr.result, final=False), tr.result
+    xs = W.sample_outputs(24, 4096, seed=48)
+    got = p[torch.from_numpy(xs).to("cuda")].double().cpu().numpy()
+    e64 = oracle_inputs(host)
+    ref = fd.reconstruct(e64, cut, xs)
+    assert metrics.rel_l1(got, ref) <= 1e-6
+    ok, info = elementwise_ok(got, ref, abs_bound(e64, cut, xs), U32, sum_terms("fp32", 64 + 64))
     assert ok, info
