@@ -117,3 +117,51 @@ def subcircuit_entries(circ, sub, form="pauli"):
 
 def circuit_entries(circ, form="pauli"):
     return [subcircuit_entries(circ, s, form) for s in circ.subcircuits()]
+
+
+def variant_tensor(circ, sub):
+    """Every variant distribution of a subcircuit stacked as
+    [4^k_in][3^k_out][2^f][2^k_out]: initialisation combination (per incoming
+    cut 0 |0>, 1 |1>, 2 |+>, 3 |+i>, first cut the most significant base-4
+    digit), measurement-basis combination (per outgoing cut 0 computational,
+    1 X, 2 Y, first cut the most significant base-3 digit), output bits, then
+    the measured cut bits (first outgoing cut the most significant bit)."""
+    k_in, k_out = len(sub.q_in), len(sub.q_out)
+    V = np.zeros((4 ** k_in, 3 ** k_out, 2 ** sub.f, 2 ** k_out))
+    for ii, inits in enumerate(itertools.product(range(4), repeat=k_in)):
+        for bi, bases in enumerate(itertools.product(("Z", "X", "Y"), repeat=k_out)):
+            V[ii, bi] = variant_distribution(circ, sub, inits, bases)
+    return V
+
+
+def entries_from_variants(V, cut_kind):
+    """Pauli-form entry tensor from stacked variant distributions (Sections
+    3.1-3.2): for every label assignment, the outgoing cuts' labels pick the
+    measurement bases and weight the measured bits by Eq. 3; the incoming cuts'
+    labels combine the initialisations by the p_{2,i} rule.
+
+    V: [4^k_in][3^k_out][2^f][2^k_out] as variant_tensor.  cut_kind: per
+    incident cut in ascending cut id, 0 if initialised here (incoming), 1 if
+    measured here (outgoing); the i-th incoming / outgoing cut of that list is
+    the i-th digit of V's initialisation / basis axes.  Row of E = base-4
+    number of the labels (I=0, X=1, Y=2, Z=3) in cut_kind's order, first most
+    significant.
+    """
+    cut_kind = list(cut_kind)
+    k_in, k_out = cut_kind.count(0), cut_kind.count(1)
+    assert V.shape[0] == 4 ** k_in and V.shape[1] == 3 ** k_out and V.shape[3] == 2 ** k_out
+    basis_digit = {0: 0, 3: 0, 1: 1, 2: 2}
+    E = np.zeros((4 ** (k_in + k_out), V.shape[2]))
+    for row, labels in enumerate(itertools.product(range(4), repeat=k_in + k_out)):
+        l_in = [l for l, kd in zip(labels, cut_kind) if kd == 0]
+        l_out = [l for l, kd in zip(labels, cut_kind) if kd == 1]
+        bi = 0
+        for l in l_out:
+            bi = 3 * bi + basis_digit[l]
+        for ii, inits in enumerate(itertools.product(range(4), repeat=k_in)):
+            coef = 1.0
+            for lab, init in zip(l_in, inits):
+                coef *= _DOWN_PAULI[lab][init]
+            if coef != 0.0:
+                E[row] += coef * attribute(V[ii, bi], l_out)
+    return E

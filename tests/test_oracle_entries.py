@@ -84,3 +84,59 @@ def test_cut_map_shapes():
     assert [cut.entry_shape(c) for c in range(3)] == [(64, 512), (4096, 512), (64, 4096)]
     assert sorted(cut.out_qubit) == list(range(30))
     assert [s.d for s in circ.subcircuits()] == [12, 12, 12]
+
+
+# ---- entries from stacked variant distributions (the input of on-device
+# entry construction)
+
+@pytest.mark.parametrize("own,bridges,layers", SHAPES[:5])
+def test_entries_from_variants_equal_paper_route(own, bridges, layers):
+    """From the stacked simulated variants, with the chain's cut order (incoming
+    cuts before outgoing ones), the entries equal the paper route (itself
+    pinned to the independent operator route above)."""
+    circ = W.bridged_chain(own, bridges, layers, seed=13)
+    for sub in circ.subcircuits():
+        V = variants.variant_tensor(circ, sub)
+        kinds = [0] * len(sub.q_in) + [1] * len(sub.q_out)
+        E = variants.entries_from_variants(V, kinds)
+        ref = variants.subcircuit_entries(circ, sub)
+        assert E.shape == ref.shape
+        assert np.max(np.abs(E - ref)) < 1e-13
+
+
+def test_entries_from_variants_row_sums_any_distribution():
+    """For any normalised variant distributions (finite shots included): a row
+    whose outgoing labels are all I sums to 2^k_in if every incoming label is
+    I and to 0 otherwise (the I, Z, X, Y initialisation weights sum to 2, 0,
+    0, 0)."""
+    V = W.random_variants(2, 2, 4, seed=3)
+    Vs = W.sample_variant_shots(V, 1000, seed=4)
+    for VV in (V, Vs):
+        E = variants.entries_from_variants(VV, [0, 1, 0, 1])
+        for row in range(E.shape[0]):
+            d = [(row >> (2 * (3 - t))) & 3 for t in range(4)]   # labels of cuts 0..3
+            if d[1] == 0 and d[3] == 0:
+                want = 4.0 if d[0] == 0 and d[2] == 0 else 0.0
+                assert abs(E[row].sum() - want) < 1e-12, (row, d)
+
+
+def test_entries_from_variants_cut_order_permutes_rows():
+    """Listing the same cuts in another id order permutes the label digits of
+    the rows and nothing else."""
+    V = W.random_variants(1, 2, 3, seed=6)
+    a = variants.entries_from_variants(V, [0, 1, 1]).reshape(4, 4, 4, -1)   # (in, out0, out1)
+    b = variants.entries_from_variants(V, [1, 0, 1]).reshape(4, 4, 4, -1)   # (out0, in, out1)
+    assert np.array_equal(np.transpose(a, (1, 0, 2, 3)), b)
+
+
+def test_entries_from_variants_single_cut_by_hand():
+    """One measured cut (k_out = 1) and no incoming cut: rows I, X, Y, Z are
+    p0 + p1 in the computational basis, p0 - p1 in the X and Y bases, and
+    p0 - p1 in the computational basis (Eq. 3 written out)."""
+    V = W.random_variants(0, 1, 2, seed=8)   # [1][3][4][2]
+    E = variants.entries_from_variants(V, [1])
+    comp, xb, yb = V[0, 0], V[0, 1], V[0, 2]
+    assert np.allclose(E[0], comp[:, 0] + comp[:, 1], atol=0, rtol=0)
+    assert np.allclose(E[1], xb[:, 0] - xb[:, 1], atol=0, rtol=0)
+    assert np.allclose(E[2], yb[:, 0] - yb[:, 1], atol=0, rtol=0)
+    assert np.allclose(E[3], comp[:, 0] - comp[:, 1], atol=0, rtol=0)

@@ -119,3 +119,25 @@ def random_entries(cut: CutMap, seed, zero_rows=(), scale=None):
     for (c, row) in zero_rows:
         ents[c][row, :] = 0.0
     return ents
+
+
+def sample_variant_shots(V, shots, seed):
+    """Finite-shot variant distributions: every variant's distribution over
+    (output bits, measured cut bits) of V [4^k_in][3^k_out][2^f][2^k_out]
+    replaced by seeded multinomial counts / shots."""
+    rng = np.random.default_rng(seed)
+    out = np.empty_like(V)
+    for i in range(V.shape[0]):
+        for j in range(V.shape[1]):
+            p = np.clip(V[i, j].ravel(), 0.0, None)
+            p = p / p.sum()
+            out[i, j] = (rng.multinomial(shots, p) / shots).reshape(V.shape[2:])
+    return out
+
+
+def random_variants(k_in, k_out, f, seed):
+    """Seeded synthetic variant distributions [4^k_in][3^k_out][2^f][2^k_out]:
+    each variant a normalised Exp(1) draw over its 2^(f + k_out) outcomes."""
+    rng = np.random.default_rng(seed)
+    V = rng.exponential(1.0, size=(4 ** k_in, 3 ** k_out, 2 ** f, 2 ** k_out))
+    return V / V.sum(axis=(2, 3), keepdims=True)
