@@ -39,6 +39,7 @@ WORKLOAD = {
     "c3": "FD n=30 K=6, three 12-qubit subcircuits (fused chain), 4096 terms",
     "c4": "DD n=40 K=8, four 12-qubit subcircuits, 2^20 bins per recursion, 5 recursions",
     "c5": "256 FD instances n~U{12..24} K~U{1..4} 2-3 subcircuits: forward + cross-entropy adjoint",
+    "entries": "entry construction from variant distributions: two 22-output-qubit subcircuits joined by 2 cuts",
 }
 
 # kernel sources whose change invalidates a committed HBM-counter record
@@ -53,7 +54,7 @@ def _args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default per config)")
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5", "entries"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--calibrate", action="store_true",
@@ -98,7 +99,8 @@ def _sync_time(fn, steps, warmup, torch):
 
 
 def _traced(fn, steps, cqc, torch):
-    """Per-kernel (launches, summed ms) from HIP events around every launch."""
+    """Per-kernel (launches, summed ms) from the start and stop events each
+    launch's dispatch records (the kernels' own run times)."""
     with cqc.trace() as tr:
         for i in range(steps):
             fn(i)
@@ -308,6 +310,62 @@ def bench_dd(args, torch, cqc, W):
 
 
 # ---------------------------------------------------------------------------
+def bench_entries(args, torch, cqc, W):
+    """entries: on-device entry construction (Eq. 3 attribution and the
+    initialisation combination) for the upstream and downstream subcircuits of
+    a two-cut pair, 2^22 output columns each, FP32 variants and entries."""
+    f = 22
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(6)
+
+    def variants_of(k_in, k_out):
+        V = torch.empty((4 ** k_in, 3 ** k_out, 2 ** f, 2 ** k_out), dtype=torch.float32, device="cuda")
+        V.exponential_(generator=gen)
+        V /= V.sum(dim=(2, 3), keepdim=True)
+        return V
+    jobs = [(variants_of(0, 2), [1, 1]), (variants_of(2, 0), [0, 0])]
+    outs = cqc.build_entries(jobs)
+    steps = args.steps or 20
+    warmup = args.warmup if args.warmup is not None else 3
+
+    def step(i):
+        cqc.build_entries(jobs, outs=outs)
+    ms = _sync_time(step, steps, warmup, torch)
+    kt = _traced(step, steps, cqc, torch)
+    cnt, tot = kt["build_entries"]
+    in_bytes = sum(V.numel() * 4 for V, _ in jobs)
+    out_elems = sum(E.numel() for E in outs)
+    # algorithmic bytes of a step: every variant value read once, every entry written once
+    roof = _roof("hbm", (in_bytes + 4 * out_elems) / (tot / steps * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s",
+                 "build_entries", tot / cnt, None)
+    roof["bytes_per_step"] = in_bytes + 4 * out_elems
+    roof["launches_per_step"] = cnt / steps
+    out = _line("entries", "entry-tensor elements built per second from variant distributions (FP32)",
+                out_elems / (ms * 1e-3), "entries/s", steps, warmup, ms, "f32",
+                {"f": f, "cuts": 2, "variants_bytes": in_bytes}, roof, kernels_ms=kt)
+    if not args.no_cpu:
+        from oracle import variants  # CPU-baseline leg only
+        xs = np.sort(np.random.default_rng(9).choice(2 ** f, 4096, replace=False))
+        samples = [(V[:, :, torch.from_numpy(xs).cuda(), :].double().cpu().numpy(), k) for V, k in jobs]
+        for (Vs, k), E in zip(samples, outs):
+            ref = variants.entries_from_variants(Vs, k)
+            got = E[:, torch.from_numpy(xs).cuda()].double().cpu().numpy()
+            out.setdefault("err_max_abs_sampled", 0.0)
+            out["err_max_abs_sampled"] = max(out["err_max_abs_sampled"], float(np.max(np.abs(got - ref))))
+        per = sum(4 ** len(k) * len(xs) for _, k in samples)
+        t0, reps = time.perf_counter(), 0
+        while time.perf_counter() - t0 < args.cpu_seconds:
+            for Vs, k in samples:
+                variants.entries_from_variants(Vs, k)
+            reps += 1
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": per * reps / el, "unit": "entries/s", "cores": 1, "kind": "oracle",
+                               "sample": f"4096 seeded output columns of both jobs x {reps} repetitions "
+                                         f"({el:.1f} s), numpy FP64 per-label definition"}
+    return out
+
+
+# ---------------------------------------------------------------------------
 def bench_batch(args, torch, cqc, W):
     """c5: 256 instances, forward + cross-entropy gradient + adjoint, one graph."""
     insts = W.batch_instances(256)
@@ -424,6 +482,8 @@ def main():
         out = bench_fd(args, args.config, torch, cqc, W)
     elif args.config == "c4":
         out = bench_dd(args, torch, cqc, W)
+    elif args.config == "entries":
+        out = bench_entries(args, torch, cqc, W)
     else:
         out = bench_batch(args, torch, cqc, W)
     print(json.dumps(out), flush=True)

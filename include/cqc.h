@@ -158,6 +158,44 @@ int cqc_batch_backward_create(cqc_batch batch, const void *const *grad_out,
 int cqc_batch_backward_run(cqc_batch_bwd b, hipStream_t stream);
 int cqc_batch_backward_destroy(cqc_batch_bwd b);
 
+/* On-device entry construction (Sections 3.1-3.2, Pauli form of Eq. 1): the
+ * entry tensor E_c of a subcircuit from the measured distributions of its
+ * variants - the outgoing cuts' labels pick the measurement bases and weight
+ * the measured cut bits by Eq. 3 (I: +1 for both outcomes; X, Y, Z: +1 for 0,
+ * -1 for 1; I and Z share the computational basis), the incoming cuts' labels
+ * combine the initialisations (I: q0 + q1, Z: q0 - q1, X: 2 q+ - q0 - q1,
+ * Y: 2 q+i - q0 - q1); several cuts multiply.
+ *   f         output qubits of the subcircuit (2^f columns), 0 <= f <= 30
+ *   n_cuts    incident cuts k = k_in + k_out; k_in <= 3, k_out <= 4
+ *   cut_kind  (host)[n_cuts]: the incident cuts in ascending cut id, 0 if the
+ *             subcircuit initialises the cut qubit (incoming), 1 if it
+ *             measures it (outgoing)
+ *   variants  DEVICE [4^k_in][3^k_out][2^f][2^k_out], dtype in_t: for every
+ *             initialisation combination (per incoming cut, in cut_kind's
+ *             order: 0 |0>, 1 |1>, 2 |+>, 3 |+i>; first the most significant
+ *             base-4 digit) and measurement-basis combination (per outgoing
+ *             cut: 0 computational, 1 X, 2 Y; first the most significant
+ *             base-3 digit), the probability or normalised shot count of
+ *             every output bit string x (local order, first qubit the most
+ *             significant bit) and measured cut-bit string (first outgoing
+ *             cut the most significant bit)
+ *   entries   DEVICE [4^k][2^f], dtype out_t, written in full: the layout
+ *             cqc_reconstruct_fd takes (row = base-4 number of the labels
+ *             I=0, X=1, Y=2, Z=3 of the incident cuts in ascending cut id)
+ * Sums are accumulated in FP64 and rounded once to out_t.  n_jobs launches,
+ * one per job, on `stream`; no workspace, no synchronisation (graph-
+ * capturable).  Validation (dtypes, sizes, cut_kind values, NULL pointers)
+ * happens for every job before the first launch. */
+typedef struct {
+  int32_t f;
+  int32_t n_cuts;
+  const int32_t *cut_kind;
+  const void *variants;
+  void *entries;
+} cqc_entry_job;
+int cqc_build_entries(const cqc_entry_job *jobs, int32_t n_jobs, cqc_dtype in_t, cqc_dtype out_t,
+                      hipStream_t stream);
+
 /* Dynamic definition (Algorithm 1, Section 4.3).
  * Recursion 1 makes `first_active` (or, if NULL, the first n_active qubits in
  * output order) active; every later recursion picks, among all bins produced

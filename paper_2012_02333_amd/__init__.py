@@ -19,7 +19,7 @@ import torch
 from . import _lib
 from ._lib import CqcError, PREC
 
-__all__ = ["CutMap", "reconstruct_fd", "reconstruct_dd", "reconstruct_backward", "FDCall", "Batch", "BatchBackward",
+__all__ = ["CutMap", "reconstruct_fd", "reconstruct_dd", "reconstruct_backward", "FDCall", "Batch", "BatchBackward", "build_entries",
            "ReconstructFD", "BackwardCall", "cost", "autotune", "trace", "CqcError", "selftest_mfma", "library_path"]
 
 _DT = {torch.float32: _lib.F32, torch.float64: _lib.F64}
@@ -226,6 +226,48 @@ class BatchBackward:
         if h:
             _lib.lib().cqc_batch_backward_destroy(h)
             self._h = None
+
+
+def build_entries(jobs, out_dtype=None, outs=None):
+    """Entry tensors from stacked variant distributions, on the device
+    (cqc_build_entries).  jobs: list of (variants, cut_kind) with variants a
+    contiguous device tensor [4^k_in][3^k_out][2^f][2^k_out] and cut_kind the
+    incident cuts in ascending cut id (0 incoming, 1 outgoing).  Returns one
+    [4^k][2^f] tensor per job (the given outs, if any, are filled instead),
+    enqueued on the current stream."""
+    jobs = list(jobs)
+    if not jobs:
+        raise ValueError("no jobs")
+    in_dt = jobs[0][0].dtype
+    out_dt = out_dtype or in_dt
+    if in_dt not in _DT or out_dt not in _DT:
+        raise ValueError("variants and entries must be float32 or float64")
+    arr = (_lib.CqcEntryJob * len(jobs))()
+    result, keep = [], []
+    for j, (V, kinds) in enumerate(jobs):
+        kinds = [int(k) for k in kinds]
+        k_in, k_out = kinds.count(0), kinds.count(1)
+        if V.dtype != in_dt or not V.is_cuda or not V.is_contiguous() or V.dim() != 4:
+            raise ValueError("variants must be contiguous 4-d device tensors of one dtype")
+        if V.shape[0] != 4 ** k_in or V.shape[1] != 3 ** k_out or V.shape[3] != 2 ** k_out:
+            raise ValueError(f"variants shape {tuple(V.shape)} does not match cut_kind {kinds}")
+        nf = V.shape[2]
+        f = nf.bit_length() - 1
+        if nf != 1 << f:
+            raise ValueError("the output axis must have 2^f entries")
+        if outs is not None:
+            E = outs[j]
+            if E.shape != (4 ** len(kinds), nf) or E.dtype != out_dt or not E.is_contiguous():
+                raise ValueError("outs must match the entry shapes and dtype")
+        else:
+            E = torch.empty((4 ** len(kinds), nf), dtype=out_dt, device=V.device)
+        ck = (ctypes.c_int32 * max(1, len(kinds)))(*kinds)
+        keep.append(ck)
+        arr[j] = _lib.CqcEntryJob(f, len(kinds), ck, V.data_ptr(), E.data_ptr())
+        result.append(E)
+    s = torch.cuda.current_stream(jobs[0][0].device).cuda_stream
+    _lib.check(_lib.lib().cqc_build_entries(arr, len(jobs), _DT[in_dt], _DT[out_dt], s))
+    return result
 
 
 def reconstruct_fd(entries, cut, precision="fp32", out_dtype=None, with_mass=True):

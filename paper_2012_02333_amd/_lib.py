@@ -20,7 +20,7 @@ EXPORTS = [
     "cqc_trace_enable", "cqc_trace_read", "cqc_status_string", "cqc_last_error_detail",
     "cqc_version", "cqc_selftest_mfma", "cqc_batch_create", "cqc_batch_run", "cqc_batch_destroy",
     "cqc_batch_backward_workspace_size", "cqc_batch_backward_create", "cqc_batch_backward_run",
-    "cqc_batch_backward_destroy",
+    "cqc_batch_backward_destroy", "cqc_build_entries",
 ]
 
 
@@ -34,6 +34,12 @@ class CqcCut(ctypes.Structure):
 class CqcInstance(ctypes.Structure):
     _fields_ = [("cut", CqcCut), ("entries", ctypes.POINTER(ctypes.c_void_p)),
                 ("out", ctypes.c_void_p), ("mass", ctypes.c_void_p)]
+
+
+class CqcEntryJob(ctypes.Structure):
+    _fields_ = [("f", ctypes.c_int32), ("n_cuts", ctypes.c_int32),
+                ("cut_kind", ctypes.POINTER(ctypes.c_int32)), ("variants", ctypes.c_void_p),
+                ("entries", ctypes.c_void_p)]
 
 
 class CqcDDParams(ctypes.Structure):
@@ -92,6 +98,7 @@ def lib():
     L.cqc_batch_backward_create.argtypes = [vp, P(vp), P(P(vp)), vp, sz, vp, P(vp)]
     L.cqc_batch_backward_run.argtypes = [vp, vp]
     L.cqc_batch_backward_destroy.argtypes = [vp]
+    L.cqc_build_entries.argtypes = [P(CqcEntryJob), i32, ctypes.c_int, ctypes.c_int, vp]
     for name in EXPORTS:
         f = getattr(L, name)
         if f.restype is None or f.restype is ctypes.c_int:

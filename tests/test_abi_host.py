@@ -133,3 +133,33 @@ def test_batch_backward_rejects_null_handles():
     assert L.cqc_batch_backward_run(None, None) == 1
     assert L.cqc_batch_backward_destroy(None) == 0
     assert L.cqc_batch_run(None, None) != 0
+
+
+def test_build_entries_validation():
+    """cqc_build_entries refuses bad jobs before any launch: more than three
+    incoming or four outgoing cuts, cut kinds other than 0/1, NULL tensors,
+    f outside [0, 30], unknown dtypes."""
+    L = _lib.lib()
+    I32 = ctypes.c_int32
+
+    def job(f, kinds, v=0x1000, e=0x2000):
+        ck = (I32 * max(1, len(kinds)))(*kinds)
+        j = _lib.CqcEntryJob(f, len(kinds), ck, v, e)
+        j._keep = ck
+        return j
+
+    def call(j, in_t=0, out_t=0):
+        arr = (_lib.CqcEntryJob * 1)(j)
+        return L.cqc_build_entries(arr, 1, in_t, out_t, None)
+
+    assert call(job(4, [0, 0, 0, 0])) == 3          # CQC_ERR_UNSUPPORTED
+    assert call(job(4, [1, 1, 1, 1, 1])) == 3
+    assert call(job(4, [0, 2])) == 1                # CQC_ERR_INVALID_ARG
+    assert call(job(4, [0], v=None)) == 1
+    assert call(job(4, [1], e=None)) == 1
+    assert call(job(31, [1])) == 2                  # CQC_ERR_SHAPE
+    assert call(job(-1, [1])) == 2
+    assert call(job(4, [1]), in_t=7) == 1
+    assert L.cqc_build_entries(None, 1, 0, 0, None) == 1
+    arr = (_lib.CqcEntryJob * 1)(job(4, [1]))
+    assert L.cqc_build_entries(arr, 0, 0, 0, None) == 1
