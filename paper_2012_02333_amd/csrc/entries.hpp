@@ -13,6 +13,7 @@ struct EntryArgs {
   void *E;         // [4^k][2^f]
   int32_t f, k_in, k_out, k;
   int32_t p3;      // 3^k_out
+  int32_t vec;     // FP32 variants 16-byte aligned: measured-bit strings read with 16-byte loads
   int32_t in_pos[kEntryMaxIn];    // digit of the i-th incoming cut in the row number (0: most significant)
   int32_t out_pos[kEntryMaxOut];  // same for the outgoing cuts
 };

@@ -55,9 +55,22 @@ __global__ __launch_bounds__(256) void k_build_entries(const EntryArgs a) {
     for (int i = 0; i < NI; ++i) {
       const TI *v = V + (((int64_t)i * a.p3 + bi) * nx + x) * nb;
       double s = 0.0;
-      for (int b = 0; b < nb; ++b) {
-        const double w = (double)v[b];
-        s += (__popc((uint32_t)b & mask) & 1) ? -w : w;
+      if (sizeof(TI) == 4 && a.vec && nb >= 4) {
+        // the thread's measured-bit string is nb contiguous floats: 16-byte loads
+        for (int b = 0; b < nb; b += 4) {
+          const float4 q = *reinterpret_cast<const float4 *>(v + b);
+          const float w4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const double w = (double)w4[e];
+            s += (__popc((uint32_t)(b + e) & mask) & 1) ? -w : w;
+          }
+        }
+      } else {
+        for (int b = 0; b < nb; ++b) {
+          const double w = (double)v[b];
+          s += (__popc((uint32_t)b & mask) & 1) ? -w : w;
+        }
       }
       u[i] = s;
     }

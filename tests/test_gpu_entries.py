@@ -105,3 +105,19 @@ def test_outs_are_filled_in_place():
     torch.cuda.synchronize()
     assert E3.data_ptr() == E2.data_ptr()
     assert torch.equal(E2, E1)
+
+
+def test_unaligned_fp32_variants():
+    """FP32 variants at a 4-byte (not 16-byte) aligned address take the scalar
+    path and give the same entries."""
+    _gpu()
+    V = W.random_variants(1, 2, 6, seed=51).astype(np.float32).astype(np.float64)
+    Vd = torch.from_numpy(V).to(device="cuda", dtype=torch.float32).contiguous()
+    buf = torch.empty(Vd.numel() + 1, dtype=torch.float32, device="cuda")
+    Vu = buf[1:].view(Vd.shape)
+    Vu.copy_(Vd)
+    assert Vu.data_ptr() % 16 != 0
+    (Ea,) = cqc.build_entries([(Vd, [1, 0, 1])])
+    (Eu,) = cqc.build_entries([(Vu, [1, 0, 1])])
+    torch.cuda.synchronize()
+    assert torch.equal(Ea, Eu)
