@@ -134,11 +134,21 @@ def variant_tensor(circ, sub):
     return V
 
 
-def entries_from_variants(V, cut_kind):
-    """Pauli-form entry tensor from stacked variant distributions (Sections
-    3.1-3.2): for every label assignment, the outgoing cuts' labels pick the
-    measurement bases and weight the measured bits by Eq. 3; the incoming cuts'
-    labels combine the initialisations by the p_{2,i} rule.
+# Per outgoing-cut label: the measurement basis it reads (0 computational,
+# 1 X, 2 Y) and the weights of measured bit 0 and 1.  Pauli form: Eq. 3.
+# Eigen form (Eq. 2): A1 = Tr(AI) + Tr(AZ), A2 = Tr(AI) - Tr(AZ) in the
+# computational basis, A3, A4 as X, Y.
+_UP_BASIS = {"pauli": {0: 0, 1: 1, 2: 2, 3: 0}, "eigen": {0: 0, 1: 0, 2: 1, 3: 2}}
+_UP_WEIGHT = {"pauli": {0: (1, 1), 1: (1, -1), 2: (1, -1), 3: (1, -1)},
+              "eigen": {0: (2, 0), 1: (0, 2), 2: (1, -1), 3: (1, -1)}}
+
+
+def entries_from_variants(V, cut_kind, form="pauli"):
+    """Entry tensor from stacked variant distributions (Sections 3.1-3.2): for
+    every label assignment, the outgoing cuts' labels pick the measurement
+    bases and weight the measured bits (Eq. 3 in Pauli form); the incoming
+    cuts' labels combine the initialisations by the p_{2,i} rule (Eq. 1, or
+    Eq. 2 in eigen form).
 
     V: [4^k_in][3^k_out][2^f][2^k_out] as variant_tensor.  cut_kind: per
     incident cut in ascending cut id, 0 if initialised here (incoming), 1 if
@@ -150,7 +160,8 @@ def entries_from_variants(V, cut_kind):
     cut_kind = list(cut_kind)
     k_in, k_out = cut_kind.count(0), cut_kind.count(1)
     assert V.shape[0] == 4 ** k_in and V.shape[1] == 3 ** k_out and V.shape[3] == 2 ** k_out
-    basis_digit = {0: 0, 3: 0, 1: 1, 2: 2}
+    basis_digit, weight = _UP_BASIS[form], _UP_WEIGHT[form]
+    down = _DOWN_PAULI if form == "pauli" else _DOWN_EIGEN
     E = np.zeros((4 ** (k_in + k_out), V.shape[2]))
     for row, labels in enumerate(itertools.product(range(4), repeat=k_in + k_out)):
         l_in = [l for l, kd in zip(labels, cut_kind) if kd == 0]
@@ -158,10 +169,15 @@ def entries_from_variants(V, cut_kind):
         bi = 0
         for l in l_out:
             bi = 3 * bi + basis_digit[l]
+        # weight of each measured bit string: product over the outgoing cuts
+        w = np.ones(2 ** k_out)
+        for o in range(2 ** k_out):
+            for t, lab in enumerate(l_out):
+                w[o] *= weight[lab][(o >> (k_out - 1 - t)) & 1]
         for ii, inits in enumerate(itertools.product(range(4), repeat=k_in)):
             coef = 1.0
             for lab, init in zip(l_in, inits):
-                coef *= _DOWN_PAULI[lab][init]
+                coef *= down[lab][init]
             if coef != 0.0:
-                E[row] += coef * attribute(V[ii, bi], l_out)
+                E[row] += coef * (V[ii, bi] @ w)
     return E

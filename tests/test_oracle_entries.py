@@ -140,3 +140,31 @@ def test_entries_from_variants_single_cut_by_hand():
     assert np.allclose(E[1], xb[:, 0] - xb[:, 1], atol=0, rtol=0)
     assert np.allclose(E[2], yb[:, 0] - yb[:, 1], atol=0, rtol=0)
     assert np.allclose(E[3], comp[:, 0] - comp[:, 1], atol=0, rtol=0)
+
+
+@pytest.mark.parametrize("own,bridges,layers", SHAPES[:4])
+def test_entries_from_variants_eigen_equal_paper_route(own, bridges, layers):
+    """Eigen form (Eq. 2) from the stacked variants equals the eigen-form paper
+    route, which reconstructs the same distribution as the Pauli form."""
+    circ = W.bridged_chain(own, bridges, layers, seed=19)
+    ents = []
+    for sub in circ.subcircuits():
+        V = variants.variant_tensor(circ, sub)
+        kinds = [0] * len(sub.q_in) + [1] * len(sub.q_out)
+        E = variants.entries_from_variants(V, kinds, "eigen")
+        assert np.max(np.abs(E - variants.subcircuit_entries(circ, sub, "eigen"))) < 1e-13
+        ents.append(E)
+    cut = circ.cut_map()
+    assert np.max(np.abs(fd.reconstruct(ents, cut) - sv.uncut_distribution(circ))) < 1e-13
+
+
+def test_eigen_weights_by_hand():
+    """One measured cut, eigen form: rows A1..A4 are 2 p0, 2 p1 in the
+    computational basis, p0 - p1 in the X and in the Y basis."""
+    V = W.random_variants(0, 1, 2, seed=9)
+    E = variants.entries_from_variants(V, [1], "eigen")
+    comp, xb, yb = V[0, 0], V[0, 1], V[0, 2]
+    assert np.array_equal(E[0], 2 * comp[:, 0])
+    assert np.array_equal(E[1], 2 * comp[:, 1])
+    assert np.array_equal(E[2], xb[:, 0] - xb[:, 1])
+    assert np.array_equal(E[3], yb[:, 0] - yb[:, 1])
