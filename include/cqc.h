@@ -158,13 +158,19 @@ int cqc_batch_backward_create(cqc_batch batch, const void *const *grad_out,
 int cqc_batch_backward_run(cqc_batch_bwd b, hipStream_t stream);
 int cqc_batch_backward_destroy(cqc_batch_bwd b);
 
-/* On-device entry construction (Sections 3.1-3.2, Pauli form of Eq. 1): the
- * entry tensor E_c of a subcircuit from the measured distributions of its
- * variants - the outgoing cuts' labels pick the measurement bases and weight
- * the measured cut bits by Eq. 3 (I: +1 for both outcomes; X, Y, Z: +1 for 0,
- * -1 for 1; I and Z share the computational basis), the incoming cuts' labels
- * combine the initialisations (I: q0 + q1, Z: q0 - q1, X: 2 q+ - q0 - q1,
- * Y: 2 q+i - q0 - q1); several cuts multiply.
+/* On-device entry construction (Sections 3.1-3.2): the entry tensor E_c of a
+ * subcircuit from the measured distributions of its variants - the outgoing
+ * cuts' labels pick the measurement bases and weight the measured cut bits,
+ * the incoming cuts' labels combine the initialisations; several cuts
+ * multiply.  form CQC_FORM_PAULI (Eq. 1 and Eq. 3), labels I, X, Y, Z:
+ * measured bits +1/+1 (I) or +1/-1 (X, Y, Z; I and Z share the computational
+ * basis); initialisations I: q0 + q1, X: 2 q+ - q0 - q1, Y: 2 q+i - q0 - q1,
+ * Z: q0 - q1.  form CQC_FORM_EIGEN (Eq. 2), labels A1..A4: measured bits 2/0
+ * (A1) and 0/2 (A2) in the computational basis, +1/-1 in the X (A3) and Y
+ * (A4) bases; initialisations A1: q0, A2: q1, A3: 2 q+ - q0 - q1, A4: 2 q+i -
+ * q0 - q1.  Both forms reconstruct the same distribution when every
+ * subcircuit of an instance uses the same form; the eigen form has the
+ * smaller term magnitudes.
  *   f         output qubits of the subcircuit (2^f columns), 0 <= f <= 30
  *   n_cuts    incident cuts k = k_in + k_out; k_in <= 3, k_out <= 4
  *   cut_kind  (host)[n_cuts]: the incident cuts in ascending cut id, 0 if the
@@ -181,17 +187,21 @@ int cqc_batch_backward_destroy(cqc_batch_bwd b);
  *             cut the most significant bit)
  *   entries   DEVICE [4^k][2^f], dtype out_t, written in full: the layout
  *             cqc_reconstruct_fd takes (row = base-4 number of the labels
- *             I=0, X=1, Y=2, Z=3 of the incident cuts in ascending cut id)
+ *             - I=0, X=1, Y=2, Z=3, or A1..A4 = 0..3 - of the incident cuts
+ *             in ascending cut id)
+ *   form      cqc_entry_form
  * Sums are accumulated in FP64 and rounded once to out_t.  n_jobs launches,
  * one per job, on `stream`; no workspace, no synchronisation (graph-
  * capturable).  Validation (dtypes, sizes, cut_kind values, NULL pointers)
  * happens for every job before the first launch. */
+typedef enum { CQC_FORM_PAULI = 0, CQC_FORM_EIGEN = 1 } cqc_entry_form;
 typedef struct {
   int32_t f;
   int32_t n_cuts;
   const int32_t *cut_kind;
   const void *variants;
   void *entries;
+  int32_t form;   /* cqc_entry_form */
 } cqc_entry_job;
 int cqc_build_entries(const cqc_entry_job *jobs, int32_t n_jobs, cqc_dtype in_t, cqc_dtype out_t,
                       hipStream_t stream);

@@ -228,16 +228,20 @@ class BatchBackward:
             self._h = None
 
 
-def build_entries(jobs, out_dtype=None, outs=None):
+def build_entries(jobs, out_dtype=None, outs=None, form="pauli"):
     """Entry tensors from stacked variant distributions, on the device
     (cqc_build_entries).  jobs: list of (variants, cut_kind) with variants a
     contiguous device tensor [4^k_in][3^k_out][2^f][2^k_out] and cut_kind the
-    incident cuts in ascending cut id (0 incoming, 1 outgoing).  Returns one
+    incident cuts in ascending cut id (0 incoming, 1 outgoing); form "pauli"
+    (Eq. 1, labels I X Y Z) or "eigen" (Eq. 2, labels A1..A4).  Returns one
     [4^k][2^f] tensor per job (the given outs, if any, are filled instead),
     enqueued on the current stream."""
     jobs = list(jobs)
     if not jobs:
         raise ValueError("no jobs")
+    forms = {"pauli": 0, "eigen": 1}
+    if form not in forms:
+        raise ValueError("form must be 'pauli' or 'eigen'")
     in_dt = jobs[0][0].dtype
     out_dt = out_dtype or in_dt
     if in_dt not in _DT or out_dt not in _DT:
@@ -263,7 +267,7 @@ def build_entries(jobs, out_dtype=None, outs=None):
             E = torch.empty((4 ** len(kinds), nf), dtype=out_dt, device=V.device)
         ck = (ctypes.c_int32 * max(1, len(kinds)))(*kinds)
         keep.append(ck)
-        arr[j] = _lib.CqcEntryJob(f, len(kinds), ck, V.data_ptr(), E.data_ptr())
+        arr[j] = _lib.CqcEntryJob(f, len(kinds), ck, V.data_ptr(), E.data_ptr(), forms[form])
         result.append(E)
     s = torch.cuda.current_stream(jobs[0][0].device).cuda_stream
     _lib.check(_lib.lib().cqc_build_entries(arr, len(jobs), _DT[in_dt], _DT[out_dt], s))

@@ -39,7 +39,7 @@ class CqcInstance(ctypes.Structure):
 class CqcEntryJob(ctypes.Structure):
     _fields_ = [("f", ctypes.c_int32), ("n_cuts", ctypes.c_int32),
                 ("cut_kind", ctypes.POINTER(ctypes.c_int32)), ("variants", ctypes.c_void_p),
-                ("entries", ctypes.c_void_p)]
+                ("entries", ctypes.c_void_p), ("form", ctypes.c_int32)]
 
 
 class CqcDDParams(ctypes.Structure):

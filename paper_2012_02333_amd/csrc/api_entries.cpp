@@ -47,6 +47,9 @@ int cqc_build_entries(const cqc_entry_job *jobs, int32_t n_jobs, cqc_dtype in_t,
     a.p3 = 1;
     for (int t = 0; t < kout; ++t) a.p3 *= 3;
     a.vec = in_t == CQC_F32 && (reinterpret_cast<uintptr_t>(J.variants) % 16) == 0 ? 1 : 0;
+    if (J.form != CQC_FORM_PAULI && J.form != CQC_FORM_EIGEN)
+      return Status::fail(CQC_ERR_INVALID_ARG, who + "form must be CQC_FORM_PAULI or CQC_FORM_EIGEN").code;
+    a.eigen = J.form == CQC_FORM_EIGEN ? 1 : 0;
   }
   for (int32_t j = 0; j < n_jobs; ++j) {
     Status st = launch_build_entries(args[j], in_t == CQC_F64, out_t == CQC_F64, stream);

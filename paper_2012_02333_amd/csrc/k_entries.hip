@@ -3,10 +3,13 @@
 //
 // One thread per (outgoing-label combination, output column x): for every
 // initialisation combination it adds the measured cut bits of the basis
-// combination its outgoing labels select, signed by Eq. 3 (FP64), then
-// applies the incoming cuts' initialisation weights one cut at a time as
-// 4 x 4 mode products on the per-thread vector of initialisation
-// combinations, and writes one entry per incoming-label combination.
+// combination its outgoing labels select, weighted per bit by the labels
+// (Eq. 3 in the Pauli form: +1, or +1 / -1; Eq. 2's eigen form: 2 / 0, 0 / 2,
+// +1 / -1) in FP64, then applies the incoming cuts' initialisation weights one
+// cut at a time as 4 x 4 mode products on the per-thread vector of
+// initialisation combinations, and writes one entry per incoming-label
+// combination.  The form is a template parameter, so the weights are
+// compile-time constants.
 // Consecutive threads take consecutive x: every read of a measured-bit string
 // and every entry write is coalesced across the wave.  The tensor is read
 // about once per outgoing label that shares its basis combination (I and Z
@@ -18,17 +21,23 @@
 
 namespace cqc {
 
-// Pauli-form initialisation weights w[label][init] over (|0>, |1>, |+>, |+i>).
-__device__ __forceinline__ double init_weight(int label, int init) {
-  switch (label) {
-    case 0: return init < 2 ? 1.0 : 0.0;                                  // I: q0 + q1
-    case 3: return init == 0 ? 1.0 : (init == 1 ? -1.0 : 0.0);            // Z: q0 - q1
-    case 1: return init < 2 ? -1.0 : (init == 2 ? 2.0 : 0.0);             // X: 2 q+ - q0 - q1
-    default: return init < 2 ? -1.0 : (init == 3 ? 2.0 : 0.0);            // Y: 2 q+i - q0 - q1
+// Initialisation weight of |0>, |1>, |+>, |+i> (init 0..3) for an incoming
+// label: Pauli form I: q0 + q1, X: 2 q+ - q0 - q1, Y: 2 q+i - q0 - q1,
+// Z: q0 - q1; eigen form A1: q0, A2: q1, A3, A4 as X, Y.
+template <int EIGEN>
+__device__ __forceinline__ constexpr double init_weight(int label, int init) {
+  if (EIGEN) {
+    if (label == 0) return init == 0 ? 1.0 : 0.0;
+    if (label == 1) return init == 1 ? 1.0 : 0.0;
+  } else {
+    if (label == 0) return init < 2 ? 1.0 : 0.0;
+    if (label == 3) return init == 0 ? 1.0 : (init == 1 ? -1.0 : 0.0);
   }
+  const int plus = EIGEN ? (label == 2 ? 2 : 3) : (label == 1 ? 2 : 3);   // X-like: |+>, Y-like: |+i>
+  return init < 2 ? -1.0 : (init == plus ? 2.0 : 0.0);
 }
 
-template <typename TI, typename TO, int KIN>
+template <typename TI, typename TO, int KIN, int EIGEN>
 __global__ __launch_bounds__(256) void k_build_entries(const EntryArgs a) {
   constexpr int NI = 1 << (2 * KIN);
   const int64_t nx = int64_t(1) << a.f;
@@ -41,14 +50,31 @@ __global__ __launch_bounds__(256) void k_build_entries(const EntryArgs a) {
        id += (int64_t)gridDim.x * blockDim.x) {
     const int64_t x = id & (nx - 1);
     const int lo = (int)(id >> a.f);   // outgoing labels, first outgoing cut most significant
+    // weight of measured bit string b: 0 unless (b & zmask) == zval, else
+    // scale * (-1)^popcount(b & smask).  Pauli form: I weighs both outcomes
+    // +1, X, Y, Z weigh 0 / 1 as +1 / -1.  Eigen form: A1 (A2) keeps only
+    // outcome 0 (1) with weight 2, A3, A4 weigh +1 / -1.
     int bi = 0;                        // basis combination, base 3
-    uint32_t mask = 0;                 // measured bits whose label is not I flip the sign
     int64_t rowo = 0;                  // the outgoing labels' part of the row number
+    uint32_t zmask = 0, zval = 0, smask = 0;
+    double scale = 1.0;
     for (int t = 0; t < kout; ++t) {
       const int l = (lo >> (2 * (kout - 1 - t))) & 3;
-      bi = 3 * bi + (l == 1 ? 1 : (l == 2 ? 2 : 0));
-      if (l != 0) mask |= 1u << (kout - 1 - t);
+      const uint32_t bit = 1u << (kout - 1 - t);
       rowo += (int64_t)l << (2 * (a.k - 1 - a.out_pos[t]));
+      if (EIGEN) {
+        bi = 3 * bi + (l < 2 ? 0 : l - 1);
+        if (l < 2) {
+          zmask |= bit;
+          if (l == 1) zval |= bit;
+          scale *= 2.0;
+        } else {
+          smask |= bit;
+        }
+      } else {
+        bi = 3 * bi + (l == 1 ? 1 : (l == 2 ? 2 : 0));
+        if (l != 0) smask |= bit;
+      }
     }
     double u[NI];
 #pragma unroll
@@ -62,17 +88,18 @@ __global__ __launch_bounds__(256) void k_build_entries(const EntryArgs a) {
           const float w4[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
+            const uint32_t bb = (uint32_t)(b + e);
             const double w = (double)w4[e];
-            s += (__popc((uint32_t)(b + e) & mask) & 1) ? -w : w;
+            if ((bb & zmask) == zval) s += (__popc(bb & smask) & 1) ? -w : w;
           }
         }
       } else {
         for (int b = 0; b < nb; ++b) {
           const double w = (double)v[b];
-          s += (__popc((uint32_t)b & mask) & 1) ? -w : w;
+          if (((uint32_t)b & zmask) == zval) s += (__popc((uint32_t)b & smask) & 1) ? -w : w;
         }
       }
-      u[i] = s;
+      u[i] = scale * s;
     }
     // initialisation weights, one incoming cut (base-4 digit t) at a time
 #pragma unroll
@@ -86,8 +113,8 @@ __global__ __launch_bounds__(256) void k_build_entries(const EntryArgs a) {
         const double u0 = u[base], u1 = u[base | (1 << sh)], u2 = u[base | (2 << sh)], u3 = u[base | (3 << sh)];
 #pragma unroll
         for (int l = 0; l < 4; ++l)
-          u[base | (l << sh)] = init_weight(l, 0) * u0 + init_weight(l, 1) * u1 + init_weight(l, 2) * u2 +
-                                init_weight(l, 3) * u3;
+          u[base | (l << sh)] = init_weight<EIGEN>(l, 0) * u0 + init_weight<EIGEN>(l, 1) * u1 +
+                                init_weight<EIGEN>(l, 2) * u2 + init_weight<EIGEN>(l, 3) * u3;
       }
     }
 #pragma unroll
@@ -104,11 +131,20 @@ template <typename TI, typename TO>
 static Status launch_entries_t(const EntryArgs &a, hipStream_t s) {
   const int64_t total = (int64_t(1) << (2 * a.k_out)) << a.f;
   const dim3 g((unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 65536))), b(256);
+  if (a.eigen) {
+    switch (a.k_in) {
+      case 0: return launch("build_entries", k_build_entries<TI, TO, 0, 1>, g, b, 0, s, a);
+      case 1: return launch("build_entries", k_build_entries<TI, TO, 1, 1>, g, b, 0, s, a);
+      case 2: return launch("build_entries", k_build_entries<TI, TO, 2, 1>, g, b, 0, s, a);
+      case 3: return launch("build_entries", k_build_entries<TI, TO, 3, 1>, g, b, 0, s, a);
+      default: return Status::fail(CQC_ERR_UNSUPPORTED, "more than 3 incoming cuts");
+    }
+  }
   switch (a.k_in) {
-    case 0: return launch("build_entries", k_build_entries<TI, TO, 0>, g, b, 0, s, a);
-    case 1: return launch("build_entries", k_build_entries<TI, TO, 1>, g, b, 0, s, a);
-    case 2: return launch("build_entries", k_build_entries<TI, TO, 2>, g, b, 0, s, a);
-    case 3: return launch("build_entries", k_build_entries<TI, TO, 3>, g, b, 0, s, a);
+    case 0: return launch("build_entries", k_build_entries<TI, TO, 0, 0>, g, b, 0, s, a);
+    case 1: return launch("build_entries", k_build_entries<TI, TO, 1, 0>, g, b, 0, s, a);
+    case 2: return launch("build_entries", k_build_entries<TI, TO, 2, 0>, g, b, 0, s, a);
+    case 3: return launch("build_entries", k_build_entries<TI, TO, 3, 0>, g, b, 0, s, a);
     default: return Status::fail(CQC_ERR_UNSUPPORTED, "more than 3 incoming cuts");
   }
 }

@@ -142,9 +142,9 @@ def test_build_entries_validation():
     L = _lib.lib()
     I32 = ctypes.c_int32
 
-    def job(f, kinds, v=0x1000, e=0x2000):
+    def job(f, kinds, v=0x1000, e=0x2000, form=0):
         ck = (I32 * max(1, len(kinds)))(*kinds)
-        j = _lib.CqcEntryJob(f, len(kinds), ck, v, e)
+        j = _lib.CqcEntryJob(f, len(kinds), ck, v, e, form)
         j._keep = ck
         return j
 
@@ -160,6 +160,7 @@ def test_build_entries_validation():
     assert call(job(31, [1])) == 2                  # CQC_ERR_SHAPE
     assert call(job(-1, [1])) == 2
     assert call(job(4, [1]), in_t=7) == 1
+    assert call(job(4, [1], form=2)) == 1
     assert L.cqc_build_entries(None, 1, 0, 0, None) == 1
     arr = (_lib.CqcEntryJob * 1)(job(4, [1]))
     assert L.cqc_build_entries(arr, 0, 0, 0, None) == 1

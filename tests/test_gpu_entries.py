@@ -121,3 +121,42 @@ def test_unaligned_fp32_variants():
     (Eu,) = cqc.build_entries([(Vu, [1, 0, 1])])
     torch.cuda.synchronize()
     assert torch.equal(Ea, Eu)
+
+
+@pytest.mark.parametrize("kinds", [[1], [0], [1, 0, 1], [0, 0, 1, 1], [0, 1, 1, 1, 1]])
+def test_eigen_form_matches_oracle(kinds):
+    """Eigen-form entries (Eq. 2) from finite-shot variants, FP64, against the
+    oracle's eigen form."""
+    _gpu()
+    k_in, k_out = kinds.count(0), kinds.count(1)
+    V = W.sample_variant_shots(W.random_variants(k_in, k_out, 5, seed=60 + len(kinds)), 3000, seed=61)
+    Vd = torch.from_numpy(V).cuda()
+    (E,) = cqc.build_entries([(Vd, kinds)], form="eigen")
+    torch.cuda.synchronize()
+    ref = variants.entries_from_variants(V, kinds, "eigen")
+    assert np.max(np.abs(E.cpu().numpy() - ref)) <= 1e-13 * (np.max(np.abs(ref)) + 1.0)
+
+
+def test_eigen_form_end_to_end_and_smaller_kappa():
+    """A chain with six cuts: eigen-form entries built on the GPU reconstruct
+    the uncut distribution (FP64), their condition number kappa (the term sum
+    of |products| over sum |p|) is below the Pauli form's, and both FP32
+    reconstructions meet the 1e-6 bar."""
+    _gpu()
+    circ = W.bridged_chain((3, 2, 3), (3, 3), 6, seed=23)
+    cut = circ.cut_map()
+    jobs = []
+    for sub in circ.subcircuits():
+        jobs.append((torch.from_numpy(variants.variant_tensor(circ, sub)).cuda(),
+                     [0] * len(sub.q_in) + [1] * len(sub.q_out)))
+    truth = sv.uncut_distribution(circ)
+    kap = {}
+    for form in ("pauli", "eigen"):
+        Es = cqc.build_entries(jobs, form=form)
+        p64, _ = cqc.reconstruct_fd(Es, cqc.CutMap.from_workload(cut), precision="fp64")
+        assert metrics.rel_l1(p64.cpu().numpy(), truth) < 1e-12, form
+        E32 = [E.float() for E in Es]
+        p32, _ = cqc.reconstruct_fd(E32, cqc.CutMap.from_workload(cut), precision="fp32")
+        assert metrics.rel_l1(p32.double().cpu().numpy(), truth) < 1e-6, form
+        kap[form] = metrics.kappa([E.cpu().numpy() for E in Es], cut, np.abs(truth).sum())
+    assert kap["eigen"] < kap["pauli"], kap
