@@ -40,6 +40,7 @@ WORKLOAD = {
     "c4": "DD n=40 K=8, four 12-qubit subcircuits, 2^20 bins per recursion, 5 recursions",
     "c5": "256 FD instances n~U{12..24} K~U{1..4} 2-3 subcircuits: forward + cross-entropy adjoint",
     "entries": "entry construction from variant distributions: two 22-output-qubit subcircuits joined by 2 cuts",
+    "chi2": "chi-square distance (Eq. 16) of two 2^28-outcome FP32 distributions",
 }
 
 # kernel sources whose change invalidates a committed HBM-counter record
@@ -54,7 +55,7 @@ def _args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default per config)")
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5", "entries"])
+    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5", "entries", "chi2"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--calibrate", action="store_true",
@@ -366,6 +367,38 @@ def bench_entries(args, torch, cqc, W):
 
 
 # ---------------------------------------------------------------------------
+def bench_chi2(args, torch, cqc, W):
+    """chi2: Eq. 16 over two 2^28-outcome FP32 distributions (2 GiB read)."""
+    n = 1 << 28
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    a = torch.empty(n, dtype=torch.float32, device="cuda").exponential_(generator=gen)
+    b = torch.empty(n, dtype=torch.float32, device="cuda").exponential_(generator=gen)
+    a /= a.sum()
+    b /= b.sum()
+    steps = args.steps or 20
+    warmup = args.warmup if args.warmup is not None else 3
+    ms = _sync_time(lambda i: cqc.chi2(a, b), steps, warmup, torch)
+    kt = _traced(lambda i: cqc.chi2(a, b), steps, cqc, torch)
+    cnt, tot = kt["chi2_part"]
+    roof = _roof("hbm", 8.0 * n / (tot / cnt * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", "chi2_part", tot / cnt, None)
+    out = _line("chi2", "chi-square distance outcomes/s (Eq. 16, FP32 inputs, FP64 terms)", n / (ms * 1e-3),
+                "outcomes/s", steps, warmup, ms, "f32", {"n": n}, roof, kernels_ms=kt)
+    if not args.no_cpu:
+        from oracle import metrics  # CPU-baseline leg only
+        m = 1 << 24
+        an, bn = a[:m].double().cpu().numpy(), b[:m].double().cpu().numpy()
+        t0, reps = time.perf_counter(), 0
+        while time.perf_counter() - t0 < args.cpu_seconds / 2:
+            metrics.chi2(an, bn)
+            reps += 1
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": m * reps / el, "unit": "outcomes/s", "cores": 1, "kind": "oracle",
+                               "sample": f"first 2^24 outcomes x {reps} repetitions ({el:.1f} s), numpy FP64"}
+    return out
+
+
+# ---------------------------------------------------------------------------
 def bench_batch(args, torch, cqc, W):
     """c5: 256 instances, forward + cross-entropy gradient + adjoint, one graph."""
     insts = W.batch_instances(256)
@@ -484,6 +517,8 @@ def main():
         out = bench_dd(args, torch, cqc, W)
     elif args.config == "entries":
         out = bench_entries(args, torch, cqc, W)
+    elif args.config == "chi2":
+        out = bench_chi2(args, torch, cqc, W)
     else:
         out = bench_batch(args, torch, cqc, W)
     print(json.dumps(out), flush=True)

@@ -206,6 +206,19 @@ typedef struct {
 int cqc_build_entries(const cqc_entry_job *jobs, int32_t n_jobs, cqc_dtype in_t, cqc_dtype out_t,
                       hipStream_t stream);
 
+/* Chi-square distance of two distributions (Eq. 16): *out = sum over i < n
+ * with a_i + b_i > 0 of (a_i - b_i)^2 / (a_i + b_i), every term in FP64.
+ * a, b: DEVICE [n] in dtypes a_t, b_t (e.g. a reconstruction against a
+ * reference, or two DD bin landscapes).  out: DEVICE, one FP64.  workspace:
+ * DEVICE, at least 8192 bytes (per-block partials), 8-byte aligned.  Two
+ * launches on `stream`, no synchronisation; the addition order depends only
+ * on n (not on the alignment of a and b), so the result is bitwise
+ * reproducible.  n = 0 writes 0.  Errors: CQC_ERR_INVALID_ARG for an unknown
+ * dtype, n < 0, NULL out, or NULL a / b with n > 0; CQC_ERR_WORKSPACE for a
+ * missing or short workspace. */
+int cqc_chi2(const void *a, cqc_dtype a_t, const void *b, cqc_dtype b_t, int64_t n, double *out,
+             void *workspace, size_t ws_bytes, hipStream_t stream);
+
 /* Dynamic definition (Algorithm 1, Section 4.3).
  * Recursion 1 makes `first_active` (or, if NULL, the first n_active qubits in
  * output order) active; every later recursion picks, among all bins produced

@@ -19,7 +19,7 @@ import torch
 from . import _lib
 from ._lib import CqcError, PREC
 
-__all__ = ["CutMap", "reconstruct_fd", "reconstruct_dd", "reconstruct_backward", "FDCall", "Batch", "BatchBackward", "build_entries",
+__all__ = ["CutMap", "reconstruct_fd", "reconstruct_dd", "reconstruct_backward", "FDCall", "Batch", "BatchBackward", "build_entries", "chi2",
            "ReconstructFD", "BackwardCall", "cost", "autotune", "trace", "CqcError", "selftest_mfma", "library_path"]
 
 _DT = {torch.float32: _lib.F32, torch.float64: _lib.F64}
@@ -86,16 +86,11 @@ def _check_entries(entries, cut, dtype=None):
     return dt
 
 
-_ws_cache = {}
-
-
 def _workspace(nbytes, device):
-    key = (device.index if device.index is not None else torch.cuda.current_device())
-    buf = _ws_cache.get(key)
-    if buf is None or buf.numel() < nbytes:
-        buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
-        _ws_cache[key] = buf
-    return buf
+    """A fresh workspace for one enqueued call.  Torch's caching allocator
+    orders its reuse on the current stream, which is the stream the call runs
+    on, so concurrent calls on different streams never share one."""
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
 
 class FDCall:
@@ -272,6 +267,21 @@ def build_entries(jobs, out_dtype=None, outs=None, form="pauli"):
     s = torch.cuda.current_stream(jobs[0][0].device).cuda_stream
     _lib.check(_lib.lib().cqc_build_entries(arr, len(jobs), _DT[in_dt], _DT[out_dt], s))
     return result
+
+
+def chi2(a, b):
+    """Eq. 16 chi-square distance of two device vectors (cqc_chi2) -> 0-d FP64
+    device tensor, enqueued on the current stream."""
+    if a.shape != b.shape or a.dim() != 1 or not a.is_cuda or not b.is_cuda:
+        raise ValueError("a and b must be 1-d device tensors of one length")
+    if a.dtype not in _DT or b.dtype not in _DT or not a.is_contiguous() or not b.is_contiguous():
+        raise ValueError("a and b must be contiguous float32 or float64")
+    out = torch.empty((), dtype=torch.float64, device=a.device)
+    ws = _workspace(8192, a.device)
+    s = torch.cuda.current_stream(a.device).cuda_stream
+    _lib.check(_lib.lib().cqc_chi2(a.data_ptr(), _DT[a.dtype], b.data_ptr(), _DT[b.dtype], a.numel(),
+                                    out.data_ptr(), ws.data_ptr(), ws.numel(), s))
+    return out
 
 
 def reconstruct_fd(entries, cut, precision="fp32", out_dtype=None, with_mass=True):

@@ -164,3 +164,16 @@ def test_build_entries_validation():
     assert L.cqc_build_entries(None, 1, 0, 0, None) == 1
     arr = (_lib.CqcEntryJob * 1)(job(4, [1]))
     assert L.cqc_build_entries(arr, 0, 0, 0, None) == 1
+
+
+def test_chi2_validation():
+    """cqc_chi2 refuses bad dtypes, n < 0, NULL output or inputs and a short
+    workspace before any launch."""
+    L = _lib.lib()
+    out, ws = 0x3000, 0x4000
+    assert L.cqc_chi2(0x1000, 7, 0x2000, 0, 10, out, ws, 8192, None) == 1
+    assert L.cqc_chi2(0x1000, 0, 0x2000, 0, -1, out, ws, 8192, None) == 1
+    assert L.cqc_chi2(0x1000, 0, 0x2000, 0, 10, None, ws, 8192, None) == 1
+    assert L.cqc_chi2(None, 0, 0x2000, 0, 10, out, ws, 8192, None) == 1
+    assert L.cqc_chi2(0x1000, 0, 0x2000, 0, 10, out, ws, 100, None) == 4
+    assert L.cqc_chi2(0x1000, 0, 0x2000, 0, 10, out, None, 8192, None) == 4
