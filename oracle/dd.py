@@ -20,6 +20,24 @@ Readings where the algorithm is silent:
   * bin index bits follow the active qubits in ascending qubit id, first = most
     significant bit; zoomed values are stored per qubit.
   * the loop stops early when no candidate bin is left.
+
+Search strategies (Section 4.3 describes a depth-first search for sparse
+outputs and a breadth-first one for dense outputs without fixing the rule;
+the readings here):
+  * "heaviest": Algorithm 1 as written - the heaviest candidate over all
+    recursions so far.
+  * "dfs": the candidates of the most recent recursion that still has any,
+    heaviest first; a recursion without merged qubits (a single state) sends
+    the search back to the latest recursion with candidates left.
+  * "bfs": the candidates of the shallowest zoom depth that still has any,
+    heaviest first across the recursions of that depth (ties: lowest
+    recursion, then bin).
+  * per_round > 1 expands several bins per round from the candidates of the
+    recursions that existed when the round began (the multi-bin expansion):
+    the best per_round of them in the strategy's order, restricted to the
+    first pick's depth (bfs) or recursion (dfs).  For bfs every depth's
+    recursions exist before its first bin is expanded, so bfs gives the same
+    records for every per_round.
 """
 from __future__ import annotations
 
@@ -83,24 +101,42 @@ def bins_from_merged(merged, cut, role, betas=None):
     return acc * (2.0 ** -K)
 
 
-def reconstruct(entries, cut, n_active, n_recursions, first_active=None, chooser=None):
+def reconstruct(entries, cut, n_active, n_recursions, first_active=None, chooser=None,
+                strategy="heaviest", per_round=1):
     """Run Algorithm 1.  Returns a list of records (dicts).
 
     chooser(records, expanded) may override the bin choice (used by parity tests
     to follow the GPU's choice where two masses tie within rounding); default is
-    the heaviest-unexpanded rule.
+    the strategy's rule, applied to the recursions that existed when the round
+    began.
     """
+    if strategy not in CHOOSERS:
+        raise ValueError(f"unknown strategy {strategy!r}")
     n = cut.n
     records, expanded = [], set()
+    round_start, round_left, restrict = 0, 0, None
     for r in range(n_recursions):
         if r == 0:
             active = list(first_active) if first_active is not None else list(range(min(n_active, n)))
             zoom = {}
             parent = (-1, -1)
         else:
-            pick = (chooser or choose_heaviest)(records, expanded)
+            if round_left == 0:
+                round_start, round_left, restrict = len(records), max(1, per_round), None
+            if chooser is not None:
+                pick = chooser(records, expanded)
+            else:
+                pick = CHOOSERS[strategy](records[:round_start], expanded, restrict)
+                if pick is None and len(records) > round_start:
+                    # the round's candidates ran dry: a new round also sees the
+                    # recursions this one made
+                    round_start, round_left, restrict = len(records), max(1, per_round), None
+                    pick = CHOOSERS[strategy](records[:round_start], expanded, None)
             if pick is None:
                 break
+            round_left -= 1
+            if restrict is None:
+                restrict = _restriction(strategy, records, pick)
             pr, pb = pick
             expanded.add(pick)
             prev = records[pr]
@@ -118,12 +154,64 @@ def reconstruct(entries, cut, n_active, n_recursions, first_active=None, chooser
             role[q] = ACTIVE
         merged = merge_entries(entries, cut, role)
         bins = bins_from_merged(merged, cut, role)
-        records.append(dict(parent=parent, role=role, zoom=zoom, active=sorted(active),
+        depth = 0 if parent[0] < 0 else records[parent[0]]["depth"] + 1
+        records.append(dict(parent=parent, role=role, zoom=zoom, active=sorted(active), depth=depth,
                             bins=bins, has_merged=any(v == MERGED for v in role)))
     return records
 
 
-def choose_heaviest(records, expanded):
+def _restriction(strategy, records, pick):
+    """What the remaining picks of a round are limited to."""
+    if strategy == "bfs":
+        return ("depth", records[pick[0]]["depth"])
+    if strategy == "dfs":
+        return ("rec", pick[0])
+    return None
+
+
+def _candidates(records, expanded):
+    """(recursion, bin, mass) of every unexpanded bin of a recursion that
+    still has merged qubits."""
+    out = []
+    for r, rec in enumerate(records):
+        if not rec["has_merged"]:
+            continue
+        for i, v in enumerate(rec["bins"]):
+            if (r, i) not in expanded:
+                out.append((r, i, float(v)))
+    return out
+
+
+def _mass_key(v):
+    return np.inf if np.isnan(v) else -v          # NaN ranks last
+
+
+def choose_dfs(records, expanded, restrict=None):
+    """Heaviest candidate of the latest recursion that has one."""
+    cands = _candidates(records, expanded)
+    if restrict is not None:
+        cands = [c for c in cands if c[0] == restrict[1]]
+    if not cands:
+        return None
+    last = max(c[0] for c in cands)
+    r, i, _ = min((c for c in cands if c[0] == last), key=lambda c: (_mass_key(c[2]), c[1]))
+    return (r, i)
+
+
+def choose_bfs(records, expanded, restrict=None):
+    """Heaviest candidate of the shallowest depth that has one."""
+    cands = _candidates(records, expanded)
+    if restrict is not None:
+        cands = [c for c in cands if records[c[0]]["depth"] == restrict[1]]
+    if not cands:
+        return None
+    top = min(records[c[0]]["depth"] for c in cands)
+    r, i, _ = min((c for c in cands if records[c[0]]["depth"] == top),
+                  key=lambda c: (_mass_key(c[2]), c[0], c[1]))
+    return (r, i)
+
+
+def choose_heaviest(records, expanded, restrict=None):
     """Largest bin mass among unexpanded bins of recursions with merged qubits;
     ties -> lowest (recursion, bin)."""
     best, best_val = None, None
@@ -140,3 +228,6 @@ def choose_heaviest(records, expanded):
         if best_val is None or b[i] > best_val:   # strict: earlier recursion wins ties
             best, best_val = (r, i), b[i]
     return best
+
+
+CHOOSERS = {"heaviest": choose_heaviest, "dfs": choose_dfs, "bfs": choose_bfs}
