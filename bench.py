@@ -272,6 +272,15 @@ def bench_dd(args, torch, cqc, W):
     ms = _sync_time(step, steps, warmup, torch)
     kt = _traced(step, steps, cqc, torch)
     bins, recs = holder["r"]
+
+    # the same search with four bins per host round trip: the four refinements
+    # of the first recursion have no merged qubits, so they are the same four
+    # picks, enqueued together behind one read-back
+    def step4(i):
+        holder["r4"] = cqc.reconstruct_dd(e32, cut, a, R, precision="fp32", bins_per_round=4)
+    ms4 = _sync_time(step4, steps, warmup, torch)
+    bins4, recs4 = holder["r4"]
+    same4 = [r["parent"] for r in recs4] == [r["parent"] for r in recs] and bool(torch.equal(bins4, bins))
     nrec = len(recs)
     per_call = {k: (v[0] / steps, v[1] / steps) for k, v in kt.items()}
     name, (cnt, tot) = max(per_call.items(), key=lambda kv: kv[1][1])
@@ -287,6 +296,7 @@ def bench_dd(args, torch, cqc, W):
                 {"n": inst.n, "K": inst.K, "n_active": a, "recursions": nrec, "precision": "fp32",
                  "seed": W.RECIPES["c4"]["seed"]},
                 roof, us_per_recursion=1e3 * ms / nrec, kernels_ms_per_call=per_call,
+                four_bins_per_round={"ms_per_step": ms4, "same_records": same4},
                 records=[{"parent": r["parent"], "mass": r["mass"]} for r in recs])
     if not args.no_cpu:
         from oracle import dd, native  # CPU-baseline leg only

@@ -221,21 +221,39 @@ int cqc_chi2(const void *a, cqc_dtype a_t, const void *b, cqc_dtype b_t, int64_t
 
 /* Dynamic definition (Algorithm 1, Section 4.3).
  * Recursion 1 makes `first_active` (or, if NULL, the first n_active qubits in
- * output order) active; every later recursion picks, among all bins produced
- * so far that are not yet expanded and still contain merged qubits, the one
- * with the largest FP64 mass (ties: lowest recursion, then lowest bin index),
- * zooms its active qubits to the bin's bits, and makes the next n_active
- * un-zoomed qubits in output order active.  Merged qubits are summed out of
- * the entries (FP64 accumulation) before the term sum.  Bin b of a recursion
- * has its active qubits (ascending id) as bits, first = most significant.
- * Stops early when no bin can be refined.
- * This call is host-driven: it synchronises `stream` once per recursion to
- * read the chosen bin, and returns after the last recursion completed. */
+ * output order) active; every later recursion refines one bin produced so far
+ * that is not yet expanded and still contains merged qubits (a candidate):
+ * it zooms the bin's recursion's active qubits to the bin's bits and makes
+ * the next n_active un-zoomed qubits in output order active.  Merged qubits
+ * are summed out of the entries (FP64 accumulation) before the term sum.  Bin
+ * b of a recursion has its active qubits (ascending id) as bits, first = most
+ * significant.  Stops early when no candidate is left.
+ * Which candidate (Section 4.3 names a depth-first search for sparse outputs
+ * and a breadth-first one for dense outputs):
+ *   CQC_DD_HEAVIEST  the largest FP64 mass over all recursions (Algorithm 1);
+ *                    ties: lowest recursion, then lowest bin index.
+ *   CQC_DD_DFS       the heaviest candidate of the most recent recursion that
+ *                    has one (a single-state recursion sends the search back
+ *                    up); ties: lowest bin index.  With several bins per
+ *                    round: the latest round, and in it the earliest pick.
+ *   CQC_DD_BFS       the heaviest candidate of the shallowest zoom depth that
+ *                    has one; ties: lowest recursion, then lowest bin index.
+ * Rounds: each round picks up to bins_per_round candidates, in the strategy's
+ * order, from the recursions that existed when the round began (limited to
+ * the first pick's depth for BFS and to its recursion for DFS; a round whose
+ * candidates run out ends early), then runs all of them.  bins_per_round = 1
+ * is the one-bin-per-recursion search; BFS gives the same records for every
+ * bins_per_round.
+ * This call is host-driven: it synchronises `stream` once per round (and once
+ * per extra candidate refill) and returns after the last recursion completed. */
+typedef enum { CQC_DD_HEAVIEST = 0, CQC_DD_DFS = 1, CQC_DD_BFS = 2 } cqc_dd_strategy;
+
 typedef struct {
   int32_t n_active;          /* a: active qubits per recursion, 1..30            */
   int32_t n_recursions;      /* R >= 1                                            */
   const int32_t *first_active; /* HOST [n_active] or NULL                         */
-  int32_t strategy;          /* 0 = heaviest unexpanded bin (Algorithm 1)        */
+  int32_t strategy;          /* cqc_dd_strategy                                   */
+  int32_t bins_per_round;    /* 0..64; 0 means 1                                  */
 } cqc_dd_params;
 
 typedef struct {

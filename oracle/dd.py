@@ -28,7 +28,10 @@ the readings here):
     recursions so far.
   * "dfs": the candidates of the most recent recursion that still has any,
     heaviest first; a recursion without merged qubits (a single state) sends
-    the search back to the latest recursion with candidates left.
+    the search back to the latest recursion with candidates left.  With
+    several bins per round, "most recent" means the latest round, and within
+    it the earliest (heaviest) pick, so the search continues under the
+    heaviest bin it just expanded.
   * "bfs": the candidates of the shallowest zoom depth that still has any,
     heaviest first across the recursions of that depth (ties: lowest
     recursion, then bin).
@@ -114,7 +117,7 @@ def reconstruct(entries, cut, n_active, n_recursions, first_active=None, chooser
         raise ValueError(f"unknown strategy {strategy!r}")
     n = cut.n
     records, expanded = [], set()
-    round_start, round_left, restrict = 0, 0, None
+    round_start, round_left, restrict, rnd = 0, 0, None, 0
     for r in range(n_recursions):
         if r == 0:
             active = list(first_active) if first_active is not None else list(range(min(n_active, n)))
@@ -122,7 +125,7 @@ def reconstruct(entries, cut, n_active, n_recursions, first_active=None, chooser
             parent = (-1, -1)
         else:
             if round_left == 0:
-                round_start, round_left, restrict = len(records), max(1, per_round), None
+                round_start, round_left, restrict, rnd = len(records), max(1, per_round), None, rnd + 1
             if chooser is not None:
                 pick = chooser(records, expanded)
             else:
@@ -130,7 +133,7 @@ def reconstruct(entries, cut, n_active, n_recursions, first_active=None, chooser
                 if pick is None and len(records) > round_start:
                     # the round's candidates ran dry: a new round also sees the
                     # recursions this one made
-                    round_start, round_left, restrict = len(records), max(1, per_round), None
+                    round_start, round_left, restrict, rnd = len(records), max(1, per_round), None, rnd + 1
                     pick = CHOOSERS[strategy](records[:round_start], expanded, None)
             if pick is None:
                 break
@@ -156,7 +159,7 @@ def reconstruct(entries, cut, n_active, n_recursions, first_active=None, chooser
         bins = bins_from_merged(merged, cut, role)
         depth = 0 if parent[0] < 0 else records[parent[0]]["depth"] + 1
         records.append(dict(parent=parent, role=role, zoom=zoom, active=sorted(active), depth=depth,
-                            bins=bins, has_merged=any(v == MERGED for v in role)))
+                            round=rnd, bins=bins, has_merged=any(v == MERGED for v in role)))
     return records
 
 
@@ -187,14 +190,16 @@ def _mass_key(v):
 
 
 def choose_dfs(records, expanded, restrict=None):
-    """Heaviest candidate of the latest recursion that has one."""
+    """Heaviest candidate of the most recent recursion that has one: the
+    latest round, and in it the earliest pick."""
     cands = _candidates(records, expanded)
     if restrict is not None:
         cands = [c for c in cands if c[0] == restrict[1]]
     if not cands:
         return None
-    last = max(c[0] for c in cands)
-    r, i, _ = min((c for c in cands if c[0] == last), key=lambda c: (_mass_key(c[2]), c[1]))
+    last = max(records[c[0]]["round"] for c in cands)
+    rec = min(c[0] for c in cands if records[c[0]]["round"] == last)
+    r, i, _ = min((c for c in cands if c[0] == rec), key=lambda c: (_mass_key(c[2]), c[1]))
     return (r, i)
 
 

@@ -291,8 +291,17 @@ def reconstruct_fd(entries, cut, precision="fp32", out_dtype=None, with_mass=Tru
     return call.outs[0], (call.mass[0] if with_mass else None)
 
 
-def reconstruct_dd(entries, cut, n_active, n_recursions, first_active=None, precision="fp32"):
-    """Dynamic definition (Algorithm 1) -> (bins [R_done, 2^a] float64, records list)."""
+DD_STRATEGIES = {"heaviest": 0, "dfs": 1, "bfs": 2}
+
+
+def reconstruct_dd(entries, cut, n_active, n_recursions, first_active=None, precision="fp32",
+                   strategy="heaviest", bins_per_round=1):
+    """Dynamic definition (Algorithm 1) -> (bins [R_done, 2^a] float64, records list).
+
+    strategy: "heaviest" (Algorithm 1), "dfs" or "bfs" (Section 4.3);
+    bins_per_round: bins expanded per host round trip."""
+    if strategy not in DD_STRATEGIES:
+        raise ValueError(f"unknown strategy {strategy!r}")
     in_dt = _check_entries(entries, cut)
     dev = entries[0].device
     ptrs = (ctypes.c_void_p * len(entries))(*[E.data_ptr() for E in entries])
@@ -300,14 +309,14 @@ def reconstruct_dd(entries, cut, n_active, n_recursions, first_active=None, prec
     fa = None
     if first_active is not None:
         fa = (ctypes.c_int32 * len(first_active))(*[int(q) for q in first_active])
-    params = _lib.CqcDDParams(int(n_active), int(n_recursions), fa, 0)
+    params = _lib.CqcDDParams(int(n_active), int(n_recursions), fa, DD_STRATEGIES[strategy], int(bins_per_round))
     L = _lib.lib()
     nb = ctypes.c_size_t(0)
     _lib.check(L.cqc_dd_workspace_size(ctypes.byref(inst), _DT[in_dt], PREC[precision],
                                        ctypes.byref(params), ctypes.byref(nb)))
     ws = _workspace(int(nb.value), dev)
     a = min(int(n_active), cut.n)
-    bins = torch.zeros((int(n_recursions), 2 ** a), dtype=torch.float64, device=dev)
+    bins = torch.empty((int(n_recursions), 2 ** a), dtype=torch.float64, device=dev)   # rows past n_done unused
     recs = (_lib.CqcDDRecord * int(n_recursions))()
     done = ctypes.c_int32(0)
     _lib.check(L.cqc_reconstruct_dd(ctypes.byref(inst), _DT[in_dt], PREC[precision],
@@ -318,9 +327,10 @@ def reconstruct_dd(entries, cut, n_active, n_recursions, first_active=None, prec
     for r in range(done.value):
         rec = recs[r]
         role = [int(rec.role[q]) for q in range(cut.n)]
-        out.append(dict(parent=(int(rec.parent_rec), int(rec.parent_bin)), n_active=int(rec.n_active),
-                        mass=float(rec.mass), role=role,
-                        active=[q for q in range(cut.n) if role[q] == -2]))
+        parent = (int(rec.parent_rec), int(rec.parent_bin))
+        out.append(dict(parent=parent, n_active=int(rec.n_active), mass=float(rec.mass), role=role,
+                        active=[q for q in range(cut.n) if role[q] == -2],
+                        depth=0 if parent[0] < 0 else out[parent[0]]["depth"] + 1))
     return bins[:done.value], out
 
 

@@ -6,15 +6,31 @@
 // active), never on which bin was chosen - only the zoomed VALUES depend on
 // the data.  So every depth's contraction plan and workspace are known before
 // anything runs; per recursion the host only learns which bin to refine.
+//
+// Recursions run in rounds: a round picks up to bins_per_round bins from the
+// recursions that existed when it began (in the order of the search strategy,
+// restricted to the first pick's depth for BFS and to its recursion for DFS),
+// enqueues every picked recursion's merge, term sum and top-T back to back,
+// and reads all their candidates and masses with one copy and one sync.
 #include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
+#include <mutex>
 
 #include "dd.hpp"
 
 namespace cqc {
+
+// >= 0 when pos[j] == pos[0] + j for every j (bit j of a packed index lands at
+// position shift + j), -1 otherwise; 0 for an empty list
+static int contiguous_shift(const std::vector<int> &pos) {
+  for (size_t j = 1; j < pos.size(); ++j)
+    if (pos[j] != pos[0] + (int)j) return -1;
+  return pos.empty() ? 0 : pos[0];
+}
 
 struct DepthPlan {
   std::vector<int> active;                   // ascending qubit ids
@@ -27,10 +43,18 @@ struct DepthPlan {
   size_t end = 0;
 };
 
+// what a round reads back per recursion: its top-T candidates and its mass
+struct DdSlot {
+  TopOut top;
+  double mass;
+};
+
+constexpr int kDdMaxPerRound = 64;
+
 struct DdPlan {
   CutInfo cut;
   Acc acc;
-  int a = 0, R = 0;
+  int a = 0, R = 0, strategy = 0, per_round = 1;
   std::vector<DepthPlan> depths;
   size_t topk_off = 0, out_off = 0, bytes = 0;
 };
@@ -49,7 +73,12 @@ static Status build_dd(const cqc_instance *inst, cqc_dtype in_t, cqc_precision p
   }
   CQC_TRY(validate_cut(&inst->cut, CQC_MAX_DD_QUBITS, &d.cut));
   const int n = d.cut.n;
-  if (p->strategy != 0) return Status::fail(CQC_ERR_UNSUPPORTED, "only strategy 0 (heaviest bin) is implemented");
+  if (p->strategy < CQC_DD_HEAVIEST || p->strategy > CQC_DD_BFS)
+    return Status::fail(CQC_ERR_INVALID_ARG, "unknown strategy");
+  if (p->bins_per_round < 0 || p->bins_per_round > kDdMaxPerRound)
+    return Status::fail(CQC_ERR_INVALID_ARG, "bins_per_round must be in [0, 64]");
+  d.strategy = p->strategy;
+  d.per_round = std::max(1, (int)p->bins_per_round);
   if (p->n_active < 1 || p->n_active > 30) return Status::fail(CQC_ERR_INVALID_ARG, "n_active must be in [1, 30]");
   if (p->n_recursions < 1) return Status::fail(CQC_ERR_INVALID_ARG, "n_recursions must be >= 1");
   if (n < 1) return Status::fail(CQC_ERR_SHAPE, "dynamic definition needs at least one qubit");
@@ -107,6 +136,18 @@ static Status build_dd(const cqc_instance *inst, cqc_dtype in_t, cqc_precision p
       off += esz * (size_t)plan.tensors[c].rows() * ((size_t)1 << dp.act_local[c].size());
     }
     dp.net = layout_net(plan, d.acc, off);
+    // a recursion's steps are small (2^a bins at most): prefer more, smaller
+    // register tiles so the grid covers the chip (64 x 256 tiles leave most
+    // CUs idle below 2^22 outputs)
+    for (size_t i = 0; i < dp.net.tile.size(); ++i) {
+      const Step &st = dp.net.plan.steps[i];
+      const int64_t M = int64_t(1) << st.logM, N = int64_t(1) << st.logN;
+      if (dp.net.tile[i] == kTileL && M * N * st.nbatch < (int64_t(1) << 22) && M >= 32 && N >= 128) {
+        dp.net.tile[i] = kTileM;
+        const TileShape sh = tile_shape(kTileM);
+        dp.net.nblocks[i] = ((M + sh.bm - 1) / sh.bm) * ((N + sh.bn - 1) / sh.bn) * st.nbatch;
+      }
+    }
     dp.end = dp.net.bytes;
     d.depths.push_back(std::move(dp));
     // next depth
@@ -120,7 +161,7 @@ static Status build_dd(const cqc_instance *inst, cqc_dtype in_t, cqc_precision p
   for (auto &dp : d.depths) end = std::max(end, dp.end);
   d.topk_off = align_up(end, 256);
   d.out_off = align_up(d.topk_off + topk_scratch_bytes(int64_t(1) << d.a, kTopT), 256);
-  d.bytes = align_up(d.out_off + sizeof(TopOut) + 8, 256);
+  d.bytes = align_up(d.out_off + sizeof(DdSlot) * (size_t)d.per_round, 256);
   *out = std::move(d);
   return Status::ok();
 }
@@ -128,6 +169,7 @@ static Status build_dd(const cqc_instance *inst, cqc_dtype in_t, cqc_precision p
 namespace {
 struct RecState {
   int depth = 0;
+  int round = 0;
   std::map<int, int> zoomval;        // qubit -> 0/1
   std::vector<std::pair<double, int64_t>> cands;
   size_t consumed = 0;
@@ -136,6 +178,55 @@ struct RecState {
   int64_t nbins = 0;
 };
 }  // namespace
+
+// Plans of recent calls, keyed by every input that determines them (the cut,
+// dtypes, precision and parameters): a repeated query skips re-planning every
+// depth.  Only successful builds are stored; the cache is bounded and guarded.
+static bool dd_key(const cqc_instance *inst, cqc_dtype in_t, cqc_precision prec, const cqc_dd_params *p,
+                   std::vector<int64_t> *key) {
+  if (!inst || !p) return false;
+  const cqc_cut &c = inst->cut;
+  if (c.n_qubits < 0 || c.n_qubits > CQC_MAX_DD_QUBITS || c.n_sub < 0 || c.n_sub > CQC_MAX_SUB || c.n_cuts < 0 ||
+      c.n_cuts > CQC_MAX_CUTS || !c.f || !c.out_qubit || (c.n_cuts > 0 && (!c.edge_up || !c.edge_down)))
+    return false;
+  if (p->n_active < 1 || p->n_active > 30 || (p->first_active && p->n_active > c.n_qubits)) return false;
+  key->assign({c.n_qubits, c.n_sub, c.n_cuts, (int64_t)in_t, (int64_t)prec, p->n_active, p->n_recursions,
+               p->strategy, p->bins_per_round, p->first_active ? 1 : 0});
+  for (int i = 0; i < c.n_sub; ++i) key->push_back(c.f[i]);
+  for (int e = 0; e < c.n_cuts; ++e) {
+    key->push_back(c.edge_up[e]);
+    key->push_back(c.edge_down[e]);
+  }
+  for (int q = 0; q < c.n_qubits; ++q) key->push_back(c.out_qubit[q]);
+  if (p->first_active)
+    for (int i = 0; i < p->n_active; ++i) key->push_back(p->first_active[i]);
+  return true;
+}
+
+static Status cached_dd(const cqc_instance *inst, cqc_dtype in_t, cqc_precision prec, const cqc_dd_params *p,
+                        std::shared_ptr<const DdPlan> *out) {
+  static std::mutex mu;
+  static std::map<std::vector<int64_t>, std::shared_ptr<const DdPlan>> cache;
+  std::vector<int64_t> key;
+  const bool keyed = dd_key(inst, in_t, prec, p, &key);
+  if (keyed) {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      *out = it->second;
+      return Status::ok();
+    }
+  }
+  auto plan = std::make_shared<DdPlan>();
+  CQC_TRY(build_dd(inst, in_t, prec, p, plan.get()));
+  if (keyed) {
+    std::lock_guard<std::mutex> g(mu);
+    if (cache.size() >= 64) cache.clear();
+    cache[key] = plan;
+  }
+  *out = std::move(plan);
+  return Status::ok();
+}
 
 }  // namespace cqc
 
@@ -146,19 +237,20 @@ extern "C" {
 int cqc_dd_workspace_size(const cqc_instance *inst, cqc_dtype in_t, cqc_precision prec,
                           const cqc_dd_params *p, size_t *bytes) {
   if (!bytes) return Status::fail(CQC_ERR_INVALID_ARG, "bytes is NULL").code;
-  DdPlan d;
-  Status st = build_dd(inst, in_t, prec, p, &d);
+  std::shared_ptr<const DdPlan> plan;
+  Status st = cached_dd(inst, in_t, prec, p, &plan);
   if (!st.good()) return st.code;
-  *bytes = d.bytes;
+  *bytes = plan->bytes;
   return CQC_OK;
 }
 
 int cqc_reconstruct_dd(const cqc_instance *inst, cqc_dtype in_t, cqc_precision prec,
                        const cqc_dd_params *p, double *bins, cqc_dd_record *records,
                        int32_t *n_done, void *workspace, size_t ws_bytes, hipStream_t stream) {
-  DdPlan d;
-  Status st = build_dd(inst, in_t, prec, p, &d);
+  std::shared_ptr<const DdPlan> plan;
+  Status st = cached_dd(inst, in_t, prec, p, &plan);
   if (!st.good()) return st.code;
+  const DdPlan &d = *plan;
   if (!bins || !records || !n_done) return Status::fail(CQC_ERR_INVALID_ARG, "bins, records or n_done is NULL").code;
   if (!inst->entries) return Status::fail(CQC_ERR_INVALID_ARG, "entries is NULL").code;
   for (int c = 0; c < d.cut.nsub; ++c)
@@ -171,147 +263,195 @@ int cqc_reconstruct_dd(const cqc_instance *inst, cqc_dtype in_t, cqc_precision p
   const int n = d.cut.n;
   const bool in_double = in_t == CQC_F64, acc_double = d.acc == Acc::F64;
   const int64_t stride = int64_t(1) << d.a;
-  TopOut *dev_top = reinterpret_cast<TopOut *>(ws + d.out_off);
-  double *dev_mass = reinterpret_cast<double *>(ws + d.out_off + sizeof(TopOut));
+  DdSlot *dev_slots = reinterpret_cast<DdSlot *>(ws + d.out_off);
+  std::vector<DdSlot> host_slots(d.per_round);
   std::vector<RecState> recs;
   *n_done = 0;
 
-  auto fetch = [&](TopOut *top, double *mass) -> Status {
-    struct {
-      TopOut t;
-      double m;
-    } host;
-    CQC_HIP_TRY(hipMemcpyAsync(&host, dev_top, sizeof(TopOut) + 8, hipMemcpyDeviceToHost, stream));
+  auto fetch = [&](int count) -> Status {
+    CQC_HIP_TRY(hipMemcpyAsync(host_slots.data(), dev_slots, sizeof(DdSlot) * count, hipMemcpyDeviceToHost,
+                               stream));
     CQC_HIP_TRY(hipStreamSynchronize(stream));
-    if (top) *top = host.t;
-    if (mass) *mass = host.m;
     return Status::ok();
   };
-  auto refill = [&](int k) -> Status {
-    RecState &rs = recs[k];
-    double av = INFINITY;
-    int64_t ai = -1;
-    if (!rs.cands.empty()) {
-      av = rs.cands.back().first;
-      ai = rs.cands.back().second;
-    }
-    CQC_TRY(launch_topk(bins + (int64_t)k * stride, rs.nbins, kTopT, ws + d.topk_off, dev_top, av, ai, stream));
-    TopOut top;
-    CQC_TRY(fetch(&top, nullptr));
+  auto take = [&](RecState &rs, const TopOut &top) {
     int got = 0;
     for (int t = 0; t < kTopT; ++t)
       if (top.index[t] != INT64_MAX) {
         rs.cands.push_back({top.value[t], top.index[t]});
         ++got;
       }
-    if (got < kTopT) rs.exhausted = true;
+    rs.exhausted = got < kTopT;
+  };
+  // the next candidates of recursion k, ranked after the ones already taken
+  auto refill = [&](int k) -> Status {
+    RecState &rs = recs[k];
+    const double av = rs.cands.back().first;
+    const int64_t ai = rs.cands.back().second;
+    CQC_TRY(launch_topk(bins + (int64_t)k * stride, rs.nbins, kTopT, ws + d.topk_off, &dev_slots[0].top, av, ai,
+                        stream));
+    CQC_TRY(fetch(1));
+    take(rs, host_slots[0].top);
     return Status::ok();
   };
+  // does recursion k (of the round's first `start`) have a candidate left?
+  auto available = [&](int k, Status &err) -> bool {
+    RecState &rk = recs[k];
+    if (!rk.has_merged) return false;
+    if (rk.consumed == rk.cands.size() && !rk.exhausted) {
+      err = refill(k);
+      if (!err.good()) return false;
+    }
+    return rk.consumed < rk.cands.size();
+  };
+  auto top_of = [&](int k) { return recs[k].cands[recs[k].consumed].first; };
+  // the strategy's next pick among recursions [0, start), or -1
+  auto choose = [&](int start, int restrict_val, Status &err) -> int {
+    int best = -1;
+    if (d.strategy == CQC_DD_DFS) {
+      // the latest round with a candidate, and in it the earliest pick
+      // (rounds never decrease along the records)
+      for (int k = start - 1; k >= 0; --k) {
+        if (best >= 0 && recs[k].round < recs[best].round) break;
+        if (restrict_val >= 0 && k != restrict_val) continue;
+        if (available(k, err)) best = k;
+        if (!err.good()) return -1;
+      }
+      return best;
+    }
+    int best_depth = INT_MAX;
+    for (int k = 0; k < start; ++k) {
+      if (d.strategy == CQC_DD_BFS && restrict_val >= 0 && recs[k].depth != restrict_val) continue;
+      if (!available(k, err)) {
+        if (!err.good()) return -1;
+        continue;
+      }
+      const int dk = d.strategy == CQC_DD_BFS ? recs[k].depth : 0;
+      if (best < 0 || dk < best_depth || (dk == best_depth && top_of(k) > top_of(best))) {
+        best = k;
+        best_depth = dk;
+      }
+    }
+    return best;
+  };
 
-  for (int r = 0; r < d.R; ++r) {
-    RecState rs;
-    int parent = -1;
-    int64_t pbin = -1;
-    if (r > 0) {
-      int best = -1;
-      for (int k = 0; k < (int)recs.size(); ++k) {
-        RecState &ck = recs[k];
-        if (!ck.has_merged) continue;
-        if (ck.consumed == ck.cands.size() && !ck.exhausted) {
-          st = refill(k);
-          if (!st.good()) return st.code;
-        }
-        if (ck.consumed == ck.cands.size()) continue;
-        if (best < 0 || ck.cands[ck.consumed].first > recs[best].cands[recs[best].consumed].first) best = k;
-      }
-      if (best < 0) break;
-      parent = best;
-      pbin = recs[best].cands[recs[best].consumed].second;
-      recs[best].consumed++;
-      const RecState &pr = recs[best];
-      rs.depth = pr.depth + 1;
-      rs.zoomval = pr.zoomval;
-      const auto &pact = d.depths[pr.depth].active;
-      const int pa = (int)pact.size();
-      for (int t = 0; t < pa; ++t) rs.zoomval[pact[t]] = (int)((pbin >> (pa - 1 - t)) & 1);
-    }
-    if (rs.depth >= (int)d.depths.size()) break;
-    const DepthPlan &dp = d.depths[rs.depth];
-    // ---- merge (FP64 accumulate) the entries over the merged qubits
-    MergeArgs ma;
-    std::memset(&ma, 0, sizeof(ma));
-    ma.n = d.cut.nsub;
-    int64_t blocks = 0;
-    std::vector<const void *> merged(d.cut.nsub);
-    for (int c = 0; c < d.cut.nsub; ++c) {
-      MergeDesc &md = ma.d[c];
-      const int f = d.cut.f[c];
-      md.src = inst->entries[c];
-      md.dst = ws + dp.merged_off[c];
-      merged[c] = md.dst;
-      md.rows = int64_t(1) << (2 * d.cut.inc[c].size());
-      md.f = f;
-      md.n_active = (int)dp.act_local[c].size();
-      md.n_merged = (int)dp.mrg_local[c].size();
-      std::vector<int> apos, mpos;
-      for (int k = md.n_active - 1; k >= 0; --k) apos.push_back(f - 1 - dp.act_local[c][k]);
-      for (int k = md.n_merged - 1; k >= 0; --k) mpos.push_back(f - 1 - dp.mrg_local[c][k]);
-      md.active_pos = pack_pos(apos);
-      md.merged_pos = pack_pos(mpos);
-      md.merged_low_contig = 1;
-      for (int k = 0; k < md.n_merged; ++k)
-        if (mpos[k] != k) md.merged_low_contig = 0;
-      int64_t zv = 0;
-      for (int j = 0; j < f; ++j) {
-        const int q = d.cut.qubits[c][j];
-        auto it = rs.zoomval.find(q);
-        if (it != rs.zoomval.end() && it->second) zv |= int64_t(1) << (f - 1 - j);
-      }
-      md.zoom_value = zv;
-      md.block_start = blocks;
-      const int64_t nout = md.rows << md.n_active;
-      blocks += md.n_merged >= 6 ? (nout + 3) / 4 : (nout + 255) / 256;
-    }
-    st = launch_dd_merge(ma, blocks, in_double, acc_double, stream);
-    if (!st.good()) return st.code;
-    // ---- term sum onto the 2^#active bins (FP64 output and FP64 bin mass)
-    double *brow = bins + (int64_t)r * stride;
-    st = run_net(dp.net, ws, merged, brow, true, dev_mass, true, stream);
-    if (!st.good()) return st.code;
-    rs.has_merged = dp.has_merged;
-    rs.nbins = int64_t(1) << dp.active.size();
-    // ---- candidates for later zooming
-    double mass = 0.0;
-    if (dp.has_merged && r + 1 < d.R) {
-      st = launch_topk(brow, rs.nbins, kTopT, ws + d.topk_off, dev_top, INFINITY, -1, stream);
-      if (!st.good()) return st.code;
-      TopOut top;
-      st = fetch(&top, &mass);
-      if (!st.good()) return st.code;
-      int got = 0;
-      for (int t = 0; t < kTopT; ++t)
-        if (top.index[t] != INT64_MAX) {
-          rs.cands.push_back({top.value[t], top.index[t]});
-          ++got;
-        }
-      rs.exhausted = got < kTopT;
+  int r = 0, round = 0;
+  while (r < d.R) {
+    // ---- picks of this round
+    std::vector<std::pair<int, int64_t>> picks;
+    if (r == 0) {
+      picks.push_back({-1, -1});
     } else {
-      st = fetch(nullptr, &mass);
-      if (!st.good()) return st.code;
-      rs.exhausted = true;
+      const int start = (int)recs.size();
+      const int lim = std::min(d.per_round, d.R - r);
+      int restrict_val = -1;
+      while ((int)picks.size() < lim) {
+        Status err = Status::ok();
+        const int k = choose(start, restrict_val, err);
+        if (!err.good()) return err.code;
+        if (k < 0) break;
+        picks.push_back({k, recs[k].cands[recs[k].consumed].second});
+        recs[k].consumed++;
+        if (restrict_val < 0 && d.strategy == CQC_DD_DFS) restrict_val = k;
+        if (restrict_val < 0 && d.strategy == CQC_DD_BFS) restrict_val = recs[k].depth;
+      }
+      if (picks.empty()) break;
     }
-    // ---- record
-    cqc_dd_record &rec = records[r];
-    std::memset(&rec, 0, sizeof(rec));
-    rec.parent_rec = parent;
-    rec.parent_bin = pbin;
-    rec.n_active = (int32_t)dp.active.size();
-    rec.mass = mass;
-    for (int q = 0; q < n; ++q) rec.role[q] = -1;
-    for (auto &kv : rs.zoomval) rec.role[kv.first] = (int8_t)kv.second;
-    for (int q : dp.active) rec.role[q] = -2;
-    recs.push_back(std::move(rs));
-    *n_done = r + 1;
+    // ---- enqueue every picked recursion
+    std::vector<RecState> fresh;
+    for (size_t i = 0; i < picks.size(); ++i) {
+      RecState rs;
+      rs.round = round;
+      const int parent = picks[i].first;
+      const int64_t pbin = picks[i].second;
+      if (parent >= 0) {
+        const RecState &pr = recs[parent];
+        rs.depth = pr.depth + 1;
+        rs.zoomval = pr.zoomval;
+        const auto &pact = d.depths[pr.depth].active;
+        const int pa = (int)pact.size();
+        for (int t = 0; t < pa; ++t) rs.zoomval[pact[t]] = (int)((pbin >> (pa - 1 - t)) & 1);
+      }
+      if (rs.depth >= (int)d.depths.size())
+        return Status::fail(CQC_ERR_UNSUPPORTED, "dynamic definition: no plan for a picked depth").code;
+      const DepthPlan &dp = d.depths[rs.depth];
+      // merge (FP64 accumulate) the entries over the merged qubits
+      MergeArgs ma;
+      std::memset(&ma, 0, sizeof(ma));
+      int64_t blocks = 0;
+      std::vector<const void *> merged(d.cut.nsub);
+      for (int c = 0; c < d.cut.nsub; ++c) {
+        const int f = d.cut.f[c];
+        // every bit active, in local order, and no conversion: the merged
+        // tensor is the entry tensor itself
+        if (dp.mrg_local[c].empty() && (int)dp.act_local[c].size() == f && in_double == acc_double) {
+          merged[c] = inst->entries[c];
+          continue;
+        }
+        MergeDesc &md = ma.d[ma.n++];
+        md.src = inst->entries[c];
+        md.dst = ws + dp.merged_off[c];
+        merged[c] = md.dst;
+        md.rows = int64_t(1) << (2 * d.cut.inc[c].size());
+        md.f = f;
+        md.n_active = (int)dp.act_local[c].size();
+        md.n_merged = (int)dp.mrg_local[c].size();
+        std::vector<int> apos, mpos;
+        for (int k = md.n_active - 1; k >= 0; --k) apos.push_back(f - 1 - dp.act_local[c][k]);
+        for (int k = md.n_merged - 1; k >= 0; --k) mpos.push_back(f - 1 - dp.mrg_local[c][k]);
+        md.active_pos = pack_pos(apos);
+        md.merged_pos = pack_pos(mpos);
+        md.active_shift = contiguous_shift(apos);
+        md.merged_shift = contiguous_shift(mpos);
+        int64_t zv = 0;
+        for (int j = 0; j < f; ++j) {
+          const int q = d.cut.qubits[c][j];
+          auto it = rs.zoomval.find(q);
+          if (it != rs.zoomval.end() && it->second) zv |= int64_t(1) << (f - 1 - j);
+        }
+        md.zoom_value = zv;
+        md.block_start = blocks;
+        const int64_t nout = md.rows << md.n_active;
+        blocks += md.n_merged >= 6 ? (nout + 3) / 4 : (nout + 255) / 256;
+      }
+      st = launch_dd_merge(ma, blocks, in_double, acc_double, stream);
+      if (!st.good()) return st.code;
+      // term sum onto the 2^#active bins (FP64 output and FP64 bin mass)
+      double *brow = bins + (int64_t)(r + i) * stride;
+      st = run_net(dp.net, ws, merged, brow, true, &dev_slots[i].mass, true, stream);
+      if (!st.good()) return st.code;
+      rs.has_merged = dp.has_merged;
+      rs.nbins = int64_t(1) << dp.active.size();
+      // candidates for later zooming
+      if (dp.has_merged && r + (int)i + 1 < d.R) {
+        st = launch_topk(brow, rs.nbins, kTopT, ws + d.topk_off, &dev_slots[i].top, INFINITY, -1, stream);
+        if (!st.good()) return st.code;
+      } else {
+        rs.exhausted = true;
+      }
+      fresh.push_back(std::move(rs));
+    }
+    // ---- one read-back for the round
+    st = fetch((int)picks.size());
+    if (!st.good()) return st.code;
+    for (size_t i = 0; i < picks.size(); ++i) {
+      RecState &rs = fresh[i];
+      const DepthPlan &dp = d.depths[rs.depth];
+      if (!rs.exhausted) take(rs, host_slots[i].top);
+      cqc_dd_record &rec = records[r + i];
+      std::memset(&rec, 0, sizeof(rec));
+      rec.parent_rec = picks[i].first;
+      rec.parent_bin = picks[i].second;
+      rec.n_active = (int32_t)dp.active.size();
+      rec.mass = host_slots[i].mass;
+      for (int q = 0; q < n; ++q) rec.role[q] = -1;
+      for (auto &kv : rs.zoomval) rec.role[kv.first] = (int8_t)kv.second;
+      for (int q : dp.active) rec.role[q] = -2;
+      recs.push_back(std::move(rs));
+    }
+    r += (int)picks.size();
+    ++round;
+    *n_done = r;
   }
   return CQC_OK;
 }

@@ -15,7 +15,8 @@ struct MergeDesc {
   int64_t rows;
   int32_t f;
   int32_t n_active, n_merged;
-  int32_t merged_low_contig;  // merged bits are exactly local positions 0..n_merged-1
+  int32_t active_shift;   // >= 0: active bit j sits at local position active_shift + j
+  int32_t merged_shift;   // >= 0: merged bit j sits at local position merged_shift + j
   int64_t zoom_value;     // fixed bits of the zoomed qubits at their local positions
   BitPos active_pos;      // active bit j (from least significant) -> local position
   BitPos merged_pos;

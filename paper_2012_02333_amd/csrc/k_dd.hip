@@ -31,17 +31,28 @@ __global__ __launch_bounds__(256) void k_dd_merge(const MergeArgs a) {
   const int64_t nout = d.rows << d.n_active;
   const int64_t nmerge = int64_t(1) << d.n_merged;
   const int64_t f = int64_t(1) << d.f;
-  const bool low_contig = d.merged_low_contig;
+  const int ash = d.active_shift, msh = d.merged_shift;
   if (nmerge >= 64) {
     const int64_t o = (bid - d.block_start) * 4 + (threadIdx.x >> 6);
     if (o >= nout) return;
     const int lane = threadIdx.x & 63;
     const int64_t r = o >> d.n_active, av = o & ((int64_t(1) << d.n_active) - 1);
-    const int64_t base = dep_bits(av, d.active_pos, d.n_active) | d.zoom_value;
+    const int64_t base = (ash >= 0 ? av << ash : dep_bits(av, d.active_pos, d.n_active)) | d.zoom_value;
     const I *row = E + r * f;
-    double s = 0.0;
-    for (int64_t m = lane; m < nmerge; m += 64)
-      s += (double)row[base | (low_contig ? m : dep_bits(m, d.merged_pos, d.n_merged))];
+    // eight accumulators per lane (lane + 64 (8 q + u) goes to u), so eight
+    // loads are in flight; combined in a fixed tree, then across the wave
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t m0 = lane; m0 < nmerge; m0 += 8 * 64) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t m = m0 + u * 64;
+        v[u] = m < nmerge ? (double)row[base | (msh >= 0 ? m << msh : dep_bits(m, d.merged_pos, d.n_merged))] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] += v[u];
+    }
+    double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
 #pragma unroll
     for (int w = 32; w >= 1; w >>= 1) s += __shfl_xor(s, w, 64);
     if (lane == 0) Out[o] = (O)s;
@@ -49,11 +60,11 @@ __global__ __launch_bounds__(256) void k_dd_merge(const MergeArgs a) {
     const int64_t o = (bid - d.block_start) * 256 + threadIdx.x;
     if (o >= nout) return;
     const int64_t r = o >> d.n_active, av = o & ((int64_t(1) << d.n_active) - 1);
-    const int64_t base = dep_bits(av, d.active_pos, d.n_active) | d.zoom_value;
+    const int64_t base = (ash >= 0 ? av << ash : dep_bits(av, d.active_pos, d.n_active)) | d.zoom_value;
     const I *row = E + r * f;
     double s = 0.0;
     for (int64_t m = 0; m < nmerge; ++m)
-      s += (double)row[base | (low_contig ? m : dep_bits(m, d.merged_pos, d.n_merged))];
+      s += (double)row[base | (msh >= 0 ? m << msh : dep_bits(m, d.merged_pos, d.n_merged))];
     Out[o] = (O)s;
   }
 }
@@ -69,65 +80,108 @@ __device__ __forceinline__ bool better(const Cand &a, const Cand &b) {
 // NaN never wins: it compares false both ways, so treat it as -inf.
 __device__ __forceinline__ double key(double v) { return v != v ? -__builtin_inf() : v; }
 
-// Block-wide selection of the best `t` candidates from per-thread sorted
-// lists (best first) of length <= kTopT.
-__device__ void block_select(Cand (&mine)[kTopT], int nmine, int t, Cand *out, Cand *lds) {
-  int head = 0;
-  for (int k = 0; k < t; ++k) {
-    Cand c = head < nmine ? mine[head] : Cand{-__builtin_inf(), INT64_MAX};
-    lds[threadIdx.x] = c;
-    __syncthreads();
-    for (int w = 128; w >= 1; w >>= 1) {
-      if ((int)threadIdx.x < w && better(lds[threadIdx.x + w], lds[threadIdx.x]))
-        lds[threadIdx.x] = lds[threadIdx.x + w];
-      __syncthreads();
+constexpr Cand kNoCand{-__builtin_inf(), INT64_MAX};
+
+// Per-thread ranking of the best kTopT candidates seen, best first, kept in
+// registers: every index is a compile-time constant, and a new candidate
+// bubbles down the list by branch-free compare-and-swap.
+__device__ __forceinline__ void push_cand(Cand (&m)[kTopT], Cand c) {
+#pragma unroll
+  for (int k = 0; k < kTopT; ++k) {
+    // selects on values, not on references, so the list stays in registers
+    const double mv = m[k].v, cv = c.v;
+    const int64_t mi = m[k].i, ci = c.i;
+    const bool b = cv > mv || (cv == mv && ci < mi);
+    m[k].v = b ? cv : mv;
+    m[k].i = b ? ci : mi;
+    c.v = b ? mv : cv;
+    c.i = b ? mi : ci;
+  }
+}
+
+// Block-wide best kTopT of the per-thread rankings: kTopT rounds of a wave
+// argmax (shuffles) and a combine of the NW wave winners in LDS; the thread holding the
+// winner pops it.  Bin indices are unique, so exactly one thread pops.
+template <int NW>
+__device__ __forceinline__ void block_top(Cand (&m)[kTopT], Cand *out) {
+  __shared__ Cand wbest[NW];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll 1
+  for (int k = 0; k < kTopT; ++k) {
+    Cand c = m[0];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const double xv = __shfl_xor(c.v, o, 64);
+      const int64_t xi = (int64_t)__shfl_xor((long long)c.i, o, 64);
+      const bool b = xv > c.v || (xv == c.v && xi < c.i);
+      c.v = b ? xv : c.v;
+      c.i = b ? xi : c.i;
     }
-    const Cand win = lds[0];
-    if (threadIdx.x == 0) out[k] = win;
-    if (head < nmine && mine[head].i == win.i && mine[head].v == win.v) ++head;
+    if (lane == 0) wbest[wave] = c;
     __syncthreads();
+    Cand w = wbest[0];
+#pragma unroll
+    for (int j = 1; j < NW; ++j)
+      if (better(wbest[j], w)) w = wbest[j];
+    __syncthreads();
+    if (threadIdx.x == 0) out[k] = w;
+    if (w.i != INT64_MAX && m[0].i == w.i) {
+#pragma unroll
+      for (int j = 0; j + 1 < kTopT; ++j) m[j] = m[j + 1];
+      m[kTopT - 1] = kNoCand;
+    }
   }
 }
 
-__device__ void insert_cand(Cand (&mine)[kTopT], int &n, int t, Cand c) {
-  if (n == t && !better(c, mine[t - 1])) return;
-  int p = n < t ? n++ : t - 1;
-  while (p > 0 && better(c, mine[p - 1])) {
-    mine[p] = mine[p - 1];
-    --p;
-  }
-  mine[p] = c;
-}
-
-// Stage 1: each block reduces a contiguous range of bins to its best t among
-// the candidates ranked strictly after `after` (so a consumed prefix of the
+// Stage 1: each block ranks a contiguous range of bins, keeping only the
+// candidates ranked strictly after `after` (so a consumed prefix of the
 // ranking can be skipped when more candidates are needed).
-__global__ __launch_bounds__(256) void k_topk_stage1(const double *bins, int64_t count, int t,
-                                                     int64_t per_block, Cand *partial, double after_v,
-                                                     int64_t after_i) {
-  __shared__ Cand lds[256];
-  Cand mine[kTopT];
-  int n = 0;
+__global__ __launch_bounds__(256) void k_topk_stage1(const double *bins, int64_t count, int64_t per_block,
+                                                     Cand *partial, double after_v, int64_t after_i) {
+  Cand m[kTopT];
+#pragma unroll
+  for (int k = 0; k < kTopT; ++k) m[k] = kNoCand;
   const Cand after{after_v, after_i};
   const int64_t b0 = (int64_t)blockIdx.x * per_block;
   const int64_t b1 = count < b0 + per_block ? count : b0 + per_block;
-  for (int64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
-    const Cand c{key(bins[i]), i};
-    if (better(after, c)) insert_cand(mine, n, t, c);
+  // chunks of 2048 bins: a thread's eight loads are all in flight before it
+  // ranks them
+  for (int64_t c0 = b0; c0 < b1; c0 += 8 * 256) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t i = c0 + u * 256 + threadIdx.x;
+      v[u] = i < b1 ? bins[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t i = c0 + u * 256 + threadIdx.x;
+      const Cand c{key(v[u]), i};
+      if (i < b1 && better(after, c)) push_cand(m, c);
+    }
   }
-  block_select(mine, n, t, partial + (int64_t)blockIdx.x * t, lds);
+  block_top<4>(m, partial + (int64_t)blockIdx.x * kTopT);
 }
 
-// Stage 2: one block reduces all stage-1 candidates to the best t.
-__global__ __launch_bounds__(256) void k_topk_stage2(const Cand *partial, int64_t count, int t,
-                                                     TopOut *out) {
-  __shared__ Cand lds[256];
+// Stage 2: one block of 1024 threads ranks all stage-1 candidates (at most
+// 1024 blocks x kTopT: eight per thread, all loaded before ranking) and
+// writes the best t.
+__global__ __launch_bounds__(1024) void k_topk_stage2(const Cand *partial, int64_t count, int t, TopOut *out) {
   __shared__ Cand res[kTopT];
-  Cand mine[kTopT];
-  int n = 0;
-  for (int64_t i = threadIdx.x; i < count; i += blockDim.x) insert_cand(mine, n, t, partial[i]);
-  block_select(mine, n, t, res, lds);
-  if (threadIdx.x < t) {
+  Cand m[kTopT];
+#pragma unroll
+  for (int k = 0; k < kTopT; ++k) m[k] = kNoCand;
+  Cand v[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int64_t i = u * 1024 + threadIdx.x;
+    v[u] = i < count ? partial[i] : kNoCand;
+  }
+#pragma unroll
+  for (int u = 0; u < 8; ++u) push_cand(m, v[u]);
+  block_top<16>(m, res);
+  __syncthreads();
+  if ((int)threadIdx.x < t) {
     out->value[threadIdx.x] = res[threadIdx.x].v;
     out->index[threadIdx.x] = res[threadIdx.x].i;
   }
@@ -144,19 +198,22 @@ Status launch_dd_merge(const MergeArgs &a, int64_t blocks, bool in_double, bool 
 }
 
 size_t topk_scratch_bytes(int64_t count, int t) {
+  (void)t;
   const int64_t blocks = std::min<int64_t>(1024, (count + 2047) / 2048);
-  return sizeof(Cand) * (size_t)(blocks * t);
+  return sizeof(Cand) * (size_t)(blocks * kTopT);
 }
 
 Status launch_topk(const double *bins, int64_t count, int t, void *scratch, TopOut *out,
                    double after_v, int64_t after_i, hipStream_t s) {
   const int64_t blocks = std::min<int64_t>(1024, (count + 2047) / 2048);
   const int64_t per_block = (count + blocks - 1) / blocks;
+  if (t < 1 || t > kTopT) return Status::fail(CQC_ERR_INVALID_ARG, "top-k count out of range");
   Cand *partial = static_cast<Cand *>(scratch);
-  CQC_TRY(launch("topk_stage1", k_topk_stage1, dim3((unsigned)blocks), dim3(256), 0, s, bins, count, t,
-                 per_block, partial, after_v, after_i));
-  return launch("topk_stage2", k_topk_stage2, dim3(1), dim3(256), 0, s,
-                static_cast<const Cand *>(partial), blocks * t, t, out);
+  CQC_TRY(launch("topk_stage1", k_topk_stage1, dim3((unsigned)blocks), dim3(256), 0, s, bins, count, per_block,
+                 partial, after_v, after_i));
+  static_assert(1024 * kTopT <= 8 * 1024, "stage 2 holds eight candidates per thread");
+  return launch("topk_stage2", k_topk_stage2, dim3(1), dim3(1024), 0, s, static_cast<const Cand *>(partial),
+                blocks * kTopT, t, out);
 }
 
 }  // namespace cqc

@@ -177,3 +177,40 @@ def test_chi2_validation():
     assert L.cqc_chi2(None, 0, 0x2000, 0, 10, out, ws, 8192, None) == 1
     assert L.cqc_chi2(0x1000, 0, 0x2000, 0, 10, out, ws, 100, None) == 4
     assert L.cqc_chi2(0x1000, 0, 0x2000, 0, 10, out, None, 8192, None) == 4
+
+
+def _dd_ws(inst, strategy=0, per_round=1, a=3, R=4):
+    params = _lib.CqcDDParams(a, R, None, strategy, per_round)
+    nb = ctypes.c_size_t(0)
+    rc = _lib.lib().cqc_dd_workspace_size(ctypes.byref(inst), 0, 1, ctypes.byref(params), ctypes.byref(nb))
+    return rc, nb.value
+
+
+def test_dd_strategy_and_round_validation():
+    """Strategies 0..2 and bins_per_round 0..64 are accepted (the workspace grows
+    with the per-round read-back slots); anything else is refused on the host."""
+    inst = _inst(10, [5, 5], [(0, 1), (0, 1)], list(range(10)))
+    for s in (0, 1, 2):
+        assert _dd_ws(inst, s)[0] == 0
+    assert _dd_ws(inst, 3)[0] == 1
+    assert _dd_ws(inst, -1)[0] == 1
+    assert _dd_ws(inst, 0, -1)[0] == 1
+    assert _dd_ws(inst, 0, 65)[0] == 1
+    rc0, nb0 = _dd_ws(inst, 0, 0)
+    rc1, nb1 = _dd_ws(inst, 0, 1)
+    rc64, nb64 = _dd_ws(inst, 2, 64)
+    assert rc0 == rc1 == rc64 == 0 and nb0 == nb1 and nb64 > nb1
+
+
+def test_dd_plan_cache_keys_on_every_input():
+    """Alternating queries that differ in one input each get their own plan."""
+    inst = _inst(12, [6, 6], [(0, 1), (0, 1)], list(range(12)))
+    inst_perm = _inst(12, [6, 6], [(0, 1), (0, 1)], list(range(11, -1, -1)))
+    ref = {key: _dd_ws(*args)[1] for key, args in
+           {"a3": (inst, 0, 1, 3), "a5": (inst, 0, 1, 5), "r16": (inst, 2, 16, 3), "perm": (inst_perm, 0, 1, 5)}.items()}
+    assert ref["a3"] != ref["a5"] and ref["r16"] > ref["a3"]
+    for _ in range(3):
+        assert _dd_ws(inst, 0, 1, 5)[1] == ref["a5"]
+        assert _dd_ws(inst, 0, 1, 3)[1] == ref["a3"]
+        assert _dd_ws(inst, 2, 16, 3)[1] == ref["r16"]
+        assert _dd_ws(inst_perm, 0, 1, 5)[1] == ref["perm"]

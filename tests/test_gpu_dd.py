@@ -152,3 +152,104 @@ def test_dd_bad_arguments():
     with pytest.raises(cqc.CqcError) as e:
         cqc.reconstruct_dd(dev, cut, 2, 2, first_active=[1, 1])
     assert e.value.code == 1
+
+
+# ---- search strategies and multi-bin rounds
+
+def _replay_picks(bins, recs, strategy, per_round):
+    """The parents the strategy's rule gives on the GPU's own bin masses, with
+    the round structure of the call (picks from the recursions that existed
+    when the round began)."""
+    fake = [dict(bins=bins[r, :2 ** g["n_active"]], has_merged=any(v == -1 for v in g["role"]),
+                 depth=g["depth"], round=0) for r, g in enumerate(recs)]
+    choose = dd.CHOOSERS[strategy]
+    expanded, parents = set(), [(-1, -1)]
+    made, start, left, restrict, rnd = 1, 1, 0, None, 0
+    while made < len(recs):
+        if left == 0:
+            start, left, restrict, rnd = made, per_round, None, rnd + 1
+        pick = choose(fake[:start], expanded, restrict)
+        if pick is None and made > start:
+            start, left, restrict, rnd = made, per_round, None, rnd + 1
+            pick = choose(fake[:start], expanded, None)
+        fake[made]["round"] = rnd
+        assert pick is not None
+        left -= 1
+        if restrict is None and strategy != "heaviest":
+            restrict = ("depth", fake[pick[0]]["depth"]) if strategy == "bfs" else ("rec", pick[0])
+        expanded.add(pick)
+        parents.append(pick)
+        made += 1
+    return parents
+
+
+@pytest.mark.parametrize("strategy", ["heaviest", "dfs", "bfs"])
+@pytest.mark.parametrize("per_round", [1, 4])
+@pytest.mark.parametrize("prec,dtype,tol", [("fp64", torch.float64, 1e-12), ("fp32", torch.float32, 1e-6)])
+def test_dd_strategies_match_oracle(strategy, per_round, prec, dtype, tol):
+    _gpu()
+    inst = W.make_instance((3, 2, 3), (2, 2), 6, seed=31)        # n = 12, a = 3: depth 3 has no merged qubit
+    a, R = 3, 13
+    host, dev = to_dev(inst.entries, dtype)
+    cut = cqc.CutMap.from_workload(inst.cut)
+    bins, recs = cqc.reconstruct_dd(dev, cut, a, R, precision=prec, strategy=strategy, bins_per_round=per_round)
+    bins = bins.cpu().numpy()
+    assert len(recs) == R
+    assert [tuple(r["parent"]) for r in recs] == _replay_picks(bins, recs, strategy, per_round)
+    e64 = oracle_inputs(host)
+    ref = dd.reconstruct(e64, inst.cut, a, R, chooser=_follow(recs))
+    for r, (g, o) in enumerate(zip(recs, ref)):
+        assert g["role"] == o["role"] and g["depth"] == o["depth"], r
+        nb = 2 ** g["n_active"]
+        assert metrics.rel_l1(bins[r, :nb], o["bins"]) <= tol, r
+        assert abs(g["mass"] - o["bins"].sum()) <= tol * np.abs(o["bins"]).sum() + 1e-15
+    if prec == "fp64":     # no near-ties at this seed: the oracle's own choices agree
+        free = dd.reconstruct(e64, inst.cut, a, R, strategy=strategy, per_round=per_round)
+        assert [tuple(r["parent"]) for r in recs] == [r["parent"] for r in free]
+
+
+def test_dd_bfs_rounds_do_not_change_records():
+    """BFS: every depth's recursions exist before its first bin is expanded, so
+    one bin per round and five per round give bitwise the same bins."""
+    _gpu()
+    inst = W.make_instance((4, 4), (2,), 4, seed=32)
+    host, dev = to_dev(inst.entries, torch.float32)
+    cut = cqc.CutMap.from_workload(inst.cut)
+    b1, r1 = cqc.reconstruct_dd(dev, cut, 3, 20, strategy="bfs", bins_per_round=1)
+    b5, r5 = cqc.reconstruct_dd(dev, cut, 3, 20, strategy="bfs", bins_per_round=5)
+    assert [r["parent"] for r in r1] == [r["parent"] for r in r5]
+    assert torch.equal(b1, b5)
+    assert [r["depth"] for r in r1[:9]] == [0] + [1] * 8          # all of recursion 1's bins first
+
+
+def test_dd_dfs_locates_deterministic_state():
+    """One active qubit, two bins per round: every round expands both bins of
+    the heaviest newest recursion, so the state is pinned one qubit per round."""
+    _gpu()
+    target = [0, 1, 1, 0, 1, 0, 1]
+    circ = W.bridged_chain((3, 2), (2,), 4, seed=0, x_gates=tuple((0, q) for q, b in enumerate(target) if b))
+    circ.angles[:] = 0.0
+    cut = circ.cut_map()
+    n = cut.n
+    host, dev = to_dev(W.circuit_entries(circ), torch.float32)
+    bins, recs = cqc.reconstruct_dd(dev, cqc.CutMap.from_workload(cut), 1, 1 + 2 * (n - 1), strategy="dfs",
+                                    bins_per_round=2)
+    bins = bins.cpu().numpy()
+    heavy = [g for g in recs if g["mass"] > 0.5]
+    assert len(heavy) == n
+    last = max(heavy, key=lambda g: g["depth"])
+    assert last["depth"] == n - 1
+    assert [last["role"][q] for q in range(n - 1)] == target[:n - 1]
+    assert int(np.argmax(bins[recs.index(last), :2])) == target[n - 1]
+
+
+def test_dd_strategy_arguments():
+    _gpu()
+    inst = W.make_instance((3, 3), (1,), 4, seed=1)
+    host, dev = to_dev(inst.entries, torch.float32)
+    cut = cqc.CutMap.from_workload(inst.cut)
+    with pytest.raises(ValueError):
+        cqc.reconstruct_dd(dev, cut, 2, 2, strategy="random")
+    with pytest.raises(cqc.CqcError) as e:
+        cqc.reconstruct_dd(dev, cut, 2, 2, bins_per_round=65)
+    assert e.value.code == 1

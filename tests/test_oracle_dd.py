@@ -147,15 +147,16 @@ def test_dfs_is_preorder_walk():
 
 def test_dfs_multi_bin_round():
     """per_round = 3: the first round expands the three heaviest first-recursion
-    bins; the next round starts from the newest of them, depth first."""
+    bins; the next round goes down under the heaviest of them, taking its
+    children heaviest first."""
     inst = W.make_instance((3, 2), (2,), 6, seed=22)
     p = sv.uncut_distribution(inst.circuit)
     recs = dd.reconstruct(inst.entries, inst.cut, 2, 6, strategy="dfs", per_round=3)
     top = sorted(range(4), key=lambda b: (-_prefix_masses(p, inst.n, 2)[b], b))
     assert [r["parent"] for r in recs[1:4]] == [(0, b) for b in top[:3]]
-    m4 = _prefix_masses(p, inst.n, 4).reshape(4, 4)[top[2]]
-    assert recs[4]["parent"] == (3, int(sorted(range(4), key=lambda b: (-m4[b], b))[0]))
-    assert recs[5]["parent"][0] == 3
+    m4 = _prefix_masses(p, inst.n, 4).reshape(4, 4)[top[0]]
+    kids = sorted(range(4), key=lambda b: (-m4[b], b))
+    assert [r["parent"] for r in recs[4:6]] == [(1, kids[0]), (1, kids[1])]
 
 
 @pytest.mark.parametrize("per_round", [1, 3, 7])
