@@ -11,7 +11,7 @@ the writes.
 
 Prints ONE JSON line.  `--config` selects another workload of the same family
 (its own line, same fields):
-  c3  FD fused chain, n=30, K=6, three 12-qubit subcircuits (FP32, BF16X6, FP64)
+  c3  FD fused chain, n=30, K=6, three 12-qubit subcircuits (FP32, BF16X6, BF16X3, FP64)
   c4  DD, n=40, K=8, 2^20 bins per recursion, 5 recursions (FP32, FP64 bins)
   c5  256 instances (n 12..24, K 1..4) forward + cross-entropy adjoint, one
       graph-captured step
@@ -183,6 +183,9 @@ def bench_fd(args, cfg, torch, cqc, W):
 
     r32, s32 = measure("fp32", e32, torch.float32)
     rbf, sbf = measure("bf16x6", e32, torch.float32)
+    # the two-part split (accuracy/speed study): only where steps have more
+    # than 16 terms does it differ from FP32
+    r3, s3 = measure("bf16x3", e32, torch.float32) if cfg != "c2" else (None, None)
     r64, s64 = measure("fp64", e64, torch.float64)
 
     def dominant(kt, prefix=None):
@@ -208,6 +211,8 @@ def bench_fd(args, cfg, torch, cqc, W):
         roof["plan_flops_per_step"] = 2.0 * macs
         name_b, avg_b = dominant(rbf["kernels_ms"], "wide_bf16x6_final")
         roof_bf = _roof("hbm", (4 * N) / (avg_b * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", name_b, avg_b, None)
+        name_3, avg_3 = dominant(r3["kernels_ms"], "wide_bf16x3_final")
+        roof_3 = _roof("hbm", (4 * N) / (avg_3 * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", name_3, avg_3, None)
 
     metric = METRIC if cfg == "c2" else "FD reconstructed probs/s n=30,K=6 fused chain: MFMA-FP32 at 1e-6 rel err"
     out = _line(cfg, metric, r32["value"], "probs/s", steps, warmup, r32["ms_per_step"], "f32",
@@ -218,6 +223,9 @@ def bench_fd(args, cfg, torch, cqc, W):
                 bf16x6={**{k: rbf[k] for k in ("value", "ms_per_step", "kernels_ms", "mass")}, "roofline": roof_bf})
     out["speedup_fp32_vs_fp64"] = r32["value"] / r64["value"]
     out["speedup_bf16x6_vs_fp64"] = rbf["value"] / r64["value"]
+    if r3 is not None:
+        out["bf16x3"] = {**{k: r3[k] for k in ("value", "ms_per_step", "kernels_ms", "mass")}, "roofline": roof_3}
+        out["speedup_bf16x3_vs_fp64"] = r3["value"] / r64["value"]
 
     if not args.no_cpu:
         from oracle import native, metrics  # CPU-baseline leg only
@@ -243,6 +251,8 @@ def bench_fd(args, cfg, torch, cqc, W):
             ref = native.reconstruct(e64_np, inst.cut, xs)
             out["err_rel_l1_fp32_sampled"] = metrics.rel_l1(g32, ref)
             out["err_rel_l1_bf16x6_sampled"] = metrics.rel_l1(sbf[1], ref)
+            if s3 is not None:
+                out["err_rel_l1_bf16x3_sampled"] = metrics.rel_l1(s3[1], ref)
             out["fp64_plain"]["err_rel_l1_sampled"] = metrics.rel_l1(
                 s64[1], native.reconstruct(inst.entries, inst.cut, xs))
             rng = np.random.default_rng(11)

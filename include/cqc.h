@@ -62,8 +62,14 @@ typedef enum { CQC_F32 = 0, CQC_F64 = 1 } cqc_dtype;
  *           and DD bin masses are summed in FP64.
  *   BF16X6: each float operand split into three bfloat16 parts (a = a0+a1+a2),
  *           the six products a_i b_j with i+j <= 2 on BF16 MFMA with FP32
- *           accumulation (Henry, Tang, Heinecke, ARITH 2019).            */
-typedef enum { CQC_PREC_FP64 = 0, CQC_PREC_FP32 = 1, CQC_PREC_BF16X6 = 2 } cqc_precision;
+ *           accumulation (Henry, Tang, Heinecke, ARITH 2019).
+ *   BF16X3: the speed end of the same split: two bfloat16 parts
+ *           (a = a0+a1) and the three products a_i b_j with i+j <= 1; the
+ *           dropped part and product leave up to about 3 * 2^-18 of |a b| per
+ *           product (about 1e-5 relative, above the FP32 forms' error).
+ * Steps with at most 16 terms (<= 2 shared cuts) or a one-column operand
+ * run the FP32 form under both split precisions.                        */
+typedef enum { CQC_PREC_FP64 = 0, CQC_PREC_FP32 = 1, CQC_PREC_BF16X6 = 2, CQC_PREC_BF16X3 = 3 } cqc_precision;
 
 /* Limits of this implementation. */
 #define CQC_MAX_SUB 16        /* subcircuits per instance                      */
@@ -148,7 +154,7 @@ int cqc_batch_destroy(cqc_batch batch);
  * synchronisation, no allocation), so it may be captured into a HIP graph
  * together with cqc_batch_run.  Results are bitwise reproducible (split-K
  * partials are added in a fixed order).  An FP64 batch runs the FP64 adjoint;
- * FP32 and BF16X6 batches run the FP32 one.
+ * FP32 and split-BF16 batches run the FP32 one.
  * cqc_batch_backward_destroy frees the host-side handle only. */
 typedef struct cqc_batch_bwd_s *cqc_batch_bwd;
 int cqc_batch_backward_workspace_size(cqc_batch batch, size_t *bytes);

@@ -407,7 +407,8 @@ class BackwardCall:
 
 class ReconstructFD(torch.autograd.Function):
     """p = FD(entries); backward runs the library's adjoint kernels.  The
-    adjoint has no BF16X6 form: a BF16X6 forward is differentiated in FP32."""
+    adjoint has no split-BF16 form: a BF16X6 or BF16X3 forward is differentiated
+    in FP32."""
 
     @staticmethod
     def forward(ctx, cut, precision, *entries):
@@ -420,7 +421,7 @@ class ReconstructFD(torch.autograd.Function):
     def backward(ctx, grad_p):
         entries = ctx.saved_tensors
         g = grad_p.contiguous().to(entries[0].dtype)
-        prec = "fp32" if ctx.precision == "bf16x6" else ctx.precision
+        prec = "fp32" if ctx.precision in ("bf16x6", "bf16x3") else ctx.precision
         grads = reconstruct_backward(list(entries), ctx.cut, g, prec)
         return (None, None) + tuple(grads)
 

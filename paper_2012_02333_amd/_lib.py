@@ -11,7 +11,7 @@ CQC_OK = 0
 STATUS = {0: "CQC_OK", 1: "CQC_ERR_INVALID_ARG", 2: "CQC_ERR_SHAPE", 3: "CQC_ERR_UNSUPPORTED",
           4: "CQC_ERR_WORKSPACE", 5: "CQC_ERR_HIP"}
 F32, F64 = 0, 1
-PREC = {"fp64": 0, "fp32": 1, "bf16x6": 2}
+PREC = {"fp64": 0, "fp32": 1, "bf16x6": 2, "bf16x3": 3}
 MAX_DD_QUBITS = 128
 
 EXPORTS = [

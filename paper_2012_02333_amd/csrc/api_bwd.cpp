@@ -121,7 +121,8 @@ static Status bwd_plans(const cqc_instance *inst, int32_t n_inst, cqc_dtype in_t
   switch (prec) {
     case CQC_PREC_FP64: *acc = Acc::F64; break;
     case CQC_PREC_FP32: *acc = Acc::F32; break;
-    case CQC_PREC_BF16X6: return Status::fail(CQC_ERR_UNSUPPORTED, "BF16X6 is not available for the adjoint");
+    case CQC_PREC_BF16X6:
+    case CQC_PREC_BF16X3: return Status::fail(CQC_ERR_UNSUPPORTED, "the split-BF16 forms are not available for the adjoint");
     default: return Status::fail(CQC_ERR_INVALID_ARG, "unknown precision");
   }
   if (need_ptrs && (!gout || !gents)) return Status::fail(CQC_ERR_INVALID_ARG, "gradient arrays are NULL");

@@ -69,6 +69,7 @@ static Status build_dd(const cqc_instance *inst, cqc_dtype in_t, cqc_precision p
     case CQC_PREC_FP64: d.acc = Acc::F64; break;
     case CQC_PREC_FP32: d.acc = Acc::F32; break;
     case CQC_PREC_BF16X6: d.acc = Acc::BF16X6; break;
+    case CQC_PREC_BF16X3: d.acc = Acc::BF16X3; break;
     default: return Status::fail(CQC_ERR_INVALID_ARG, "unknown precision");
   }
   CQC_TRY(validate_cut(&inst->cut, CQC_MAX_DD_QUBITS, &d.cut));

@@ -12,6 +12,7 @@ Status precision_acc(cqc_precision prec, Acc *acc) {
     case CQC_PREC_FP64: *acc = Acc::F64; return Status::ok();
     case CQC_PREC_FP32: *acc = Acc::F32; return Status::ok();
     case CQC_PREC_BF16X6: *acc = Acc::BF16X6; return Status::ok();
+    case CQC_PREC_BF16X3: *acc = Acc::BF16X3; return Status::ok();
     default: return Status::fail(CQC_ERR_INVALID_ARG, "unknown precision");
   }
 }

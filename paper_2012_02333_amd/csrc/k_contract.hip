@@ -705,14 +705,14 @@ TileShape tile_shape(int cfg) {
 
 bool tile_ok(Acc acc, int cfg) {
   if (cfg < 0 || cfg >= kTileCount) return false;
-  if (acc == Acc::BF16X6) return cfg == kTileW;
+  if (is_split(acc)) return cfg == kTileW;
   if (acc == Acc::F64) return cfg != kTileW;
   return true;
 }
 
 int choose_tile(Acc acc, int nS, int logM, int logN, bool wide_ok, int64_t nbatch) {
   const int64_t M = int64_t(1) << logM, N = int64_t(1) << logN;
-  if (acc == Acc::BF16X6) return kTileW;
+  if (is_split(acc)) return kTileW;
   // long term sums over large tiles are compute-bound: LDS-staged operands, on
   // steps with at least 256 tiles of 128 x 128 (fewer leave most of the chip
   // idle on the persistent kernel: the 64 x 256 register kernel then wins, e.g.
@@ -778,7 +778,7 @@ static Status launch_queue_m(int cfg, bool small, const QueueLaunch &q, hipStrea
 
 Status launch_contract_queue(Acc acc, int mode, int cfg, bool small, const QueueLaunch &q, hipStream_t s) {
   if (!tile_ok(acc, cfg)) return Status::fail(CQC_ERR_INVALID_ARG, "tile configuration not available for this arithmetic");
-  if (cfg == kTileW) return launch_contract_wide_queue(acc == Acc::BF16X6, mode, q, s);
+  if (cfg == kTileW) return launch_contract_wide_queue(split_parts(acc), mode, q, s);
   if (acc == Acc::F32) {
     if (mode == kModeIntermediate) return launch_queue_m<float, kModeIntermediate>(cfg, small, q, s);
     if (mode == kModeFinalBlocked) return launch_queue_m<float, kModeFinalBlocked>(cfg, small, q, s);
@@ -798,7 +798,7 @@ static Status launch_contract_t(int cfg, const ContractArgs &a, hipStream_t s) {
 
 Status launch_contract(Acc acc, bool out_double, int cfg, const ContractArgs &a, hipStream_t s) {
   if (!tile_ok(acc, cfg)) return Status::fail(CQC_ERR_INVALID_ARG, "tile configuration not available for this arithmetic");
-  if (cfg == kTileW) return launch_contract_wide(acc == Acc::BF16X6, out_double, a, s);
+  if (cfg == kTileW) return launch_contract_wide(split_parts(acc), out_double, a, s);
   if (acc == Acc::F32)
     return out_double ? launch_contract_t<float, double>(cfg, a, s)
                       : launch_contract_t<float, float>(cfg, a, s);

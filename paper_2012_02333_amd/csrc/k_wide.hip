@@ -12,6 +12,10 @@
 //           products are below 2^-24 of |a b|, so the result keeps FP32
 //           accuracy at the bfloat16 matrix-core rate (6 products at 16x the
 //           FP32 rate: 2.7x the FP32 form's arithmetic throughput).
+//   BF16X3  two parts a = a0 + a1 (16 significand bits) and the three products
+//           a_i b_j with i + j <= 1, smallest first: half the BF16X6 matrix-core
+//           work, with the dropped part and product up to about 3 * 2^-18 of
+//           |a b| per product - the speed end of the same split.
 //
 // A label-list pass first compacts, for every batch entry of the step, the
 // live terms (both operand rows non-zero: early termination, Section 4.2) in
@@ -48,7 +52,7 @@ constexpr int kB16Ld = 40;      // bfloat16 per LDS operand column and part (BF1
 constexpr int kStLd = kWT + 4;  // floats per row of an epilogue staging slice
 }  // namespace
 
-// a = h + m + l with each part the round-to-nearest bfloat16 of what is left.
+// a = h + m (+ l) with each part the round-to-nearest bfloat16 of what is left.
 __device__ __forceinline__ void split3(float a, __bf16 *h, __bf16 *m, __bf16 *l) {
   const __bf16 p0 = (__bf16)a;
   const float r1 = a - (float)p0;
@@ -238,10 +242,12 @@ struct QueueSeq {
   __device__ const ContractArgs &args(const WideTile &t) const { return descs[t.d]; }
 };
 
-template <bool SPLIT, typename O, int MODE, class Seq>
+// NP: bfloat16 parts per operand (3: BF16X6, 2: BF16X3), 0 for the FP32 form.
+template <int NP, typename O, int MODE, class Seq>
 __device__ __forceinline__ void wide_run(Seq &seq) {
-  // operand staging area: FP32 [256 columns][kF32Ld]; BF16X6 [3 parts][256][kB16Ld]
-  constexpr int kOpBytes = SPLIT ? 3 * 2 * kWB * kB16Ld * 2 : 2 * kWB * kF32Ld * 4;
+  static_assert(NP == 0 || NP == 2 || NP == 3, "FP32, BF16X3 or BF16X6");
+  // operand staging area: FP32 [256 columns][kF32Ld]; split forms [NP parts][256][kB16Ld]
+  constexpr int kOpBytes = NP ? NP * 2 * kWB * kB16Ld * 2 : 2 * kWB * kF32Ld * 4;
   static_assert(kOpBytes >= 4 * 16 * kStLd * 4, "epilogue staging fits in the operand area");
   __shared__ __attribute__((aligned(16))) unsigned char smem[kOpBytes];
   __shared__ double red[4];
@@ -301,7 +307,7 @@ __device__ __forceinline__ void wide_run(Seq &seq) {
     constexpr int b = decltype(B)::value;
     auto val = [&](int k, int j) { return (colok[b][j] && ((okrow[b] >> k) & 1u)) ? pre[b][k][j] : 0.0f; };
     const int col0 = (roleX ? 0 : kWB) + 2 * lane;   // first of this lane's two LDS operand columns
-    if constexpr (!SPLIT) {
+    if constexpr (NP == 0) {
       // term k of a 16-term group g sits at 16 g + 4 (k % 4) + (k % 16) / 4, so
       // lane group lg reads terms {lg, lg+4, lg+8, lg+12} of the group at once;
       // this wave's half is group `half`
@@ -330,14 +336,14 @@ __device__ __forceinline__ void wide_run(Seq &seq) {
           const int pos = 16 * half + 8 * o;
           *reinterpret_cast<bf16x8 *>(bp + (0 * 2 * kWB + col0 + j) * kB16Ld + pos) = h;
           *reinterpret_cast<bf16x8 *>(bp + (1 * 2 * kWB + col0 + j) * kB16Ld + pos) = m;
-          *reinterpret_cast<bf16x8 *>(bp + (2 * 2 * kWB + col0 + j) * kB16Ld + pos) = l;
+          if constexpr (NP == 3) *reinterpret_cast<bf16x8 *>(bp + (2 * 2 * kWB + col0 + j) * kB16Ld + pos) = l;
         }
     }
   };
   // MFMA mapping: A operand = Y (MFMA row <-> n), B operand = X (MFMA column
   // <-> m), so lane (l16, lg) accumulates 4 consecutive n of output row l16.
   auto compute = [&]() {
-    if constexpr (!SPLIT) {
+    if constexpr (NP == 0) {
       const float *px = reinterpret_cast<const float *>(smem) + (wm * kWT + l16) * kF32Ld + 4 * lg;
       const float *py = reinterpret_cast<const float *>(smem) + (kWB + wn * kWT + l16) * kF32Ld + 4 * lg;
 #pragma unroll
@@ -363,26 +369,28 @@ __device__ __forceinline__ void wide_run(Seq &seq) {
       }
     } else {
       const __bf16 *bp = reinterpret_cast<const __bf16 *>(smem);
-      bf16x8 xv[4][3];
+      bf16x8 xv[4][NP];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int p = 0; p < 3; ++p)
+        for (int p = 0; p < NP; ++p)
           xv[i][p] = *reinterpret_cast<const bf16x8 *>(bp + (p * 2 * kWB + wm * kWT + i * 16 + l16) * kB16Ld + 8 * lg);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        bf16x8 yv[3];
+        bf16x8 yv[NP];
 #pragma unroll
-        for (int p = 0; p < 3; ++p)
+        for (int p = 0; p < NP; ++p)
           yv[p] = *reinterpret_cast<const bf16x8 *>(bp + (p * 2 * kWB + kWB + wn * kWT + j * 16 + l16) * kB16Ld +
                                                     8 * lg);
-        // (part of Y, part of X) for the six products, smallest first
+        // (part of Y, part of X) for the six (three) products, smallest first
+        if constexpr (NP == 3) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yv[0], xv[i][2], acc[i][j], 0, 0, 0);
+          for (int i = 0; i < 4; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yv[0], xv[i][NP - 1], acc[i][j], 0, 0, 0);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yv[2], xv[i][0], acc[i][j], 0, 0, 0);
+          for (int i = 0; i < 4; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yv[NP - 1], xv[i][0], acc[i][j], 0, 0, 0);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yv[1], xv[i][1], acc[i][j], 0, 0, 0);
+          for (int i = 0; i < 4; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yv[1], xv[i][1], acc[i][j], 0, 0, 0);
+        }
 #pragma unroll
         for (int i = 0; i < 4; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yv[0], xv[i][1], acc[i][j], 0, 0, 0);
 #pragma unroll
@@ -542,23 +550,23 @@ __device__ __forceinline__ void wide_run(Seq &seq) {
 
 // Occupancy target: two blocks per CU (8 waves).  Three FP32 blocks would fit
 // the LDS but not the registers without spilling, and measure slower.
-template <bool SPLIT> struct WideOcc { static constexpr int kWaves = 2; };
+template <int NP> struct WideOcc { static constexpr int kWaves = 2; };
 
-template <bool SPLIT, typename O, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WideOcc<SPLIT>::kWaves, WideOcc<SPLIT>::kWaves)))
+template <int NP, typename O, int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WideOcc<NP>::kWaves, WideOcc<NP>::kWaves)))
 void k_wide(const ContractArgs a) {
   StridedSeq seq(a);
-  wide_run<SPLIT, O, MODE>(seq);
+  wide_run<NP, O, MODE>(seq);
 }
 
-template <bool SPLIT, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WideOcc<SPLIT>::kWaves, WideOcc<SPLIT>::kWaves)))
+template <int NP, int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WideOcc<NP>::kWaves, WideOcc<NP>::kWaves)))
 void k_wide_queue(const ContractArgs *__restrict__ descs,
                                                     const int64_t *__restrict__ prefix, int ndesc,
                                                     unsigned long long *queue, int64_t total) {
   __shared__ int64_t slot[2];
   QueueSeq seq{descs, prefix, ndesc, queue, total, slot};
-  wide_run<SPLIT, float, MODE>(seq);
+  wide_run<NP, float, MODE>(seq);
 }
 // ---------------------------------------------------------------------------
 bool wide_fits(const ContractArgs &a) {
@@ -593,41 +601,64 @@ static Status launch_persistent(const char *nm, K kernel, const ContractArgs &a,
   return launch(nm, kernel, dim3((unsigned)G), dim3(256), 0, s, a);
 }
 
-template <bool SPLIT, typename O>
+template <int NP> struct WideNames;
+template <> struct WideNames<0> {
+  static constexpr const char *fin = "wide_f32_final", *mid = "wide_f32_inter", *queue = "wide_f32_queue";
+};
+template <> struct WideNames<2> {
+  static constexpr const char *fin = "wide_bf16x3_final", *mid = "wide_bf16x3_inter", *queue = "wide_bf16x3_queue";
+};
+template <> struct WideNames<3> {
+  static constexpr const char *fin = "wide_bf16x6_final", *mid = "wide_bf16x6_inter", *queue = "wide_bf16x6_queue";
+};
+
+template <int NP, typename O>
 static Status launch_wide_t(const ContractArgs &a, hipStream_t s) {
-  const char *fin = SPLIT ? "wide_bf16x6_final" : "wide_f32_final";
-  const char *mid = SPLIT ? "wide_bf16x6_inter" : "wide_f32_inter";
   CQC_TRY(launch("label_list", k_label_list, dim3((unsigned)a.nbatch), dim3(256), 0, s, a));
-  if (a.mode == kModeFinalBlocked) return launch_persistent(fin, k_wide<SPLIT, O, kModeFinalBlocked>, a, s);
-  if (a.mode == kModeFinalDeposit) return launch_persistent(fin, k_wide<SPLIT, O, kModeFinalDeposit>, a, s);
-  return launch_persistent(mid, k_wide<SPLIT, float, kModeIntermediate>, a, s);
+  if (a.mode == kModeFinalBlocked) return launch_persistent(WideNames<NP>::fin, k_wide<NP, O, kModeFinalBlocked>, a, s);
+  if (a.mode == kModeFinalDeposit) return launch_persistent(WideNames<NP>::fin, k_wide<NP, O, kModeFinalDeposit>, a, s);
+  return launch_persistent(WideNames<NP>::mid, k_wide<NP, float, kModeIntermediate>, a, s);
 }
 
-Status launch_contract_wide(bool split, bool out_double, const ContractArgs &a, hipStream_t s) {
+template <int NP>
+static Status launch_wide_np(bool out_double, const ContractArgs &a, hipStream_t s) {
+  return out_double ? launch_wide_t<NP, double>(a, s) : launch_wide_t<NP, float>(a, s);
+}
+
+Status launch_contract_wide(int parts, bool out_double, const ContractArgs &a, hipStream_t s) {
   if (!a.lists || !a.counts || a.nbatch < 1 || a.list_ld < wide_list_ld(a.nS))
     return Status::fail(CQC_ERR_INVALID_ARG, "wide contraction without label-list workspace");
   if (!wide_fits(a))
     return Status::fail(CQC_ERR_UNSUPPORTED, "wide contraction: an operand has one column or exceeds 2^30 elements");
-  if (split) return out_double ? launch_wide_t<true, double>(a, s) : launch_wide_t<true, float>(a, s);
-  return out_double ? launch_wide_t<false, double>(a, s) : launch_wide_t<false, float>(a, s);
+  switch (parts) {
+    case 0: return launch_wide_np<0>(out_double, a, s);
+    case 2: return launch_wide_np<2>(out_double, a, s);
+    case 3: return launch_wide_np<3>(out_double, a, s);
+    default: return Status::fail(CQC_ERR_INVALID_ARG, "wide contraction: unknown operand split");
+  }
 }
 
-template <bool SPLIT>
+template <int NP>
 static Status launch_wide_queue_t(int mode, const QueueLaunch &q, hipStream_t s) {
   const dim3 grid(q.grid), block(256);
-  const char *nm = SPLIT ? "wide_bf16x6_queue" : "wide_f32_queue";
+  const char *nm = WideNames<NP>::queue;
   CQC_TRY(launch("label_list_table", k_label_list_table, dim3((unsigned)q.btotal), block, 0, s, q.descs, q.bprefix,
                  q.ndesc));
   if (mode == kModeFinalBlocked)
-    return launch(nm, k_wide_queue<SPLIT, kModeFinalBlocked>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
+    return launch(nm, k_wide_queue<NP, kModeFinalBlocked>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
   if (mode == kModeFinalDeposit)
-    return launch(nm, k_wide_queue<SPLIT, kModeFinalDeposit>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
-  return launch(nm, k_wide_queue<SPLIT, kModeIntermediate>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
+    return launch(nm, k_wide_queue<NP, kModeFinalDeposit>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
+  return launch(nm, k_wide_queue<NP, kModeIntermediate>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
 }
 
-Status launch_contract_wide_queue(bool split, int mode, const QueueLaunch &q, hipStream_t s) {
+Status launch_contract_wide_queue(int parts, int mode, const QueueLaunch &q, hipStream_t s) {
   if (!q.bprefix || q.btotal < 1) return Status::fail(CQC_ERR_INVALID_ARG, "wide queue without label-list table");
-  return split ? launch_wide_queue_t<true>(mode, q, s) : launch_wide_queue_t<false>(mode, q, s);
+  switch (parts) {
+    case 0: return launch_wide_queue_t<0>(mode, q, s);
+    case 2: return launch_wide_queue_t<2>(mode, q, s);
+    case 3: return launch_wide_queue_t<3>(mode, q, s);
+    default: return Status::fail(CQC_ERR_INVALID_ARG, "wide queue: unknown operand split");
+  }
 }
 
 }  // namespace cqc

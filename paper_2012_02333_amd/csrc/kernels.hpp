@@ -90,13 +90,16 @@ struct FlagArgs {
   int32_t is_double;
 };
 
-// Arithmetic of a plan.  BF16X6 keeps every tensor in FP32 and splits the
-// operands into three bfloat16 parts inside the wide kernel.
-enum class Acc { F32, F64, BF16X6 };
+// Arithmetic of a plan.  BF16X6 and BF16X3 keep every tensor in FP32 and
+// split the operands into three (two) bfloat16 parts inside the wide kernel.
+enum class Acc { F32, F64, BF16X6, BF16X3 };
+inline bool is_split(Acc a) { return a == Acc::BF16X6 || a == Acc::BF16X3; }
+// bfloat16 parts per operand of the wide kernel's form (0: FP32)
+inline int split_parts(Acc a) { return a == Acc::BF16X6 ? 3 : a == Acc::BF16X3 ? 2 : 0; }
 
 // Tile configurations of the contraction kernels: L, M, S, T select the
 // register-operand kernel (FP32 and FP64), W the LDS-staged wide kernel
-// (FP32 and BF16X6; the only one BF16X6 runs on).
+// (FP32 and the split forms; the only one the split forms run on).
 enum TileCfg : int32_t { kTileL = 0, kTileM = 1, kTileS = 2, kTileT = 3, kTileW = 4, kTileCount = 5 };
 struct TileShape { int bm, bn; };
 TileShape tile_shape(int cfg);
@@ -107,13 +110,13 @@ TileShape tile_shape(int cfg);
 int choose_tile(Acc acc, int nS, int logM, int logN, bool wide_ok, int64_t nbatch);
 // Whether the arithmetic has a kernel with this tile configuration.
 bool tile_ok(Acc acc, int cfg);
-// Arithmetic a step of a plan runs in.  A BF16X6 step runs the FP32 form
+// Arithmetic a step of a plan runs in.  A split-form step runs the FP32 form
 // where the split has nothing to win: an operand the wide kernel cannot take
 // (one column: a matrix-vector product), or at most 16 terms (nS <= 2 shared
 // cuts; such a step is bound by its output writes, and FP32 products are at
-// least as accurate as the six BF16 ones).
+// least as accurate as the BF16 ones).
 inline Acc step_acc(Acc acc, bool wide_ok, int nS) {
-  return acc == Acc::BF16X6 && (!wide_ok || nS <= 2) ? Acc::F32 : acc;
+  return is_split(acc) && (!wide_ok || nS <= 2) ? Acc::F32 : acc;
 }
 
 Status launch_row_flags(const FlagArgs &a, int64_t total_blocks, hipStream_t s);
@@ -150,10 +153,10 @@ Status launch_row_flags_table(const FlagDesc *descs, int32_t n, int64_t total_bl
                               unsigned long long *counters, int32_t n_counters, hipStream_t s);
 Status launch_mass_table(const MassDesc *descs, int32_t n, hipStream_t s);
 Status launch_contract(Acc acc, bool out_double, int cfg, const ContractArgs &a, hipStream_t s);
-Status launch_contract_wide(bool split, bool out_double, const ContractArgs &a, hipStream_t s);
+Status launch_contract_wide(int parts, bool out_double, const ContractArgs &a, hipStream_t s);
 // Whether both operands of a step are within the wide kernel's 2^30-element addressing.
 bool wide_fits(const ContractArgs &a);
-Status launch_contract_wide_queue(bool split, int mode, const QueueLaunch &q, hipStream_t s);
+Status launch_contract_wide_queue(int parts, int mode, const QueueLaunch &q, hipStream_t s);
 Status launch_convert(const void *src, bool src_double, void *dst, bool dst_double,
                       int64_t count, hipStream_t s);
 Status launch_selftest_mfma(void *out, hipStream_t s);

@@ -36,5 +36,17 @@ def elementwise_ok(p, ref, T, unit, terms):
 def sum_terms(prec, t):
     """Roundings an output of t terms goes through: the BF16X6 form adds six
     partial products per term, and its three-part split drops products below
-    4 u |a b| per term (one more u-multiple of T_x)."""
-    return 6 * t + 1 if prec == "bf16x6" else t
+    4 u |a b| per term (one more u-multiple of T_x).  The BF16X3 form adds
+    three, and its two-part split (remainders below 2^-18 |a|) drops up to
+    3 * 2^-18 |a b| = 192 u |a b| per term: 48 more u-multiples of T_x under
+    the factor 4 of elementwise_ok."""
+    if prec == "bf16x6":
+        return 6 * t + 1
+    if prec == "bf16x3":
+        return 3 * t + 48
+    return t
+
+
+# relative L1 bound of each precision per unit of kappa (sum T_x / sum |p_x|):
+# FP32 rounding, or for BF16X3 the dropped part (3 * 2^-18 = 1.14e-5 of T_x)
+REL_L1 = {"fp32": 1e-6, "bf16x6": 1e-6, "bf16x3": 1.2e-5}
