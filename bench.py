@@ -41,6 +41,7 @@ WORKLOAD = {
     "c5": "256 FD instances n~U{12..24} K~U{1..4} 2-3 subcircuits: forward + cross-entropy adjoint",
     "entries": "entry construction from variant distributions: two 22-output-qubit subcircuits joined by 2 cuts",
     "chi2": "chi-square distance (Eq. 16) of two 2^28-outcome FP32 distributions",
+    "dd35": "DD n=100 K=8, five 20-qubit subcircuits, one recursion of 2^35 FP32 bins",
 }
 
 # kernel sources whose change invalidates a committed HBM-counter record
@@ -55,7 +56,7 @@ def _args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default per config)")
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5", "entries", "chi2"])
+    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5", "entries", "chi2", "dd35"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--calibrate", action="store_true",
@@ -387,6 +388,58 @@ def bench_entries(args, torch, cqc, W):
 
 
 # ---------------------------------------------------------------------------
+def bench_dd_scale(args, torch, cqc, W):
+    """dd35: one DD recursion of 2^35 FP32 bins (128 GiB) on a 100-qubit cut."""
+    wcut, ents = W.dd_scale_instance()
+    a = W.DD_SCALE["n_active"]
+    cut = cqc.CutMap.from_workload(wcut)
+    dev = [torch.from_numpy(E).cuda() for E in ents]
+    steps = args.steps or 5
+    warmup = args.warmup if args.warmup is not None else 1
+    holder = {}
+
+    def step(i):
+        holder.pop("r", None)          # one 128 GiB bins buffer at a time
+        holder["r"] = cqc.reconstruct_dd(dev, cut, a, 1, precision="fp32", bins_dtype=torch.float32)
+    ms = _sync_time(step, steps, warmup, torch)
+    kt = _traced(step, steps, cqc, torch)
+    bins, recs = holder["r"]
+    per_call = {k: (v[0] / steps, v[1] / steps) for k, v in kt.items()}
+    name, (cnt, tot) = max(per_call.items(), key=lambda kv: kv[1][1])
+    avg = tot / cnt
+    # the final contraction writes the 2^35 FP32 bins once and reads its two
+    # operands (16 x 2^20 and 16 x 2^15 FP32)
+    alg = 4 * 2 ** a + 4 * 16 * (2 ** 20 + 2 ** 15)
+    roof = _roof("hbm", alg / (avg * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", name, avg, None)
+    out = _line("dd35", "DD reconstructed bins/s, n=100 K=8, one recursion of 2^35 bins (FP32 term sum and bins)",
+                2 ** a / (ms * 1e-3), "bins/s", steps, warmup, ms, "f32",
+                {"n": wcut.n, "K": wcut.n_cuts, "n_active": a, "recursions": 1, "precision": "fp32",
+                 "bins": "fp32", "seed": W.DD_SCALE["seed"]},
+                roof, kernels_ms_per_call=per_call, mass=recs[0]["mass"])
+    if not args.no_cpu:
+        from oracle import dd  # CPU-baseline leg only
+        role = recs[0]["role"]
+        rng = np.random.default_rng(13)
+        probe = np.sort(rng.choice(2 ** a, 64, replace=False))
+        got = bins[0, torch.from_numpy(probe).cuda()].double().cpu().numpy()
+        del holder["r"], bins
+        torch.cuda.empty_cache()
+        e64_np = [E.astype(np.float64) for E in ents]
+        t0 = time.perf_counter()
+        merged = dd.merge_entries(e64_np, wcut, role)
+        t_merge = time.perf_counter() - t0
+        ref = dd.bins_from_merged(merged, wcut, role, probe)
+        out["err_rel_l1_sampled"] = float(np.abs(got - ref).sum() / np.abs(ref).sum())
+        rate, size, reps, el = _cpu_rate(
+            lambda m: dd.bins_from_merged(merged, wcut, role, np.sort(rng.choice(2 ** a, m, replace=False))),
+            2 ** a, args.cpu_seconds, 64)
+        out["cpu_baseline"] = {"value": rate, "unit": "bins/s", "cores": 1, "kind": "oracle",
+                               "sample": f"merge ({t_merge:.1f} s, not in the rate) then {size} seeded bins x "
+                                         f"{reps} repetitions ({el:.1f} s), numpy FP64 definition over 4^8 terms"}
+    return out
+
+
+# ---------------------------------------------------------------------------
 def bench_chi2(args, torch, cqc, W):
     """chi2: Eq. 16 over two 2^28-outcome FP32 distributions (2 GiB read)."""
     n = 1 << 28
@@ -539,6 +592,8 @@ def main():
         out = bench_entries(args, torch, cqc, W)
     elif args.config == "chi2":
         out = bench_chi2(args, torch, cqc, W)
+    elif args.config == "dd35":
+        out = bench_dd_scale(args, torch, cqc, W)
     else:
         out = bench_batch(args, torch, cqc, W)
     print(json.dumps(out), flush=True)

@@ -255,11 +255,14 @@ int cqc_chi2(const void *a, cqc_dtype a_t, const void *b, cqc_dtype b_t, int64_t
 typedef enum { CQC_DD_HEAVIEST = 0, CQC_DD_DFS = 1, CQC_DD_BFS = 2 } cqc_dd_strategy;
 
 typedef struct {
-  int32_t n_active;          /* a: active qubits per recursion, 1..30            */
+  int32_t n_active;          /* a: active qubits per recursion, 1..36            */
   int32_t n_recursions;      /* R >= 1                                            */
   const int32_t *first_active; /* HOST [n_active] or NULL                         */
   int32_t strategy;          /* cqc_dd_strategy                                   */
   int32_t bins_per_round;    /* 0..64; 0 means 1                                  */
+  int32_t bins_f32;          /* 0: FP64 bins; 1: FP32 bins (half the memory: one
+                                recursion of 2^35 bins is 128 GiB); masses, the
+                                selection and the merge stay FP64            */
 } cqc_dd_params;
 
 typedef struct {
@@ -272,11 +275,13 @@ typedef struct {
 
 int cqc_dd_workspace_size(const cqc_instance *inst, cqc_dtype in_t, cqc_precision prec,
                           const cqc_dd_params *p, size_t *bytes);
-/* bins: DEVICE [n_recursions][2^n_active] FP64 (rows past the last recursion
- * are not written); records: HOST [n_recursions]; n_done: HOST, recursions run.
- * inst->out and inst->mass are ignored. */
+/* bins: DEVICE [n_recursions][2^n_active], FP64 (or FP32 with bins_f32),
+ * rows past the last recursion are not written; records: HOST [n_recursions];
+ * n_done: HOST, recursions run.  inst->out and inst->mass are ignored.  With
+ * FP32 bins the candidates are ranked on the stored FP32 values (widened
+ * exactly) and each record's mass is the FP64 sum of its stored bins. */
 int cqc_reconstruct_dd(const cqc_instance *inst, cqc_dtype in_t, cqc_precision prec,
-                       const cqc_dd_params *p, double *bins, cqc_dd_record *records,
+                       const cqc_dd_params *p, void *bins, cqc_dd_record *records,
                        int32_t *n_done, void *workspace, size_t ws_bytes,
                        hipStream_t stream);
 

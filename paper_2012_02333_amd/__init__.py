@@ -295,13 +295,16 @@ DD_STRATEGIES = {"heaviest": 0, "dfs": 1, "bfs": 2}
 
 
 def reconstruct_dd(entries, cut, n_active, n_recursions, first_active=None, precision="fp32",
-                   strategy="heaviest", bins_per_round=1):
-    """Dynamic definition (Algorithm 1) -> (bins [R_done, 2^a] float64, records list).
+                   strategy="heaviest", bins_per_round=1, bins_dtype=torch.float64):
+    """Dynamic definition (Algorithm 1) -> (bins [R_done, 2^a], records list).
 
     strategy: "heaviest" (Algorithm 1), "dfs" or "bfs" (Section 4.3);
-    bins_per_round: bins expanded per host round trip."""
+    bins_per_round: bins expanded per host round trip; bins_dtype: float64, or
+    float32 for half the memory (masses and the selection stay FP64)."""
     if strategy not in DD_STRATEGIES:
         raise ValueError(f"unknown strategy {strategy!r}")
+    if bins_dtype not in (torch.float64, torch.float32):
+        raise ValueError("bins_dtype must be float64 or float32")
     in_dt = _check_entries(entries, cut)
     dev = entries[0].device
     ptrs = (ctypes.c_void_p * len(entries))(*[E.data_ptr() for E in entries])
@@ -309,14 +312,15 @@ def reconstruct_dd(entries, cut, n_active, n_recursions, first_active=None, prec
     fa = None
     if first_active is not None:
         fa = (ctypes.c_int32 * len(first_active))(*[int(q) for q in first_active])
-    params = _lib.CqcDDParams(int(n_active), int(n_recursions), fa, DD_STRATEGIES[strategy], int(bins_per_round))
+    params = _lib.CqcDDParams(int(n_active), int(n_recursions), fa, DD_STRATEGIES[strategy], int(bins_per_round),
+                              1 if bins_dtype == torch.float32 else 0)
     L = _lib.lib()
     nb = ctypes.c_size_t(0)
     _lib.check(L.cqc_dd_workspace_size(ctypes.byref(inst), _DT[in_dt], PREC[precision],
                                        ctypes.byref(params), ctypes.byref(nb)))
     ws = _workspace(int(nb.value), dev)
     a = min(int(n_active), cut.n)
-    bins = torch.empty((int(n_recursions), 2 ** a), dtype=torch.float64, device=dev)   # rows past n_done unused
+    bins = torch.empty((int(n_recursions), 2 ** a), dtype=bins_dtype, device=dev)   # rows past n_done unused
     recs = (_lib.CqcDDRecord * int(n_recursions))()
     done = ctypes.c_int32(0)
     _lib.check(L.cqc_reconstruct_dd(ctypes.byref(inst), _DT[in_dt], PREC[precision],

@@ -45,7 +45,7 @@ class CqcEntryJob(ctypes.Structure):
 class CqcDDParams(ctypes.Structure):
     _fields_ = [("n_active", ctypes.c_int32), ("n_recursions", ctypes.c_int32),
                 ("first_active", ctypes.POINTER(ctypes.c_int32)), ("strategy", ctypes.c_int32),
-                ("bins_per_round", ctypes.c_int32)]
+                ("bins_per_round", ctypes.c_int32), ("bins_f32", ctypes.c_int32)]
 
 
 class CqcDDRecord(ctypes.Structure):

@@ -40,6 +40,7 @@ struct DepthPlan {
   std::vector<std::vector<int>> mrg_local;   // per subcircuit: merged local bits j
   NetLayout net;
   std::vector<size_t> merged_off;
+  std::vector<size_t> part_off;              // chunk sums of long merges (SIZE_MAX: none)
   size_t end = 0;
 };
 
@@ -55,6 +56,7 @@ struct DdPlan {
   CutInfo cut;
   Acc acc;
   int a = 0, R = 0, strategy = 0, per_round = 1;
+  bool bins_f32 = false;
   std::vector<DepthPlan> depths;
   size_t topk_off = 0, out_off = 0, bytes = 0;
 };
@@ -80,7 +82,9 @@ static Status build_dd(const cqc_instance *inst, cqc_dtype in_t, cqc_precision p
     return Status::fail(CQC_ERR_INVALID_ARG, "bins_per_round must be in [0, 64]");
   d.strategy = p->strategy;
   d.per_round = std::max(1, (int)p->bins_per_round);
-  if (p->n_active < 1 || p->n_active > 30) return Status::fail(CQC_ERR_INVALID_ARG, "n_active must be in [1, 30]");
+  if (p->n_active < 1 || p->n_active > 36) return Status::fail(CQC_ERR_INVALID_ARG, "n_active must be in [1, 36]");
+  if (p->bins_f32 != 0 && p->bins_f32 != 1) return Status::fail(CQC_ERR_INVALID_ARG, "bins_f32 must be 0 or 1");
+  d.bins_f32 = p->bins_f32 == 1;
   if (p->n_recursions < 1) return Status::fail(CQC_ERR_INVALID_ARG, "n_recursions must be >= 1");
   if (n < 1) return Status::fail(CQC_ERR_SHAPE, "dynamic definition needs at least one qubit");
   d.a = std::min(p->n_active, n);
@@ -131,10 +135,18 @@ static Status build_dd(const cqc_instance *inst, cqc_dtype in_t, cqc_precision p
     Plan plan = make_plan(d.cut, cols, bitpos, ad);
     size_t off = 0;
     dp.merged_off.assign(d.cut.nsub, 0);
+    dp.part_off.assign(d.cut.nsub, SIZE_MAX);
     for (int c = 0; c < d.cut.nsub; ++c) {
+      const size_t nout = (size_t)plan.tensors[c].rows() * ((size_t)1 << dp.act_local[c].size());
       off = align_up(off, 256);
       dp.merged_off[c] = off;
-      off += esz * (size_t)plan.tensors[c].rows() * ((size_t)1 << dp.act_local[c].size());
+      off += esz * nout;
+      const int lc = merge_log_chunks((int)dp.mrg_local[c].size());
+      if (lc > 0) {
+        off = align_up(off, 256);
+        dp.part_off[c] = off;
+        off += sizeof(double) * (nout << lc);
+      }
     }
     dp.net = layout_net(plan, d.acc, off);
     // a recursion's steps are small (2^a bins at most): prefer more, smaller
@@ -190,9 +202,9 @@ static bool dd_key(const cqc_instance *inst, cqc_dtype in_t, cqc_precision prec,
   if (c.n_qubits < 0 || c.n_qubits > CQC_MAX_DD_QUBITS || c.n_sub < 0 || c.n_sub > CQC_MAX_SUB || c.n_cuts < 0 ||
       c.n_cuts > CQC_MAX_CUTS || !c.f || !c.out_qubit || (c.n_cuts > 0 && (!c.edge_up || !c.edge_down)))
     return false;
-  if (p->n_active < 1 || p->n_active > 30 || (p->first_active && p->n_active > c.n_qubits)) return false;
+  if (p->n_active < 1 || p->n_active > 36 || (p->first_active && p->n_active > c.n_qubits)) return false;
   key->assign({c.n_qubits, c.n_sub, c.n_cuts, (int64_t)in_t, (int64_t)prec, p->n_active, p->n_recursions,
-               p->strategy, p->bins_per_round, p->first_active ? 1 : 0});
+               p->strategy, p->bins_per_round, p->bins_f32, p->first_active ? 1 : 0});
   for (int i = 0; i < c.n_sub; ++i) key->push_back(c.f[i]);
   for (int e = 0; e < c.n_cuts; ++e) {
     key->push_back(c.edge_up[e]);
@@ -246,13 +258,13 @@ int cqc_dd_workspace_size(const cqc_instance *inst, cqc_dtype in_t, cqc_precisio
 }
 
 int cqc_reconstruct_dd(const cqc_instance *inst, cqc_dtype in_t, cqc_precision prec,
-                       const cqc_dd_params *p, double *bins, cqc_dd_record *records,
+                       const cqc_dd_params *p, void *bins_v, cqc_dd_record *records,
                        int32_t *n_done, void *workspace, size_t ws_bytes, hipStream_t stream) {
   std::shared_ptr<const DdPlan> plan;
   Status st = cached_dd(inst, in_t, prec, p, &plan);
   if (!st.good()) return st.code;
   const DdPlan &d = *plan;
-  if (!bins || !records || !n_done) return Status::fail(CQC_ERR_INVALID_ARG, "bins, records or n_done is NULL").code;
+  if (!bins_v || !records || !n_done) return Status::fail(CQC_ERR_INVALID_ARG, "bins, records or n_done is NULL").code;
   if (!inst->entries) return Status::fail(CQC_ERR_INVALID_ARG, "entries is NULL").code;
   for (int c = 0; c < d.cut.nsub; ++c)
     if (!inst->entries[c]) return Status::fail(CQC_ERR_INVALID_ARG, "entries[" + std::to_string(c) + "] is NULL").code;
@@ -264,6 +276,9 @@ int cqc_reconstruct_dd(const cqc_instance *inst, cqc_dtype in_t, cqc_precision p
   const int n = d.cut.n;
   const bool in_double = in_t == CQC_F64, acc_double = d.acc == Acc::F64;
   const int64_t stride = int64_t(1) << d.a;
+  const size_t bin_size = d.bins_f32 ? 4 : 8;
+  char *bins = static_cast<char *>(bins_v);
+  auto bin_row = [&](int64_t r) { return bins + (size_t)r * (size_t)stride * bin_size; };
   DdSlot *dev_slots = reinterpret_cast<DdSlot *>(ws + d.out_off);
   std::vector<DdSlot> host_slots(d.per_round);
   std::vector<RecState> recs;
@@ -289,7 +304,7 @@ int cqc_reconstruct_dd(const cqc_instance *inst, cqc_dtype in_t, cqc_precision p
     RecState &rs = recs[k];
     const double av = rs.cands.back().first;
     const int64_t ai = rs.cands.back().second;
-    CQC_TRY(launch_topk(bins + (int64_t)k * stride, rs.nbins, kTopT, ws + d.topk_off, &dev_slots[0].top, av, ai,
+    CQC_TRY(launch_topk(bin_row(k), d.bins_f32, rs.nbins, kTopT, ws + d.topk_off, &dev_slots[0].top, av, ai,
                         stream));
     CQC_TRY(fetch(1));
     take(rs, host_slots[0].top);
@@ -404,6 +419,9 @@ int cqc_reconstruct_dd(const cqc_instance *inst, cqc_dtype in_t, cqc_precision p
         md.merged_pos = pack_pos(mpos);
         md.active_shift = contiguous_shift(apos);
         md.merged_shift = contiguous_shift(mpos);
+        md.log_chunks = merge_log_chunks(md.n_merged);
+        md.seg = merge_segmented(md.n_merged, md.active_shift, md.merged_shift) ? 1 : 0;
+        md.part = md.log_chunks > 0 ? reinterpret_cast<double *>(ws + dp.part_off[c]) : nullptr;
         int64_t zv = 0;
         for (int j = 0; j < f; ++j) {
           const int q = d.cut.qubits[c][j];
@@ -412,20 +430,20 @@ int cqc_reconstruct_dd(const cqc_instance *inst, cqc_dtype in_t, cqc_precision p
         }
         md.zoom_value = zv;
         md.block_start = blocks;
-        const int64_t nout = md.rows << md.n_active;
-        blocks += md.n_merged >= 6 ? (nout + 3) / 4 : (nout + 255) / 256;
+        blocks += merge_blocks(md.rows << md.n_active, md.n_merged, md.seg != 0);
       }
       st = launch_dd_merge(ma, blocks, in_double, acc_double, stream);
       if (!st.good()) return st.code;
-      // term sum onto the 2^#active bins (FP64 output and FP64 bin mass)
-      double *brow = bins + (int64_t)(r + i) * stride;
-      st = run_net(dp.net, ws, merged, brow, true, &dev_slots[i].mass, true, stream);
+      // term sum onto the 2^#active bins (FP64 or FP32 output, FP64 bin mass)
+      char *brow = bin_row(r + (int64_t)i);
+      st = run_net(dp.net, ws, merged, brow, !d.bins_f32, &dev_slots[i].mass, true, stream);
       if (!st.good()) return st.code;
       rs.has_merged = dp.has_merged;
       rs.nbins = int64_t(1) << dp.active.size();
       // candidates for later zooming
       if (dp.has_merged && r + (int)i + 1 < d.R) {
-        st = launch_topk(brow, rs.nbins, kTopT, ws + d.topk_off, &dev_slots[i].top, INFINITY, -1, stream);
+        st = launch_topk(brow, d.bins_f32, rs.nbins, kTopT, ws + d.topk_off, &dev_slots[i].top, INFINITY, -1,
+                         stream);
         if (!st.good()) return st.code;
       } else {
         rs.exhausted = true;

@@ -17,6 +17,11 @@ struct MergeDesc {
   int32_t n_active, n_merged;
   int32_t active_shift;   // >= 0: active bit j sits at local position active_shift + j
   int32_t merged_shift;   // >= 0: merged bit j sits at local position merged_shift + j
+  int32_t log_chunks;     // long merges: 2^log_chunks chunks per output, one wave each
+  double *part;           // [outputs][2^log_chunks] chunk sums (log_chunks > 0)
+  int64_t chunk_block_start;  // first block of this descriptor in the second pass (set by the launcher)
+  int32_t seg;            // short merge over the lowest bits with the active bits right above:
+                          //   a row's outputs are consecutive runs of 2^n_merged elements
   int64_t zoom_value;     // fixed bits of the zoomed qubits at their local positions
   BitPos active_pos;      // active bit j (from least significant) -> local position
   BitPos merged_pos;
@@ -33,12 +38,28 @@ struct TopOut {
   int64_t index[kTopT];
 };
 
+// Merged combinations per wave and chunk of a long merge.
+constexpr int kMergeLogChunk = 12;
+// Chunks per output of a merge over 2^n_merged combinations (log2).
+inline int merge_log_chunks(int n_merged) { return n_merged > kMergeLogChunk ? n_merged - kMergeLogChunk : 0; }
+// Whether a short merge can take the segmented path (see k_dd_merge).
+inline bool merge_segmented(int n_merged, int active_shift, int merged_shift) {
+  return n_merged >= 1 && n_merged < 6 && merged_shift == 0 && active_shift == n_merged;
+}
+// Blocks of one descriptor in the merge grid (2048 elements per segmented block).
+inline int64_t merge_blocks(int64_t nout, int n_merged, bool seg) {
+  if (n_merged >= 6) return ((nout << merge_log_chunks(n_merged)) + 3) / 4;
+  if (seg) return ((nout << n_merged) + 2047) / 2048;
+  return (nout + 255) / 256;
+}
+// blocks: sum of merge_blocks over the descriptors.  Long merges write chunk
+// sums to their `part` area, then a second pass adds them in chunk order.
 Status launch_dd_merge(const MergeArgs &a, int64_t blocks, bool in_double, bool out_double,
                        hipStream_t s);
 size_t topk_scratch_bytes(int64_t count, int t);
 // Best t bins ranked strictly after (after_v, after_i) in the order
 // (value descending, index ascending); missing places get index INT64_MAX.
-Status launch_topk(const double *bins, int64_t count, int t, void *scratch, TopOut *out,
+Status launch_topk(const void *bins, bool bins_f32, int64_t count, int t, void *scratch, TopOut *out,
                    double after_v, int64_t after_i, hipStream_t s);
 
 }  // namespace cqc

@@ -17,9 +17,12 @@ __device__ __forceinline__ int64_t dep_bits(int64_t v, const BitPos &pos, int nb
 }
 
 // E'_c[r][a] = sum_m E_c[r][dep(a, active) | zoom | dep(m, merged)], summed in
-// FP64 in ascending m (one wave per output when there are >= 64 merged
-// combinations, lanes strided over m and combined by a fixed butterfly; one
-// thread per output otherwise).
+// FP64.  With >= 64 merged combinations one wave takes each (output, chunk of
+// 2^kMergeLogChunk combinations): lanes strided over the chunk with eight
+// accumulators each, combined in a fixed tree and a fixed butterfly; an
+// output with one chunk is written directly, otherwise its chunk sums go to
+// `part` and k_dd_merge_chunks adds them in chunk order.  With fewer merged
+// combinations one thread takes each output, in ascending m.
 template <typename I, typename O>
 __global__ __launch_bounds__(256) void k_dd_merge(const MergeArgs a) {
   const int64_t bid = blockIdx.x;
@@ -33,29 +36,57 @@ __global__ __launch_bounds__(256) void k_dd_merge(const MergeArgs a) {
   const int64_t f = int64_t(1) << d.f;
   const int ash = d.active_shift, msh = d.merged_shift;
   if (nmerge >= 64) {
-    const int64_t o = (bid - d.block_start) * 4 + (threadIdx.x >> 6);
-    if (o >= nout) return;
+    const int lc = d.log_chunks;
+    const int64_t w = (bid - d.block_start) * 4 + (threadIdx.x >> 6);
+    if (w >= (nout << lc)) return;
+    const int64_t o = w >> lc, ch = w & ((int64_t(1) << lc) - 1);
+    const int64_t clen = nmerge >> lc;
     const int lane = threadIdx.x & 63;
     const int64_t r = o >> d.n_active, av = o & ((int64_t(1) << d.n_active) - 1);
     const int64_t base = (ash >= 0 ? av << ash : dep_bits(av, d.active_pos, d.n_active)) | d.zoom_value;
     const I *row = E + r * f;
-    // eight accumulators per lane (lane + 64 (8 q + u) goes to u), so eight
-    // loads are in flight; combined in a fixed tree, then across the wave
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int64_t m0 = lane; m0 < nmerge; m0 += 8 * 64) {
+    const int64_t m1 = (ch + 1) * clen;
+    for (int64_t m0 = ch * clen + lane; m0 < m1; m0 += 8 * 64) {
       double v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int64_t m = m0 + u * 64;
-        v[u] = m < nmerge ? (double)row[base | (msh >= 0 ? m << msh : dep_bits(m, d.merged_pos, d.n_merged))] : 0.0;
+        v[u] = m < m1 ? (double)row[base | (msh >= 0 ? m << msh : dep_bits(m, d.merged_pos, d.n_merged))] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) acc[u] += v[u];
     }
     double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
 #pragma unroll
-    for (int w = 32; w >= 1; w >>= 1) s += __shfl_xor(s, w, 64);
-    if (lane == 0) Out[o] = (O)s;
+    for (int k = 32; k >= 1; k >>= 1) s += __shfl_xor(s, k, 64);
+    if (lane == 0) {
+      if (lc == 0) Out[o] = (O)s;
+      else d.part[w] = s;
+    }
+  } else if (d.seg) {
+    // a row's merged runs are consecutive: element g of the stream (row r,
+    // offset e = av * nmerge + m) sits at row r, zoom | e.  Lanes read
+    // consecutive elements (eight loads in flight), and each aligned group of
+    // nmerge lanes adds its run by a butterfly within the group.
+    const int nm = d.n_merged;
+    const int64_t rowlen = int64_t(1) << (d.n_active + nm);
+    const int64_t total = nout << nm;
+    const int64_t g0 = (bid - d.block_start) * 2048 + threadIdx.x;
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t g = g0 + u * 256;
+      v[u] = g < total ? (double)E[(g / rowlen) * f + (d.zoom_value | (g % rowlen))] : 0.0;
+    }
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      double s = v[u];
+      for (int k = (1 << nm) >> 1; k >= 1; k >>= 1) s += __shfl_xor(s, k, 64);
+      const int64_t g = g0 + u * 256;
+      if ((lane & ((1 << nm) - 1)) == 0 && g < total) Out[g >> nm] = (O)s;
+    }
   } else {
     const int64_t o = (bid - d.block_start) * 256 + threadIdx.x;
     if (o >= nout) return;
@@ -67,6 +98,24 @@ __global__ __launch_bounds__(256) void k_dd_merge(const MergeArgs a) {
       s += (double)row[base | (msh >= 0 ? m << msh : dep_bits(m, d.merged_pos, d.n_merged))];
     Out[o] = (O)s;
   }
+}
+
+// Second pass of long merges: one thread per output adds its chunk sums in
+// chunk order.  Descriptors without chunks have no blocks here.
+template <typename O>
+__global__ __launch_bounds__(256) void k_dd_merge_chunks(const MergeArgs a) {
+  const int64_t bid = blockIdx.x;
+  int i = 0;
+  while (i + 1 < a.n && bid >= a.d[i + 1].chunk_block_start) ++i;
+  const MergeDesc &d = a.d[i];
+  const int64_t o = (bid - d.chunk_block_start) * 256 + threadIdx.x;
+  const int64_t nout = d.rows << d.n_active;
+  if (d.log_chunks == 0 || o >= nout) return;
+  const int64_t nc = int64_t(1) << d.log_chunks;
+  const double *p = d.part + o * nc;
+  double s = 0.0;
+  for (int64_t c = 0; c < nc; ++c) s += p[c];
+  static_cast<O *>(d.dst)[o] = (O)s;
 }
 
 // ---- top-T of FP64 bins, ordered by (value descending, index ascending)
@@ -136,7 +185,8 @@ __device__ __forceinline__ void block_top(Cand (&m)[kTopT], Cand *out) {
 // Stage 1: each block ranks a contiguous range of bins, keeping only the
 // candidates ranked strictly after `after` (so a consumed prefix of the
 // ranking can be skipped when more candidates are needed).
-__global__ __launch_bounds__(256) void k_topk_stage1(const double *bins, int64_t count, int64_t per_block,
+template <typename B>
+__global__ __launch_bounds__(256) void k_topk_stage1(const B *bins, int64_t count, int64_t per_block,
                                                      Cand *partial, double after_v, int64_t after_i) {
   Cand m[kTopT];
 #pragma unroll
@@ -151,7 +201,7 @@ __global__ __launch_bounds__(256) void k_topk_stage1(const double *bins, int64_t
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int64_t i = c0 + u * 256 + threadIdx.x;
-      v[u] = i < b1 ? bins[i] : 0.0;
+      v[u] = i < b1 ? (double)bins[i] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -191,10 +241,23 @@ Status launch_dd_merge(const MergeArgs &a, int64_t blocks, bool in_double, bool 
                        hipStream_t s) {
   const dim3 g((unsigned)blocks), b(256);
   if (in_double)
-    return out_double ? launch("dd_merge", k_dd_merge<double, double>, g, b, 0, s, a)
-                      : launch("dd_merge", k_dd_merge<double, float>, g, b, 0, s, a);
-  return out_double ? launch("dd_merge", k_dd_merge<float, double>, g, b, 0, s, a)
-                    : launch("dd_merge", k_dd_merge<float, float>, g, b, 0, s, a);
+    CQC_TRY(out_double ? launch("dd_merge", k_dd_merge<double, double>, g, b, 0, s, a)
+                       : launch("dd_merge", k_dd_merge<double, float>, g, b, 0, s, a));
+  else
+    CQC_TRY(out_double ? launch("dd_merge", k_dd_merge<float, double>, g, b, 0, s, a)
+                       : launch("dd_merge", k_dd_merge<float, float>, g, b, 0, s, a));
+  // second pass over the descriptors with chunked merges (the others get an
+  // empty block range)
+  MergeArgs c = a;
+  int64_t nb = 0;
+  for (int i = 0; i < c.n; ++i) {
+    c.d[i].chunk_block_start = nb;
+    if (c.d[i].log_chunks > 0) nb += ((c.d[i].rows << c.d[i].n_active) + 255) / 256;
+  }
+  if (nb == 0) return Status::ok();
+  const dim3 g2((unsigned)nb);
+  return out_double ? launch("dd_merge_chunks", k_dd_merge_chunks<double>, g2, b, 0, s, c)
+                    : launch("dd_merge_chunks", k_dd_merge_chunks<float>, g2, b, 0, s, c);
 }
 
 size_t topk_scratch_bytes(int64_t count, int t) {
@@ -203,14 +266,18 @@ size_t topk_scratch_bytes(int64_t count, int t) {
   return sizeof(Cand) * (size_t)(blocks * kTopT);
 }
 
-Status launch_topk(const double *bins, int64_t count, int t, void *scratch, TopOut *out,
+Status launch_topk(const void *bins, bool bins_f32, int64_t count, int t, void *scratch, TopOut *out,
                    double after_v, int64_t after_i, hipStream_t s) {
   const int64_t blocks = std::min<int64_t>(1024, (count + 2047) / 2048);
   const int64_t per_block = (count + blocks - 1) / blocks;
   if (t < 1 || t > kTopT) return Status::fail(CQC_ERR_INVALID_ARG, "top-k count out of range");
   Cand *partial = static_cast<Cand *>(scratch);
-  CQC_TRY(launch("topk_stage1", k_topk_stage1, dim3((unsigned)blocks), dim3(256), 0, s, bins, count, per_block,
-                 partial, after_v, after_i));
+  if (bins_f32)
+    CQC_TRY(launch("topk_stage1", k_topk_stage1<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                   static_cast<const float *>(bins), count, per_block, partial, after_v, after_i));
+  else
+    CQC_TRY(launch("topk_stage1", k_topk_stage1<double>, dim3((unsigned)blocks), dim3(256), 0, s,
+                   static_cast<const double *>(bins), count, per_block, partial, after_v, after_i));
   static_assert(1024 * kTopT <= 8 * 1024, "stage 2 holds eight candidates per thread");
   return launch("topk_stage2", k_topk_stage2, dim3(1), dim3(1024), 0, s, static_cast<const Cand *>(partial),
                 blocks * kTopT, t, out);

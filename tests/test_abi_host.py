@@ -179,8 +179,8 @@ def test_chi2_validation():
     assert L.cqc_chi2(0x1000, 0, 0x2000, 0, 10, out, None, 8192, None) == 4
 
 
-def _dd_ws(inst, strategy=0, per_round=1, a=3, R=4):
-    params = _lib.CqcDDParams(a, R, None, strategy, per_round)
+def _dd_ws(inst, strategy=0, per_round=1, a=3, R=4, f32=0):
+    params = _lib.CqcDDParams(a, R, None, strategy, per_round, f32)
     nb = ctypes.c_size_t(0)
     rc = _lib.lib().cqc_dd_workspace_size(ctypes.byref(inst), 0, 1, ctypes.byref(params), ctypes.byref(nb))
     return rc, nb.value
@@ -214,3 +214,15 @@ def test_dd_plan_cache_keys_on_every_input():
         assert _dd_ws(inst, 0, 1, 3)[1] == ref["a3"]
         assert _dd_ws(inst, 2, 16, 3)[1] == ref["r16"]
         assert _dd_ws(inst_perm, 0, 1, 5)[1] == ref["perm"]
+
+
+def test_dd_active_limit_and_bin_dtype():
+    """Up to 36 active qubits (2^36 bins); the bins flag is 0 (FP64) or 1
+    (FP32) and both are accepted for a 100-qubit, five-subcircuit cut."""
+    edges = [(0, 1), (0, 1), (1, 2), (1, 2), (2, 3), (2, 3), (3, 4), (3, 4)]
+    inst = _inst(100, [20] * 5, edges, list(range(100)))
+    assert _dd_ws(inst, 0, 1, 35, 1, 1)[0] == 0
+    assert _dd_ws(inst, 0, 1, 36, 1, 0)[0] == 0
+    assert _dd_ws(inst, 0, 1, 37, 1, 1)[0] == 1
+    assert _dd_ws(inst, 0, 1, 35, 1, 2)[0] == 1
+    assert _dd_ws(inst, 0, 1, 35, 1, -1)[0] == 1

@@ -46,6 +46,13 @@ RECIPES = {
 
 DD_C4 = dict(n_active=20, n_recursions=5)
 
+# DD at the paper's large-circuit scale (Section 6.2, Figure 10: one recursion
+# of 2^35 bins for circuits of up to 100 qubits): a 100-qubit chain of five
+# 20-qubit subcircuits, two cuts per boundary (K = 8).  No simulation produces
+# 100-qubit entries, so they are seeded signed random values of the right
+# shapes (not uniform distributions, whose bins would all be equal).
+DD_SCALE = dict(n=100, f=(20, 20, 20, 20, 20), cuts_per_boundary=2, n_active=35, n_recursions=1, seed=35)
+
 
 def make_instance(own, bridges, layers, seed, name="custom", x_gates=()):
     circ = bridged_chain(own, bridges, layers, seed, x_gates=x_gates)
@@ -102,6 +109,26 @@ def sample_outputs(n, count, seed):
     while len(s) < count:
         s.update(int(v) for v in rng.integers(0, 2 ** n, size=count - len(s)))
     return np.array(sorted(s), dtype=np.int64)
+
+
+def dd_scale_instance(seed=None):
+    """The DD_SCALE cut and its FP32 entries (uniform in [-1, 1) times 2^-f_c),
+    drawn directly in FP32: about 3 GiB."""
+    r = DD_SCALE
+    m = len(r["f"])
+    up = [c for c in range(m - 1) for _ in range(r["cuts_per_boundary"])]
+    down = [c + 1 for c in up]
+    cut = CutMap(r["n"], list(r["f"]), up, down, list(range(r["n"])))
+    rng = np.random.default_rng(r["seed"] if seed is None else seed)
+    ents = []
+    for c in range(cut.n_sub):
+        rows, w = cut.entry_shape(c)
+        E = rng.random((rows, w), dtype=np.float32)
+        E *= np.float32(2.0)
+        E -= np.float32(1.0)
+        E *= np.float32(2.0 ** -cut.f[c])
+        ents.append(E)
+    return cut, ents
 
 
 def random_entries(cut: CutMap, seed, zero_rows=(), scale=None):
