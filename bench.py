@@ -479,15 +479,14 @@ def bench_batch(args, torch, cqc, W):
     e32_np = [[E.astype(np.float32) for E in i.entries] for i in insts]
     ents = [[torch.from_numpy(E).cuda() for E in e] for e in e32_np]
     # every instance's p, target and dL/dp are slices of one flat buffer, so
-    # the cross-entropy gradient dL/dp = -t / max(p, 1e-30) of all instances
-    # is two elementwise launches (the negated targets are input data)
+    # the cross-entropy gradient (dL/dp = -t/p where p > 1e-30, else 0) of all
+    # instances is one fused library pass
     sizes = [2 ** i.n for i in insts]
     total = sum(sizes)
     p_flat = torch.empty(total, dtype=torch.float32, device="cuda")
     g_flat = torch.empty(total, dtype=torch.float32, device="cuda")
-    tmp_flat = torch.empty(total, dtype=torch.float32, device="cuda")
-    negt_flat = torch.from_numpy(np.concatenate(
-        [-W.dirichlet_target(i.n, 1000 + k).astype(np.float32) for k, i in enumerate(insts)])).cuda()
+    t_flat = torch.from_numpy(np.concatenate(
+        [W.dirichlet_target(i.n, 1000 + k).astype(np.float32) for k, i in enumerate(insts)])).cuda()
     outs = list(torch.split(p_flat, sizes))
     grads_out = list(torch.split(g_flat, sizes))
     batch = cqc.Batch(ents, cuts, precision="fp32", outs=outs)
@@ -495,8 +494,7 @@ def bench_batch(args, torch, cqc, W):
 
     def body():
         batch.run()
-        torch.clamp_min(p_flat, 1e-30, out=tmp_flat)
-        torch.div(negt_flat, tmp_flat, out=g_flat)
+        cqc.xent_grad(p_flat, t_flat, grad=g_flat)
         bwd.run()
     steps = args.steps or 20
     warmup = args.warmup if args.warmup is not None else 3

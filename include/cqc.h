@@ -225,6 +225,21 @@ int cqc_build_entries(const cqc_entry_job *jobs, int32_t n_jobs, cqc_dtype in_t,
 int cqc_chi2(const void *a, cqc_dtype a_t, const void *b, cqc_dtype b_t, int64_t n, double *out,
              void *workspace, size_t ws_bytes, hipStream_t stream);
 
+/* Cross-entropy of reconstructed outputs p against a target distribution t,
+ * and its gradient, in one pass (the loss that drives the adjoint below):
+ *     loss = -sum_x t_x log max(p_x, 1e-30)     (FP64, if loss != NULL)
+ *     grad_x = -t_x / p_x if p_x > 1e-30, else 0 (the floor is flat)
+ * p, t, grad: DEVICE [n] of dtype dt (grad may alias neither p nor t); the
+ * floor test is made on p widened to FP64, the division in dt.  Flat buffers
+ * of many instances' outputs are one call.  loss: DEVICE, one FP64, or NULL;
+ * with a loss the workspace (DEVICE, >= 8192 bytes, 8-byte aligned) holds
+ * per-block partials added in a fixed order (bitwise reproducible for a given
+ * n).  One or two launches on `stream`.  Errors: CQC_ERR_INVALID_ARG for an
+ * unknown dtype, n < 0 or NULL buffers with n > 0; CQC_ERR_WORKSPACE for a
+ * loss without enough workspace. */
+int cqc_xent_grad(const void *p, const void *t, cqc_dtype dt, int64_t n, void *grad, double *loss,
+                  void *workspace, size_t ws_bytes, hipStream_t stream);
+
 /* Dynamic definition (Algorithm 1, Section 4.3).
  * Recursion 1 makes `first_active` (or, if NULL, the first n_active qubits in
  * output order) active; every later recursion refines one bin produced so far

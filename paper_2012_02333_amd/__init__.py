@@ -19,7 +19,7 @@ import torch
 from . import _lib
 from ._lib import CqcError, PREC
 
-__all__ = ["CutMap", "reconstruct_fd", "reconstruct_dd", "reconstruct_backward", "FDCall", "Batch", "BatchBackward", "build_entries", "chi2",
+__all__ = ["CutMap", "reconstruct_fd", "reconstruct_dd", "reconstruct_backward", "FDCall", "Batch", "BatchBackward", "build_entries", "chi2", "xent_grad",
            "ReconstructFD", "BackwardCall", "cost", "autotune", "trace", "CqcError", "selftest_mfma", "library_path"]
 
 _DT = {torch.float32: _lib.F32, torch.float64: _lib.F64}
@@ -282,6 +282,29 @@ def chi2(a, b):
     _lib.check(_lib.lib().cqc_chi2(a.data_ptr(), _DT[a.dtype], b.data_ptr(), _DT[b.dtype], a.numel(),
                                     out.data_ptr(), ws.data_ptr(), ws.numel(), s))
     return out
+
+
+def xent_grad(p, t, grad=None, with_loss=False):
+    """Cross-entropy gradient dL/dp = -t/p where p > 1e-30, else 0, in one pass
+    (cqc_xent_grad), enqueued on the current stream -> grad (or (grad, loss)
+    with with_loss: loss = -sum t log max(p, 1e-30) as a 0-d FP64 tensor).
+    p, t, grad: contiguous 1-d device tensors of one float dtype; a flat buffer
+    of many instances' outputs is one call."""
+    if p.shape != t.shape or p.dim() != 1 or not p.is_cuda or not t.is_cuda or p.dtype != t.dtype:
+        raise ValueError("p and t must be 1-d device tensors of one shape and dtype")
+    if p.dtype not in _DT or not p.is_contiguous() or not t.is_contiguous():
+        raise ValueError("p and t must be contiguous float32 or float64")
+    if grad is None:
+        grad = torch.empty_like(p)
+    elif grad.shape != p.shape or grad.dtype != p.dtype or not grad.is_contiguous() or not grad.is_cuda:
+        raise ValueError("grad must be a contiguous device tensor like p")
+    loss = torch.empty((), dtype=torch.float64, device=p.device) if with_loss else None
+    ws = _workspace(8192, p.device) if with_loss else None
+    s = torch.cuda.current_stream(p.device).cuda_stream
+    _lib.check(_lib.lib().cqc_xent_grad(p.data_ptr(), t.data_ptr(), _DT[p.dtype], p.numel(), grad.data_ptr(),
+                                         loss.data_ptr() if with_loss else None,
+                                         ws.data_ptr() if with_loss else None, ws.numel() if with_loss else 0, s))
+    return (grad, loss) if with_loss else grad
 
 
 def reconstruct_fd(entries, cut, precision="fp32", out_dtype=None, with_mass=True):

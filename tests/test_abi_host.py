@@ -226,3 +226,16 @@ def test_dd_active_limit_and_bin_dtype():
     assert _dd_ws(inst, 0, 1, 37, 1, 1)[0] == 1
     assert _dd_ws(inst, 0, 1, 35, 1, 2)[0] == 1
     assert _dd_ws(inst, 0, 1, 35, 1, -1)[0] == 1
+
+
+def test_xent_grad_validation():
+    """cqc_xent_grad refuses a bad dtype, n < 0, NULL buffers and a loss
+    without workspace before any launch."""
+    L = _lib.lib()
+    p, t, g, loss, ws = 0x1000, 0x2000, 0x3000, 0x4000, 0x5000
+    assert L.cqc_xent_grad(p, t, 9, 10, g, None, None, 0, None) == 1
+    assert L.cqc_xent_grad(p, t, 0, -1, g, None, None, 0, None) == 1
+    assert L.cqc_xent_grad(None, t, 0, 10, g, None, None, 0, None) == 1
+    assert L.cqc_xent_grad(p, t, 0, 10, None, None, None, 0, None) == 1
+    assert L.cqc_xent_grad(p, t, 0, 10, g, loss, None, 0, None) == 4
+    assert L.cqc_xent_grad(p, t, 0, 10, g, loss, ws, 100, None) == 4
