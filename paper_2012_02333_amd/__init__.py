@@ -19,7 +19,7 @@ import torch
 from . import _lib
 from ._lib import CqcError, PREC
 
-__all__ = ["CutMap", "reconstruct_fd", "reconstruct_dd", "reconstruct_backward", "FDCall", "Batch", "BatchBackward", "build_entries", "chi2", "xent_grad",
+__all__ = ["CutMap", "reconstruct_fd", "reconstruct_dd", "reconstruct_backward", "FDCall", "Batch", "BatchBackward", "build_entries", "chi2", "xent_grad", "shard",
            "ReconstructFD", "BackwardCall", "cost", "autotune", "trace", "CqcError", "selftest_mfma", "library_path"]
 
 _DT = {torch.float32: _lib.F32, torch.float64: _lib.F64}
@@ -282,6 +282,37 @@ def chi2(a, b):
     _lib.check(_lib.lib().cqc_chi2(a.data_ptr(), _DT[a.dtype], b.data_ptr(), _DT[b.dtype], a.numel(),
                                     out.data_ptr(), ws.data_ptr(), ws.numel(), s))
     return out
+
+
+def shard(entries, cut, n_shards, index):
+    """One GPU's share of an FD reconstruction over n_shards GPUs: the outputs
+    whose top log2(n_shards) global bits equal `index`.  Those bits must be the
+    leading local bits of one subcircuit (its columns are then sliced); the
+    shard is an ordinary instance -> (entries', cut') whose 2^(n-b) outputs
+    are p[index * 2^(n-b) : (index + 1) * 2^(n-b)] of the full reconstruction.
+    Host-side slicing only; every GPU runs the same kernels on its shard."""
+    b = int(n_shards).bit_length() - 1
+    if n_shards < 1 or (1 << b) != n_shards or not 0 <= index < n_shards:
+        raise ValueError("n_shards must be a power of two and 0 <= index < n_shards")
+    if b == 0:
+        return list(entries), cut
+    off, owner = 0, None
+    for c, fc in enumerate(cut.f):
+        local = cut.out_qubits[off:off + fc]
+        if local[:b] == list(range(b)) and fc >= b:
+            owner = (c, off)
+        off += fc
+    if owner is None:
+        raise ValueError("the top output bits are not the leading local bits of one subcircuit")
+    c, off = owner
+    fc = cut.f[c]
+    w = 1 << (fc - b)
+    new_entries = list(entries)
+    new_entries[c] = entries[c][:, index * w:(index + 1) * w].contiguous()
+    f = list(cut.f)
+    f[c] = fc - b
+    oq = [q - b for q in cut.out_qubits[:off]] + [q - b for q in cut.out_qubits[off + b:]]
+    return new_entries, CutMap(cut.n - b, f, cut.edges, oq)
 
 
 def xent_grad(p, t, grad=None, with_loss=False):
