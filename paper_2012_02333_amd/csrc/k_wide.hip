@@ -2,7 +2,8 @@
 // long enough to make the step compute-bound (many shared cut labels), in two
 // arithmetic forms of the same tile program.
 //
-//   FP32    float operands on v_mfma_f32_16x16x4f32, FP32 accumulation.
+//   FP32    float operands on v_mfma_f32_32x32x2f32, FP32 accumulation (on
+//           this part it sustains about 20% more than the 16x16x4 form).
 //   BF16X6  every float operand a is split into three bfloat16 parts
 //           a = a0 + a1 + a2 (a0 = a rounded to bfloat16, a1 = the remainder
 //           rounded, a2 = the next remainder rounded; the remainders are exact
@@ -42,6 +43,7 @@ namespace cqc {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int i32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 namespace {
 constexpr int kWB = 128;        // block tile edge (m and n)
@@ -249,6 +251,7 @@ __device__ __forceinline__ void wide_run(Seq &seq) {
   // operand staging area: FP32 [256 columns][kF32Ld]; split forms [NP parts][256][kB16Ld]
   constexpr int kOpBytes = NP ? NP * 2 * kWB * kB16Ld * 2 : 2 * kWB * kF32Ld * 4;
   static_assert(kOpBytes >= 4 * 16 * kStLd * 4, "epilogue staging fits in the operand area");
+  static_assert(NP != 0 || kOpBytes >= 4 * 32 * kStLd * 4, "32-row staging slices fit in the operand area");
   __shared__ __attribute__((aligned(16))) unsigned char smem[kOpBytes];
   __shared__ double red[4];
   __shared__ int64_t rowoff[MODE == kModeFinalDeposit ? kWB : 1];
@@ -264,11 +267,27 @@ __device__ __forceinline__ void wide_run(Seq &seq) {
   const bool roleX = (wv & 1) == 0;
   const int half = wv >> 1;
 
+  // accumulators: split forms 4 x 4 blocks of 16 x 16 (f32x4 per lane); the
+  // FP32 form 2 x 2 blocks of 32 x 32 (f32x16 per lane: lane l, register r
+  // holds row n = (r % 4) + 8 (r / 4) + 4 (l / 32), column m = l % 32)
   f32x4 acc[4][4];
+  f32x16 acc2[2][2];
+  auto zero_acc = [&]() {
+    if constexpr (NP == 0) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) acc2[i][j][r] = 0.f;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+  zero_acc();
 
   // Branch-free prefetch: every lane loads (padding and overhanging columns
   // read element 0), so all kWC loads of a chunk are in flight together; the
@@ -308,15 +327,18 @@ __device__ __forceinline__ void wide_run(Seq &seq) {
     auto val = [&](int k, int j) { return (colok[b][j] && ((okrow[b] >> k) & 1u)) ? pre[b][k][j] : 0.0f; };
     const int col0 = (roleX ? 0 : kWB) + 2 * lane;   // first of this lane's two LDS operand columns
     if constexpr (NP == 0) {
-      // term k of a 16-term group g sits at 16 g + 4 (k % 4) + (k % 16) / 4, so
-      // lane group lg reads terms {lg, lg+4, lg+8, lg+12} of the group at once;
-      // this wave's half is group `half`
+      // term 2 s + h of an 8-term group sits at 4 h + s, so the half-wave h of
+      // a 32 x 32 x 2 product reads its terms {h, h+2, h+4, h+6} of the group
+      // at once; this wave's 16 terms are groups 2 half and 2 half + 1
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         float *cp = reinterpret_cast<float *>(smem) + (col0 + j) * kF32Ld + 16 * half;
 #pragma unroll
-        for (int p = 0; p < 4; ++p)
-          *reinterpret_cast<float4 *>(cp + 4 * p) = make_float4(val(p, j), val(4 + p, j), val(8 + p, j), val(12 + p, j));
+        for (int g8 = 0; g8 < 2; ++g8)
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            *reinterpret_cast<float4 *>(cp + 8 * g8 + 4 * h) =
+                make_float4(val(8 * g8 + h, j), val(8 * g8 + 2 + h, j), val(8 * g8 + 4 + h, j), val(8 * g8 + 6 + h, j));
       }
     } else {
       __bf16 *bp = reinterpret_cast<__bf16 *>(smem);
@@ -344,28 +366,28 @@ __device__ __forceinline__ void wide_run(Seq &seq) {
   // <-> m), so lane (l16, lg) accumulates 4 consecutive n of output row l16.
   auto compute = [&]() {
     if constexpr (NP == 0) {
-      const float *px = reinterpret_cast<const float *>(smem) + (wm * kWT + l16) * kF32Ld + 4 * lg;
-      const float *py = reinterpret_cast<const float *>(smem) + (kWB + wn * kWT + l16) * kF32Ld + 4 * lg;
+      // lane (i = l % 32, h = l / 32) feeds operand row/column i and term
+      // 2 s + h of each 8-term group to the s-th product of the group
+      const int i32 = lane & 31, h = lane >> 5;
+      const float *px = reinterpret_cast<const float *>(smem) + (wm * kWT + i32) * kF32Ld + 4 * h;
+      const float *py = reinterpret_cast<const float *>(smem) + (kWB + wn * kWT + i32) * kF32Ld + 4 * h;
 #pragma unroll
-      for (int g = 0; g < 2; ++g) {
-        float xv[4][4], yv[4][4];
+      for (int g = 0; g < kWC / 8; ++g) {
+        float xa[2][4], yb[2][4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const float4 v = *reinterpret_cast<const float4 *>(px + i * 16 * kF32Ld + 16 * g);
-          xv[i][0] = v.x; xv[i][1] = v.y; xv[i][2] = v.z; xv[i][3] = v.w;
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const float4 v = *reinterpret_cast<const float4 *>(py + j * 16 * kF32Ld + 16 * g);
-          yv[j][0] = v.x; yv[j][1] = v.y; yv[j][2] = v.z; yv[j][3] = v.w;
+        for (int b = 0; b < 2; ++b) {
+          const float4 v = *reinterpret_cast<const float4 *>(px + b * 32 * kF32Ld + 8 * g);
+          xa[b][0] = v.x; xa[b][1] = v.y; xa[b][2] = v.z; xa[b][3] = v.w;
+          const float4 w = *reinterpret_cast<const float4 *>(py + b * 32 * kF32Ld + 8 * g);
+          yb[b][0] = w.x; yb[b][1] = w.y; yb[b][2] = w.z; yb[b][3] = w.w;
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
+          for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(yv[j][q], xv[i][q], acc[i][j], 0, 0, 0);
+            for (int j = 0; j < 2; ++j)
+              acc2[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(yb[j][q], xa[i][q], acc2[i][j], 0, 0, 0);
       }
     } else {
       const __bf16 *bp = reinterpret_cast<const __bf16 *>(smem);
@@ -416,57 +438,91 @@ __device__ __forceinline__ void wide_run(Seq &seq) {
     const double sc64 = uni(a.scale);
     const float scf = MODE == kModeIntermediate ? 1.0f : (float)sc64;
     const O scale = (O)sc64;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      if (kStage && mw + i * 16 + 16 <= M && nw + kWT <= N) {
-        float *st = reinterpret_cast<float *>(smem) + wave * 16 * kStLd;
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          *reinterpret_cast<float4 *>(st + l16 * kStLd + j * 16 + 4 * lg) =
-              make_float4(acc[i][j][0] * scf, acc[i][j][1] * scf, acc[i][j][2] * scf, acc[i][j][3] * scf);
-        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-        // 16 lanes per 64-float row, 4 rows per store instruction.  The
-        // stores are non-temporal: the output is written once and never read
-        // here, so it should not evict the operands from L2 (measured 5%
-        // faster for BF16X6, and the L2 holds fewer dirty lines at the end)
-#pragma unroll
-        for (int rr = 0; rr < 16; rr += 4) {
-          const int row = rr + lg, c4 = l16 * 4;
-          const float4 v = *reinterpret_cast<const float4 *>(st + row * kStLd + c4);
-          __builtin_nontemporal_store(f32x4{v.x, v.y, v.z, v.w},
-                                      (gptr<f32x4>)((gptr<float>)Zb + (mw + i * 16 + row) * N + nw + c4));
-          if (MODE != kModeIntermediate) msum += ((double)v.x + (double)v.y) + ((double)v.z + (double)v.w);
-        }
-        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-        continue;
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int64_t m = mw + i * 16 + l16;
-        const int64_t n = nw + j * 16 + 4 * lg;
-        if (m >= M || n >= N) continue;
-        if (MODE == kModeIntermediate) {
-          const gptr<float> Z = (gptr<float>)Zb + m * N + n;
-          if (n + 3 < N) *(gptr<f32x4>)Z = acc[i][j];
-          else
-            for (int r = 0; r < 4; ++r)
-              if (n + r < N) Z[r] = acc[i][j][r];
-        } else {
-          O v[4];
-#pragma unroll
-          for (int r = 0; r < 4; ++r) v[r] = (O)acc[i][j][r] * scale;
-          if (MODE == kModeFinalBlocked) {
-            const gptr<O> Z = Zb + m * N + n;
-            for (int r = 0; r < 4; ++r)
-              if (n + r < N) Z[r] = v[r];
-          } else {
-            const int64_t ro = rowoff[m - g.m0];
-            for (int r = 0; r < 4; ++r)
-              if (n + r < N) Zb[ro + coloff[n + r - g.n0]] = v[r];
-          }
+    // a run of 4 consecutive n of output row m, written element-wise (edge
+    // tiles, FP64 output, bit-deposit order)
+    auto write_run = [&](int64_t m, int64_t n, const f32x4 &vals) {
+      if (m >= M || n >= N) return;
+      if (MODE == kModeIntermediate) {
+        const gptr<float> Z = (gptr<float>)Zb + m * N + n;
+        if (n + 3 < N) *(gptr<f32x4>)Z = vals;
+        else
           for (int r = 0; r < 4; ++r)
-            if (n + r < N) msum += (double)v[r];
+            if (n + r < N) Z[r] = vals[r];
+      } else {
+        O v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = (O)vals[r] * scale;
+        if (MODE == kModeFinalBlocked) {
+          const gptr<O> Z = Zb + m * N + n;
+          for (int r = 0; r < 4; ++r)
+            if (n + r < N) Z[r] = v[r];
+        } else {
+          const int64_t ro = rowoff[m - g.m0];
+          for (int r = 0; r < 4; ++r)
+            if (n + r < N) Zb[ro + coloff[n + r - g.n0]] = v[r];
         }
+        for (int r = 0; r < 4; ++r)
+          if (n + r < N) msum += (double)v[r];
+      }
+    };
+    // a staged slice of `rows` output rows x 64 columns (this wave's LDS
+    // slice, already written): 16 lanes per 64-float row, 4 rows per store
+    // instruction.  The stores are non-temporal: the output is written once
+    // and never read here, so it should not evict the operands from L2
+    // (measured 5% faster for BF16X6, and the L2 holds fewer dirty lines at
+    // the end)
+    auto store_slice = [&](const float *st, int rows, int64_t m0) {
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      for (int rr = 0; rr < rows; rr += 4) {
+        const int row = rr + lg, c4 = l16 * 4;
+        const float4 v = *reinterpret_cast<const float4 *>(st + row * kStLd + c4);
+        __builtin_nontemporal_store(f32x4{v.x, v.y, v.z, v.w},
+                                    (gptr<f32x4>)((gptr<float>)Zb + (m0 + row) * N + nw + c4));
+        if (MODE != kModeIntermediate) msum += ((double)v.x + (double)v.y) + ((double)v.z + (double)v.w);
+      }
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    };
+    if constexpr (NP == 0) {
+      // 32 x 32 blocks: lane l holds, for output row m = mb + l % 32, the runs
+      // n = 32 bj + 8 q + 4 (l / 32) + {0..3} in registers 4 q .. 4 q + 3
+      const int i32 = lane & 31, h = lane >> 5;
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi) {
+        const int64_t mb = mw + bi * 32;
+        if (kStage && mb + 32 <= M && nw + kWT <= N) {
+          float *st = reinterpret_cast<float *>(smem) + wave * 32 * kStLd;
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              *reinterpret_cast<float4 *>(st + i32 * kStLd + bj * 32 + 8 * q + 4 * h) =
+                  make_float4(acc2[bi][bj][4 * q] * scf, acc2[bi][bj][4 * q + 1] * scf,
+                              acc2[bi][bj][4 * q + 2] * scf, acc2[bi][bj][4 * q + 3] * scf);
+          store_slice(st, 32, mb);
+          continue;
+        }
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            write_run(mb + i32, nw + bj * 32 + 8 * q + 4 * h,
+                      f32x4{acc2[bi][bj][4 * q], acc2[bi][bj][4 * q + 1], acc2[bi][bj][4 * q + 2],
+                            acc2[bi][bj][4 * q + 3]});
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (kStage && mw + i * 16 + 16 <= M && nw + kWT <= N) {
+          float *st = reinterpret_cast<float *>(smem) + wave * 16 * kStLd;
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            *reinterpret_cast<float4 *>(st + l16 * kStLd + j * 16 + 4 * lg) =
+                make_float4(acc[i][j][0] * scf, acc[i][j][1] * scf, acc[i][j][2] * scf, acc[i][j][3] * scf);
+          store_slice(st, 16, mw + i * 16);
+          continue;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) write_run(mw + i * 16 + l16, nw + j * 16 + 4 * lg, acc[i][j]);
       }
     }
     double *partials = uni(a.partials);
@@ -535,10 +591,7 @@ __device__ __forceinline__ void wide_run(Seq &seq) {
     if (q0.ok && q0.c == q0.t.nch - 1) {
       __syncthreads();   // every wave is done reading operands: stage the outputs
       epilogue(item_args(q0), q0.t);
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+      zero_acc();
     }
     if (decltype(B)::value == 1 && !q1.ok) return false;
     if (q1.ok) q0 = q1;
