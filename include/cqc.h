@@ -325,6 +325,10 @@ int cqc_cost(const cqc_cut *cut, double *eq14_mults, double *plan_macs);
 int cqc_autotune(const cqc_instance *inst, int32_t n_inst, cqc_dtype in_t,
                  cqc_dtype out_t, cqc_precision prec, void *workspace,
                  size_t ws_bytes, hipStream_t stream);
+/* Clears the process-wide tile cache; the next plan that consults it reloads
+ * the file named by CQC_TUNE_CACHE (if set).  Host only; not to be called
+ * while another thread plans or tunes. */
+int cqc_tune_reset(void);
 
 /* Kernel tracing: when enabled, every kernel the library launches is
  * bracketed by HIP events on its stream; cqc_trace_read reports, per kernel

@@ -20,7 +20,7 @@ from . import _lib
 from ._lib import CqcError, PREC
 
 __all__ = ["CutMap", "reconstruct_fd", "reconstruct_dd", "reconstruct_backward", "FDCall", "Batch", "BatchBackward", "build_entries", "chi2", "xent_grad", "shard",
-           "ReconstructFD", "BackwardCall", "cost", "autotune", "trace", "CqcError", "selftest_mfma", "library_path"]
+           "ReconstructFD", "BackwardCall", "cost", "autotune", "tune_reset", "trace", "CqcError", "selftest_mfma", "library_path"]
 
 _DT = {torch.float32: _lib.F32, torch.float64: _lib.F64}
 
@@ -490,6 +490,12 @@ def autotune(call):
     s = torch.cuda.current_stream(call.device).cuda_stream
     _lib.check(_lib.lib().cqc_autotune(call._insts, call.n_inst, call._in_t, call._out_t, call.prec,
                                        call.ws.data_ptr(), call.ws_bytes, s))
+
+
+def tune_reset():
+    """Clear the process-wide tile cache (cqc_tune_reset); the next plan reloads
+    the file named by CQC_TUNE_CACHE, if set."""
+    _lib.check(_lib.lib().cqc_tune_reset())
 
 
 def cost(cut):

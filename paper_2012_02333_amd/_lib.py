@@ -20,7 +20,7 @@ EXPORTS = [
     "cqc_trace_enable", "cqc_trace_read", "cqc_status_string", "cqc_last_error_detail",
     "cqc_version", "cqc_selftest_mfma", "cqc_batch_create", "cqc_batch_run", "cqc_batch_destroy",
     "cqc_batch_backward_workspace_size", "cqc_batch_backward_create", "cqc_batch_backward_run",
-    "cqc_batch_backward_destroy", "cqc_build_entries", "cqc_chi2", "cqc_xent_grad",
+    "cqc_batch_backward_destroy", "cqc_build_entries", "cqc_chi2", "cqc_xent_grad", "cqc_tune_reset",
 ]
 
 
@@ -102,6 +102,7 @@ def lib():
     L.cqc_build_entries.argtypes = [P(CqcEntryJob), i32, ctypes.c_int, ctypes.c_int, vp]
     L.cqc_chi2.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, i64, vp, vp, sz, vp]
     L.cqc_xent_grad.argtypes = [vp, vp, ctypes.c_int, i64, vp, vp, vp, sz, vp]
+    L.cqc_tune_reset.argtypes = []
     for name in EXPORTS:
         f = getattr(L, name)
         if f.restype is None or f.restype is ctypes.c_int:

@@ -225,4 +225,12 @@ int cqc_autotune(const cqc_instance *inst, int32_t n_inst, cqc_dtype in_t, cqc_d
   return CQC_OK;
 }
 
+int cqc_tune_reset(void) {
+  Cache &c = cache();
+  std::lock_guard<std::mutex> g(c.mu);
+  c.map.clear();
+  c.loaded = false;
+  return CQC_OK;
+}
+
 }  // extern "C"

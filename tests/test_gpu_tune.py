@@ -1,0 +1,98 @@
+"""The project's tile autotuner: tuned plans stay correct, the shape-class
+cache round-trips through the CQC_TUNE_CACHE file, and a cache entry really
+changes the kernel the planner launches."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import fd, metrics
+from tests.gpu_util import to_dev, oracle_inputs, abs_bound, elementwise_ok, sum_terms, U32
+
+pytestmark = pytest.mark.gpu
+cqc = pytest.importorskip("paper_2012_02333_amd")
+
+# key fields of a cache line: acc (0 = FP32), mode (1 = blocked final),
+# small (<= 16 terms), log2 M, log2 N, shared cuts, FP64 output; then tile
+# (0 64x256, 1 32x128, 2 16x64, 3 256x16, 4 wide), XCD remap, microseconds
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture
+def tune_env(tmp_path):
+    old = os.environ.get("CQC_TUNE_CACHE")
+    path = str(tmp_path / "tune.txt")
+    os.environ["CQC_TUNE_CACHE"] = path
+    cqc.tune_reset()
+    yield path
+    if old is None:
+        del os.environ["CQC_TUNE_CACHE"]
+    else:
+        os.environ["CQC_TUNE_CACHE"] = old
+    cqc.tune_reset()
+
+
+def _check(p, host, wcut, xs=None):
+    e64 = oracle_inputs(host)
+    ref = fd.reconstruct(e64, wcut, xs)
+    got = p.double().cpu().numpy() if xs is None else p[torch.from_numpy(xs).cuda()].double().cpu().numpy()
+    ok, info = elementwise_ok(got, ref, abs_bound(e64, wcut, xs), U32, sum_terms("fp32", 4 ** wcut.n_cuts))
+    assert ok, info
+    return metrics.rel_l1(got, ref)
+
+
+def test_autotuned_chain_stays_correct(tune_env):
+    """n=23, three subcircuits, 4096 terms (a wide-kernel step): tune, then
+    check sampled outputs and bitwise repeatability; the cache file holds a
+    valid line for every tuned shape class."""
+    _gpu()
+    inst = W.make_instance((6, 5, 6), (3, 3), 6, seed=82)
+    host, dev = to_dev(inst.entries, torch.float32)
+    cut = cqc.CutMap.from_workload(inst.cut)
+    call = cqc.FDCall(dev, cut, precision="fp32")
+    cqc.autotune(call)
+    call.run()
+    a = call.outs[0].clone()
+    call.run()
+    assert torch.equal(a, call.outs[0])
+    xs = W.sample_outputs(inst.n, 2048, seed=83)
+    assert _check(a, host, inst.cut, xs) <= 1e-6
+    lines = [l.split() for l in open(tune_env).read().splitlines() if l.strip()]
+    assert len(lines) >= 2
+    for f in lines:
+        assert len(f) == 10
+        assert 0 <= int(f[7]) <= 4 and int(f[8]) in (0, 1) and float(f[9]) > 0
+    # a fresh load of the file gives the same plan and output
+    cqc.tune_reset()
+    call.run()
+    assert torch.equal(a, call.outs[0])
+
+
+def test_cache_entry_changes_the_kernel(tune_env):
+    """f = (7, 9), two cuts: by default the two-tile strip kernel; a cache line
+    for its shape class naming the 16 x 64 tile makes the planner launch that
+    one instead, with a correct result either way."""
+    _gpu()
+    inst = W.make_instance((7, 7), (2,), 6, seed=84)
+    assert list(inst.cut.f) == [7, 9]
+    host, dev = to_dev(inst.entries, torch.float32)
+    cut = cqc.CutMap.from_workload(inst.cut)
+    with cqc.trace() as tr:
+        p, _ = cqc.reconstruct_fd(dev, cut, precision="fp32")
+        torch.cuda.synchronize()
+    assert any(k.startswith("contract_small_strip") for k in tr.result), list(tr.result)
+    _check(p, host, inst.cut)
+    with open(tune_env, "w") as fh:
+        fh.write("0 1 1 7 9 2 0 2 0 1.000\n")
+    cqc.tune_reset()
+    with cqc.trace() as tr:
+        q, _ = cqc.reconstruct_fd(dev, cut, precision="fp32")
+        torch.cuda.synchronize()
+    assert "contract_small_16x64" in tr.result and not any(k.startswith("contract_small_strip") for k in tr.result)
+    _check(q, host, inst.cut)
