@@ -180,6 +180,53 @@ static Status build_dd(const cqc_instance *inst, cqc_dtype in_t, cqc_precision p
 }
 
 namespace {
+// Page-locked host buffers for the per-round read-back of the selected bins:
+// a device-to-host copy into pinned memory goes straight to its destination,
+// without the runtime's staging copy for pageable memory.  One buffer per
+// concurrent query, taken from a process-wide free list and returned when
+// the query ends; the buffers are kept until the process exits.
+class PinnedSlots {
+ public:
+  PinnedSlots() {
+    {
+      std::lock_guard<std::mutex> g(mu());
+      if (!pool().empty()) {
+        p_ = pool().back();
+        pool().pop_back();
+        return;
+      }
+    }
+    void *v = nullptr;
+    if (hipHostMalloc(&v, sizeof(DdSlot) * kDdMaxPerRound, hipHostMallocDefault) == hipSuccess) {
+      p_ = static_cast<DdSlot *>(v);
+    } else {
+      (void)hipGetLastError();
+      fallback_.resize(kDdMaxPerRound);   // pageable: slower read-back, same results
+    }
+  }
+  ~PinnedSlots() {
+    if (!p_) return;
+    std::lock_guard<std::mutex> g(mu());
+    pool().push_back(p_);
+  }
+  PinnedSlots(const PinnedSlots &) = delete;
+  PinnedSlots &operator=(const PinnedSlots &) = delete;
+  DdSlot &operator[](size_t i) { return p_ ? p_[i] : fallback_[i]; }
+  DdSlot *data() { return p_ ? p_ : fallback_.data(); }
+
+ private:
+  static std::mutex &mu() {
+    static std::mutex m;
+    return m;
+  }
+  static std::vector<DdSlot *> &pool() {
+    static auto *v = new std::vector<DdSlot *>();   // never destroyed: used until exit
+    return *v;
+  }
+  DdSlot *p_ = nullptr;
+  std::vector<DdSlot> fallback_;
+};
+
 struct RecState {
   int depth = 0;
   int round = 0;
@@ -280,7 +327,7 @@ int cqc_reconstruct_dd(const cqc_instance *inst, cqc_dtype in_t, cqc_precision p
   char *bins = static_cast<char *>(bins_v);
   auto bin_row = [&](int64_t r) { return bins + (size_t)r * (size_t)stride * bin_size; };
   DdSlot *dev_slots = reinterpret_cast<DdSlot *>(ws + d.out_off);
-  std::vector<DdSlot> host_slots(d.per_round);
+  PinnedSlots host_slots;   // d.per_round <= kDdMaxPerRound slots
   std::vector<RecState> recs;
   *n_done = 0;
 

@@ -169,7 +169,10 @@ Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &en
     const bool od = last ? out_double : L.acc == Acc::F64;
     const Acc sa = step_acc(L.acc, st.wide_ok(), (int)st.S.size());
     int cfg = L.tile[i], xcd = 0;
-    if (!tuned_choice(sa, mode, a.nS <= 2, st.logM, st.logN, a.nS, od, &cfg, &xcd) || !tile_ok(sa, cfg)) {
+    // a cached choice is keyed by shape class, which does not fix the operand
+    // heights: the wide tile also needs this step's operands to fit it
+    if (!tuned_choice(sa, mode, a.nS <= 2, st.logM, st.logN, a.nS, od, &cfg, &xcd) || !tile_ok(sa, cfg) ||
+        (cfg == kTileW && !st.wide_ok())) {
       cfg = L.tile[i];
       // the wide kernel's tiles of one operand row block share that block's
       // operand columns: keep them on one XCD (and its L2)

@@ -144,9 +144,16 @@ static Status tune_step(const NetLayout &L, size_t si, char *ws, const std::vect
   const Acc sa = step_acc(L.acc, st.wide_ok(), (int)st.S.size());
   const int64_t work = (int64_t(1) << (st.logM + st.logN)) * st.nbatch;
   const int reps = work >= (int64_t(1) << 24) ? 10 : 30;
-  hipEvent_t e0, e1;
-  CQC_HIP_TRY(hipEventCreate(&e0));
-  CQC_HIP_TRY(hipEventCreate(&e1));
+  struct Events {  // destroyed on every return path
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Events() {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+    }
+  } ev;
+  CQC_HIP_TRY(hipEventCreate(&ev.e0));
+  CQC_HIP_TRY(hipEventCreate(&ev.e1));
+  hipEvent_t e0 = ev.e0, e1 = ev.e1;
   Choice best{-1, 0, 1e30};
   for (int cfg = 0; cfg < kTileCount; ++cfg) {
     if (!tile_ok(sa, cfg)) continue;
@@ -175,8 +182,6 @@ static Status tune_step(const NetLayout &L, size_t si, char *ws, const std::vect
       if (us < best.us) best = Choice{cfg, xcd, us};
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   if (best.cfg >= 0)
     record(Key((int)sa, a.mode, (int)(a.nS <= 2), st.logM, st.logN, a.nS, (int)od), best);
   return Status::ok();

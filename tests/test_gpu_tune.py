@@ -96,3 +96,28 @@ def test_cache_entry_changes_the_kernel(tune_env):
         torch.cuda.synchronize()
     assert "contract_small_16x64" in tr.result and not any(k.startswith("contract_small_strip") for k in tr.result)
     _check(q, host, inst.cut)
+
+
+def test_wide_entry_skipped_where_operands_do_not_fit(tune_env):
+    """A cache line names the wide tile for a shape class; a step of that class
+    whose operand has a single column (a subcircuit without output qubits)
+    cannot run the wide kernel, so the planner keeps its built-in tile and the
+    result is still the oracle's."""
+    _gpu()
+    cut = W.CutMap(9, [0, 9], [0], [1], list(range(9)))
+    rng = np.random.default_rng(85)
+    host = [rng.standard_normal((4, 1)), rng.standard_normal((4, 2 ** 9))]
+    dev = [torch.from_numpy(e).float().cuda() for e in host]
+    with open(tune_env, "w") as fh:
+        for mode in (1, 2):
+            for lm, ln in ((0, 9), (9, 0)):
+                fh.write(f"0 {mode} 1 {lm} {ln} 1 0 4 0 1.000\n")
+    cqc.tune_reset()
+    with cqc.trace() as tr:
+        p, _ = cqc.reconstruct_fd(dev, cqc.CutMap.from_workload(cut), precision="fp32")
+        torch.cuda.synchronize()
+    assert not any("wide" in k for k in tr.result), list(tr.result)
+    e64 = [np.asarray(e, dtype=np.float32).astype(np.float64) for e in host]
+    ref = fd.reconstruct(e64, cut)
+    ok, info = elementwise_ok(p.double().cpu().numpy(), ref, abs_bound(e64, cut), U32, sum_terms("fp32", 4))
+    assert ok, info
