@@ -268,6 +268,7 @@ size_t topk_scratch_bytes(int64_t count, int t) {
 
 Status launch_topk(const void *bins, bool bins_f32, int64_t count, int t, void *scratch, TopOut *out,
                    double after_v, int64_t after_i, hipStream_t s) {
+  if (count < 1) return Status::fail(CQC_ERR_INVALID_ARG, "top-k over no bins");
   const int64_t blocks = std::min<int64_t>(1024, (count + 2047) / 2048);
   const int64_t per_block = (count + blocks - 1) / blocks;
   if (t < 1 || t > kTopT) return Status::fail(CQC_ERR_INVALID_ARG, "top-k count out of range");
