@@ -148,31 +148,48 @@ __device__ __forceinline__ void push_cand(Cand (&m)[kTopT], Cand c) {
   }
 }
 
-// Block-wide best kTopT of the per-thread rankings: kTopT rounds of a wave
-// argmax (shuffles) and a combine of the NW wave winners in LDS; the thread holding the
-// winner pops it.  Bin indices are unique, so exactly one thread pops.
+// Block-wide best kTopT of the per-thread rankings, in kTopT rounds.  A round
+// finds each wave's winner - the largest head value by a butterfly over values
+// only, then the lowest index among the lanes holding it (one lane in the
+// usual case, read directly) - and combines the NW wave winners in LDS; the
+// thread holding the overall winner pops it.  Bin indices are unique, so
+// exactly one thread pops.  The wave winners alternate between two LDS rows,
+// so one barrier per round suffices: a wave can only rewrite a row after the
+// next round's barrier, which every wave reaches after reading that row.
 template <int NW>
 __device__ __forceinline__ void block_top(Cand (&m)[kTopT], Cand *out) {
-  __shared__ Cand wbest[NW];
+  __shared__ Cand wbest[2][NW];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll 1
   for (int k = 0; k < kTopT; ++k) {
-    Cand c = m[0];
+    double mv = m[0].v;   // keys are never NaN
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
-      const double xv = __shfl_xor(c.v, o, 64);
-      const int64_t xi = (int64_t)__shfl_xor((long long)c.i, o, 64);
-      const bool b = xv > c.v || (xv == c.v && xi < c.i);
-      c.v = b ? xv : c.v;
-      c.i = b ? xi : c.i;
+      const double x = __shfl_xor(mv, o, 64);
+      mv = x > mv ? x : mv;
     }
-    if (lane == 0) wbest[wave] = c;
+    const bool hold = m[0].v == mv;
+    const unsigned long long hit = __ballot(hold);   // never empty
+    Cand c;
+    c.v = mv;
+    if (__popcll(hit) == 1) {
+      c.i = __shfl(m[0].i, __ffsll((long long)hit) - 1, 64);
+    } else {
+      int64_t ci = hold ? m[0].i : INT64_MAX;
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        const int64_t x = (int64_t)__shfl_xor((long long)ci, o, 64);
+        ci = x < ci ? x : ci;
+      }
+      c.i = ci;
+    }
+    Cand *wb = wbest[k & 1];
+    if (lane == 0) wb[wave] = c;
     __syncthreads();
-    Cand w = wbest[0];
+    Cand w = wb[0];
 #pragma unroll
     for (int j = 1; j < NW; ++j)
-      if (better(wbest[j], w)) w = wbest[j];
-    __syncthreads();
+      if (better(wb[j], w)) w = wb[j];
     if (threadIdx.x == 0) out[k] = w;
     if (w.i != INT64_MAX && m[0].i == w.i) {
 #pragma unroll
