@@ -135,6 +135,7 @@ constexpr Cand kNoCand{-__builtin_inf(), INT64_MAX};
 // registers: every index is a compile-time constant, and a new candidate
 // bubbles down the list by branch-free compare-and-swap.
 __device__ __forceinline__ void push_cand(Cand (&m)[kTopT], Cand c) {
+  if (!better(c, m[kTopT - 1])) return;   // cannot enter the list (a whole wave skips)
 #pragma unroll
   for (int k = 0; k < kTopT; ++k) {
     // selects on values, not on references, so the list stays in registers
@@ -245,7 +246,8 @@ __global__ __launch_bounds__(1024) void k_topk_stage2(const Cand *partial, int64
     v[u] = i < count ? partial[i] : kNoCand;
   }
 #pragma unroll
-  for (int u = 0; u < 8; ++u) push_cand(m, v[u]);
+  for (int u = 0; u < 8; ++u)
+    if (u * 1024 + (int64_t)threadIdx.x < count) push_cand(m, v[u]);
   block_top<16>(m, res);
   __syncthreads();
   if ((int)threadIdx.x < t) {
