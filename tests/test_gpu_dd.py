@@ -253,3 +253,32 @@ def test_dd_strategy_arguments():
     with pytest.raises(cqc.CqcError) as e:
         cqc.reconstruct_dd(dev, cut, 2, 2, bins_per_round=65)
     assert e.value.code == 1
+
+
+@pytest.mark.parametrize("strategy,per_round", [("heaviest", 1), ("heaviest", 4), ("dfs", 1), ("dfs", 4),
+                                                ("bfs", 1)])
+@pytest.mark.parametrize("prec,dtype", [("fp64", torch.float64), ("fp32", torch.float32)])
+def test_dd_exact_ties_go_to_lowest_index(strategy, per_round, prec, dtype):
+    """A uniform distribution (only the all-identity row is non-zero, every
+    entry 1): all 4096 first-recursion bins tie exactly, so every ranking -
+    within a thread, across a wave, across blocks and after a refill of the
+    candidate list - must order them by index, and the records are exactly
+    the oracle's own, bins included."""
+    _gpu()
+    cut = W.CutMap(16, [8, 8], [0], [1], list(range(16)))
+    ents = [np.zeros((4, 256)), np.zeros((4, 256))]
+    ents[0][0] = 1.0
+    ents[1][0] = 1.0
+    a, R = 12, 12                      # eleven picks: more than one top-8 list
+    host, dev = to_dev(ents, dtype)
+    bins, recs = cqc.reconstruct_dd(dev, cqc.CutMap.from_workload(cut), a, R, precision=prec,
+                                    strategy=strategy, bins_per_round=per_round)
+    bins = bins.cpu().numpy()
+    ref = dd.reconstruct(oracle_inputs(host), cut, a, R, strategy=strategy, per_round=per_round)
+    assert [tuple(r["parent"]) for r in recs] == [r["parent"] for r in ref]
+    assert [tuple(r["parent"]) for r in recs][1:4] == [(0, 0), (0, 1), (0, 2)]
+    for r, (g, o) in enumerate(zip(recs, ref)):
+        assert g["role"] == o["role"], r
+        nb = 2 ** g["n_active"]
+        assert np.array_equal(bins[r, :nb], o["bins"]), r
+        assert g["mass"] == o["bins"].sum(), r
