@@ -231,24 +231,26 @@ __global__ __launch_bounds__(256) void k_topk_stage1(const B *bins, int64_t coun
   block_top<4>(m, partial + (int64_t)blockIdx.x * kTopT);
 }
 
-// Stage 2: one block of 1024 threads ranks all stage-1 candidates (at most
-// 1024 blocks x kTopT: eight per thread, all loaded before ranking) and
-// writes the best t.
-__global__ __launch_bounds__(1024) void k_topk_stage2(const Cand *partial, int64_t count, int t, TopOut *out) {
+// Stage 2: one block of 256 threads ranks all stage-1 candidates (at most
+// 1024 blocks x kTopT), eight loads in flight per thread at a time, and
+// writes the best t.  Four waves keep the block-wide rounds cheap.
+__global__ __launch_bounds__(256) void k_topk_stage2(const Cand *partial, int64_t count, int t, TopOut *out) {
   __shared__ Cand res[kTopT];
   Cand m[kTopT];
 #pragma unroll
   for (int k = 0; k < kTopT; ++k) m[k] = kNoCand;
-  Cand v[8];
+  for (int64_t c0 = 0; c0 < count; c0 += 8 * 256) {
+    Cand v[8];
 #pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    const int64_t i = u * 1024 + threadIdx.x;
-    v[u] = i < count ? partial[i] : kNoCand;
+    for (int u = 0; u < 8; ++u) {
+      const int64_t i = c0 + u * 256 + threadIdx.x;
+      v[u] = i < count ? partial[i] : kNoCand;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (c0 + u * 256 + (int64_t)threadIdx.x < count) push_cand(m, v[u]);
   }
-#pragma unroll
-  for (int u = 0; u < 8; ++u)
-    if (u * 1024 + (int64_t)threadIdx.x < count) push_cand(m, v[u]);
-  block_top<16>(m, res);
+  block_top<4>(m, res);
   __syncthreads();
   if ((int)threadIdx.x < t) {
     out->value[threadIdx.x] = res[threadIdx.x].v;
@@ -298,8 +300,7 @@ Status launch_topk(const void *bins, bool bins_f32, int64_t count, int t, void *
   else
     CQC_TRY(launch("topk_stage1", k_topk_stage1<double>, dim3((unsigned)blocks), dim3(256), 0, s,
                    static_cast<const double *>(bins), count, per_block, partial, after_v, after_i));
-  static_assert(1024 * kTopT <= 8 * 1024, "stage 2 holds eight candidates per thread");
-  return launch("topk_stage2", k_topk_stage2, dim3(1), dim3(1024), 0, s, static_cast<const Cand *>(partial),
+  return launch("topk_stage2", k_topk_stage2, dim3(1), dim3(256), 0, s, static_cast<const Cand *>(partial),
                 blocks * kTopT, t, out);
 }
 
