@@ -131,22 +131,43 @@ __device__ __forceinline__ double key(double v) { return v != v ? -__builtin_inf
 
 constexpr Cand kNoCand{-__builtin_inf(), INT64_MAX};
 
-// Per-thread ranking of the best kTopT candidates seen, best first, kept in
-// registers: every index is a compile-time constant, and a new candidate
-// bubbles down the list by branch-free compare-and-swap.
-__device__ __forceinline__ void push_cand(Cand (&m)[kTopT], Cand c) {
-  if (!better(c, m[kTopT - 1])) return;   // cannot enter the list (a whole wave skips)
-#pragma unroll
-  for (int k = 0; k < kTopT; ++k) {
-    // selects on values, not on references, so the list stays in registers
-    const double mv = m[k].v, cv = c.v;
-    const int64_t mi = m[k].i, ci = c.i;
-    const bool b = cv > mv || (cv == mv && ci < mi);
-    m[k].v = b ? cv : mv;
-    m[k].i = b ? ci : mi;
-    c.v = b ? mv : cv;
-    c.i = b ? mi : ci;
-  }
+// Eight candidates at a time: compare-and-swap (better first) on values,
+// a 19-exchange sorting network for eight, and the best eight of two sorted
+// lists by one bitonic step (elementwise best of one list and the other
+// reversed) plus a bitonic sort - 39 exchanges per eight candidates where
+// eight insertions into a full list take 64.
+static_assert(kTopT == 8, "the sorting network and merge are for eight");
+__device__ __forceinline__ void cas(Cand &a, Cand &b) {
+  const bool s = better(b, a);
+  const double av = a.v, bv = b.v;
+  const int64_t ai = a.i, bi = b.i;
+  a.v = s ? bv : av;
+  a.i = s ? bi : ai;
+  b.v = s ? av : bv;
+  b.i = s ? ai : bi;
+}
+__device__ __forceinline__ void sort8(Cand (&c)[8]) {
+  cas(c[0], c[2]); cas(c[1], c[3]); cas(c[4], c[6]); cas(c[5], c[7]);
+  cas(c[0], c[4]); cas(c[1], c[5]); cas(c[2], c[6]); cas(c[3], c[7]);
+  cas(c[0], c[1]); cas(c[2], c[3]); cas(c[4], c[5]); cas(c[6], c[7]);
+  cas(c[2], c[4]); cas(c[3], c[5]);
+  cas(c[1], c[4]); cas(c[3], c[6]);
+  cas(c[1], c[2]); cas(c[3], c[4]); cas(c[5], c[6]);
+}
+// m and c sorted best first; m becomes the best eight of both, sorted
+__device__ __forceinline__ void keep_better(Cand &a, const Cand &b) {
+  const bool s = better(b, a);
+  const double av = a.v, bv = b.v;
+  const int64_t ai = a.i, bi = b.i;
+  a.v = s ? bv : av;
+  a.i = s ? bi : ai;
+}
+__device__ __forceinline__ void merge8(Cand (&m)[kTopT], Cand (&c)[8]) {
+  keep_better(m[0], c[7]); keep_better(m[1], c[6]); keep_better(m[2], c[5]); keep_better(m[3], c[4]);
+  keep_better(m[4], c[3]); keep_better(m[5], c[2]); keep_better(m[6], c[1]); keep_better(m[7], c[0]);
+  cas(m[0], m[4]); cas(m[1], m[5]); cas(m[2], m[6]); cas(m[3], m[7]);
+  cas(m[0], m[2]); cas(m[1], m[3]); cas(m[4], m[6]); cas(m[5], m[7]);
+  cas(m[0], m[1]); cas(m[2], m[3]); cas(m[4], m[5]); cas(m[6], m[7]);
 }
 
 // Block-wide best kTopT of the per-thread rankings, in kTopT rounds.  A round
@@ -221,12 +242,17 @@ __global__ __launch_bounds__(256) void k_topk_stage1(const B *bins, int64_t coun
       const int64_t i = c0 + u * 256 + threadIdx.x;
       v[u] = i < b1 ? (double)bins[i] : 0.0;
     }
+    Cand c[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int64_t i = c0 + u * 256 + threadIdx.x;
-      const Cand c{key(v[u]), i};
-      if (i < b1 && better(after, c)) push_cand(m, c);
+      const Cand x{key(v[u]), i};
+      const bool ok = i < b1 && better(after, x);   // selects on values: the lists stay in registers
+      c[u].v = ok ? x.v : kNoCand.v;
+      c[u].i = ok ? x.i : kNoCand.i;
     }
+    sort8(c);
+    merge8(m, c);
   }
   block_top<4>(m, partial + (int64_t)blockIdx.x * kTopT);
 }
@@ -246,9 +272,8 @@ __global__ __launch_bounds__(256) void k_topk_stage2(const Cand *partial, int64_
       const int64_t i = c0 + u * 256 + threadIdx.x;
       v[u] = i < count ? partial[i] : kNoCand;
     }
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (c0 + u * 256 + (int64_t)threadIdx.x < count) push_cand(m, v[u]);
+    sort8(v);
+    merge8(m, v);
   }
   block_top<4>(m, res);
   __syncthreads();
