@@ -189,7 +189,7 @@ def test_heaviest_multi_bin_round():
     m2 = _prefix_masses(p, n, 2)
     top = sorted(range(4), key=lambda b: (-m2[b], b))
     assert [r["parent"] for r in recs[1:3]] == [(0, top[0]), (0, top[1])]
-    # round 2: the two heaviest of {the remaining first-recursion bins} and
+    # the second expansion round: the two heaviest of {the remaining first-recursion bins} and
     # {the depth-2 bins under top[0], top[1]}, all as brute-force masses
     m4 = _prefix_masses(p, n, 4)
     pool = [(m2[b], 0, b) for b in top[2:]] + [(m4[4 * top[j] + b], 1 + j, b) for j in range(2) for b in range(4)]
