@@ -282,3 +282,40 @@ def test_dd_exact_ties_go_to_lowest_index(strategy, per_round, prec, dtype):
         nb = 2 ** g["n_active"]
         assert np.array_equal(bins[r, :nb], o["bins"]), r
         assert g["mass"] == o["bins"].sum(), r
+
+
+def test_dd_concurrent_queries_on_two_streams():
+    """Two host threads run DD queries at once, each on its own stream: the
+    shared plan cache and the pool of page-locked read-back buffers serve both,
+    and every query returns the records of a query run alone."""
+    import threading
+    _gpu()
+    inst = W.make_instance((3, 2, 3), (2, 2), 6, seed=31)
+    host, dev = to_dev(inst.entries, torch.float32)
+    cut = cqc.CutMap.from_workload(inst.cut)
+    ref_bins, ref_recs = cqc.reconstruct_dd(dev, cut, 3, 9, precision="fp32", bins_per_round=2)
+    ref_bins = ref_bins.cpu()
+    results, errors = [[], []], []
+
+    def worker(k):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                for _ in range(6):
+                    b, r = cqc.reconstruct_dd(dev, cut, 3, 9, precision="fp32", bins_per_round=2)
+                    s.synchronize()
+                    results[k].append((b.cpu(), r))
+        except Exception as e:          # reported below, in the main thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=worker, args=(k,)) for k in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    for k in range(2):
+        assert len(results[k]) == 6
+        for b, r in results[k]:
+            assert torch.equal(b, ref_bins)
+            assert [(g["parent"], g["mass"]) for g in r] == [(g["parent"], g["mass"]) for g in ref_recs]
