@@ -22,11 +22,14 @@ namespace cqc {
 constexpr int kXentMaxBlocks = 1024;
 constexpr double kXentFloor = 1e-30;
 
+typedef float xf4 __attribute__((ext_vector_type(4)));
+
+// every element is touched once: non-temporal loads and stores
 template <bool VEC, typename T>
 __device__ __forceinline__ void xload4(const T *p, int64_t i, T (&v)[4]) {
   if constexpr (VEC && sizeof(T) == 4) {
-    const float4 q = *reinterpret_cast<const float4 *>(p + i);
-    v[0] = q.x, v[1] = q.y, v[2] = q.z, v[3] = q.w;
+    const xf4 q = __builtin_nontemporal_load(reinterpret_cast<const xf4 *>(p + i));
+    v[0] = q[0], v[1] = q[1], v[2] = q[2], v[3] = q[3];
   } else {
 #pragma unroll
     for (int k = 0; k < 4; ++k) v[k] = p[i + k];
@@ -36,7 +39,7 @@ __device__ __forceinline__ void xload4(const T *p, int64_t i, T (&v)[4]) {
 template <bool VEC, typename T>
 __device__ __forceinline__ void xstore4(T *p, int64_t i, const T (&v)[4]) {
   if constexpr (VEC && sizeof(T) == 4) {
-    *reinterpret_cast<float4 *>(p + i) = make_float4(v[0], v[1], v[2], v[3]);
+    __builtin_nontemporal_store(xf4{v[0], v[1], v[2], v[3]}, reinterpret_cast<xf4 *>(p + i));
   } else {
 #pragma unroll
     for (int k = 0; k < 4; ++k) p[i + k] = v[k];
