@@ -18,11 +18,14 @@ namespace cqc {
 
 constexpr int kChi2MaxBlocks = 1024;
 
+typedef float cf4 __attribute__((ext_vector_type(4)));
+
+// every element is read once: non-temporal loads for the FP32 stream
 template <bool VEC, typename T>
 __device__ __forceinline__ void load4(const T *p, int64_t i, double (&v)[4]) {
   if constexpr (VEC && sizeof(T) == 4) {
-    const float4 q = *reinterpret_cast<const float4 *>(p + i);
-    v[0] = q.x, v[1] = q.y, v[2] = q.z, v[3] = q.w;
+    const cf4 q = __builtin_nontemporal_load(reinterpret_cast<const cf4 *>(p + i));
+    v[0] = q[0], v[1] = q[1], v[2] = q[2], v[3] = q[3];
   } else if constexpr (VEC) {
     const double2 q0 = *reinterpret_cast<const double2 *>(p + i);
     const double2 q1 = *reinterpret_cast<const double2 *>(p + i + 2);
