@@ -16,8 +16,13 @@ follows):
                Section 3.3: 4^K Kronecker products scaled by 2^-K) and the
                Eq. 14 cost model
   dd           dynamic definition (Algorithm 1, Section 4.3)
+  blocked      full FD vectors in bounded memory (2^30 outputs): the same
+               definition with each label summed as soon as both of its
+               subcircuits are multiplied in (distributivity; the progressive
+               build Eq. 14 counts), one output block at a time
   adjoint      gradient of a loss on the reconstructed distribution with
-               respect to every entry tensor, by its plain definition
+               respect to every entry tensor, by its plain definition, over
+               the whole tensor (vjp) or at chosen elements (vjp_at)
   metrics      relative L1, chi^2 (Eq. 16), cancellation factor kappa
   native       C/OpenMP twin of the FD definition, used for CPU timing
 

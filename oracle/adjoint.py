@@ -51,3 +51,43 @@ def cross_entropy_grad(p, t):
     live = p > CE_FLOOR
     g[live] = -t[live] / p[live]
     return g
+
+
+def vjp_at(entries, cut, G, c, elems):
+    """dL/dE_c[r, y] at the (r, y) pairs in `elems`, by the same plain definition
+    as vjp: for each pair, the labels l with row_c(l) = r in ascending order,
+    and for each l the outputs x with x_c = y (the other qubits enumerated in
+    ascending global order) weighted by G[x] and the other factors.
+
+    Costs 4^(K - k_c) * 2^(n - f_c) products per element, so single entries of
+    large instances (n = 24) can be checked without the full vjp.
+    """
+    n, K = cut.n, cut.n_cuts
+    ents = [np.asarray(E, dtype=np.float64) for E in entries]
+    G = np.asarray(G, dtype=np.float64)
+    qs = cut.out_qubits_of(c)
+    others = [q for q in range(n) if q not in qs]
+    j = np.arange(2 ** len(others), dtype=np.int64)
+    free = np.zeros_like(j)
+    for t, q in enumerate(others):
+        free |= ((j >> (len(others) - 1 - t)) & 1) << (n - 1 - q)
+    out = np.empty(len(elems), dtype=np.float64)
+    for i, (r, y) in enumerate(elems):
+        fixed = 0
+        for t, q in enumerate(qs):
+            fixed |= ((int(y) >> (len(qs) - 1 - t)) & 1) << (n - 1 - q)
+        xs = free | fixed
+        g = G[xs]
+        xcs = [_fd.local_index(cut, c2, xs) for c2 in range(cut.n_sub)]
+        acc = 0.0
+        for l in range(4 ** K):
+            d = _fd.label_digits(l, K)
+            if _fd.row_of(cut, c, d) != int(r):
+                continue
+            prod = g.copy()
+            for c2 in range(cut.n_sub):
+                if c2 != c:
+                    prod = prod * ents[c2][_fd.row_of(cut, c2, d)][xcs[c2]]
+            acc += float(np.sum(prod))
+        out[i] = acc * (2.0 ** -K)
+    return out

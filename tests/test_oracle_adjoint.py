@@ -66,3 +66,40 @@ def test_cross_entropy_floor():
     g = adjoint.cross_entropy_grad(p, t)
     assert np.array_equal(g, [-0.5, 0.0, 0.0, -0.5])
     assert abs(adjoint.cross_entropy(p, t) - (-0.5 * np.log(0.5) - 0.5 * np.log(1e-30))) < 1e-12
+
+
+@pytest.mark.parametrize("own,bridges,layers", [((3, 3), (2,), 4), ((2, 3, 2), (2, 1), 4),
+                                                ((2, 2, 2, 2), (1, 1, 1), 4)])
+def test_vjp_at_equals_vjp(own, bridges, layers):
+    inst = W.make_instance(own, bridges, layers, seed=6)
+    G = np.random.default_rng(3).standard_normal(2 ** inst.n)
+    grads = adjoint.vjp(inst.entries, inst.cut, G)
+    rng = np.random.default_rng(9)
+    for c, E in enumerate(inst.entries):
+        elems = [(int(rng.integers(E.shape[0])), int(rng.integers(E.shape[1]))) for _ in range(12)]
+        got = adjoint.vjp_at(inst.entries, inst.cut, G, c, elems)
+        ref = np.array([grads[c][r, y] for r, y in elems])
+        scale = np.max(np.abs(grads[c]))
+        assert np.max(np.abs(got - ref)) <= 1e-13 * scale
+
+
+def test_vjp_at_closed_form_permuted_order():
+    # n_C = 2: dE_A = 2^-K B G^T and dE_B = 2^-K A G, with G laid out in the
+    # local (x_A, x_B) order after undoing a scattered global output order
+    K = 2
+    perm = [3, 0, 5, 1, 4, 2]
+    cut = W.CutMap(n=6, f=[2, 4], edge_up=[0] * K, edge_down=[1] * K, out_qubit=perm)
+    A, B = W.random_entries(cut, seed=7)
+    G = np.random.default_rng(8).standard_normal(2 ** 6)
+    # local index (x_A, x_B) -> global index
+    loc = np.arange(64)
+    glob = np.zeros(64, dtype=np.int64)
+    for j, q in enumerate(perm):
+        glob |= ((loc >> (5 - j)) & 1) << (5 - q)
+    Gl = G[glob].reshape(4, 16)
+    gA = (2.0 ** -K) * (B @ Gl.T)
+    gB = (2.0 ** -K) * (A @ Gl)
+    elems_a = [(r, y) for r in range(16) for y in range(4)]
+    elems_b = [(r, y) for r in (0, 5, 15) for y in range(16)]
+    assert np.max(np.abs(adjoint.vjp_at([A, B], cut, G, 0, elems_a) - [gA[r, y] for r, y in elems_a])) < 1e-15
+    assert np.max(np.abs(adjoint.vjp_at([A, B], cut, G, 1, elems_b) - [gB[r, y] for r, y in elems_b])) < 1e-15

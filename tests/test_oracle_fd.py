@@ -131,3 +131,50 @@ def test_metrics_closed_forms():
     ents = [np.abs(E) for E in W.random_entries(cut, seed=3)]
     p = fd.reconstruct(ents, cut)
     assert abs(metrics.kappa(ents, cut, np.abs(p).sum()) - 1.0) < 1e-14
+
+
+def test_rel_l2_closed_forms():
+    ref = np.array([3.0, 4.0])
+    assert abs(metrics.rel_l2(ref + np.array([0.3, -0.4]), ref) - 0.1) < 1e-15
+    assert abs(metrics.rel_l2(ref * (1 + 1e-3), ref) - 1e-3) < 1e-15
+    # normalised by the second argument, not the first
+    assert abs(metrics.rel_l2(np.array([6.0, 8.0]), ref) - 1.0) < 1e-15
+    assert abs(metrics.rel_l2(ref, np.array([6.0, 8.0])) - 0.5) < 1e-15
+    # an orthogonal perturbation adds in quadrature
+    assert abs(metrics.rel_l2(np.array([1.0, 1e-5, 0.0]), np.array([1.0, 0.0, 0.0])) - 1e-5) < 1e-20
+    # a zero reference reports the plain norm
+    assert metrics.rel_l2(np.array([3.0, 4.0]), np.zeros(2)) == 5.0
+
+
+def test_kappa_signed_hand_case():
+    # one cut between two one-qubit subcircuits, signed integer entries:
+    # |A| row sums (3, 3, 1, 4), |B| row sums (2, 3, 5, 1): numerator 24 / 2 = 12;
+    # p = A^T B / 2 = (-1, 4.5, -2, 1.5), sum |p| = 9, so kappa = 4/3
+    cut = W.CutMap(n=2, f=[1, 1], edge_up=[0], edge_down=[1], out_qubit=[0, 1])
+    A = np.array([[1.0, -2.0], [3.0, 0.0], [0.0, -1.0], [2.0, 2.0]])
+    B = np.array([[1.0, 1.0], [-1.0, 2.0], [2.0, -3.0], [0.0, 1.0]])
+    p = fd.reconstruct([A, B], cut)
+    assert np.array_equal(p, [-1.0, 4.5, -2.0, 1.5])
+    assert abs(metrics.kappa([A, B], cut, np.abs(p).sum()) - 4.0 / 3.0) < 1e-15
+
+
+def test_kappa_equals_brute_force_abs_term_sum():
+    # kappa * sum|p| = sum_x sum_l |term(l, x)|, term by term over a signed
+    # three-subcircuit chain with a permuted output order
+    cut = W.CutMap(n=6, f=[2, 2, 2], edge_up=[0, 1, 0], edge_down=[1, 2, 2],
+                   out_qubit=[4, 1, 5, 0, 2, 3])
+    ents = W.random_entries(cut, seed=21)
+    p = fd.reconstruct(ents, cut)
+    tot = 0.0
+    for x in range(2 ** cut.n):
+        xc = [int(fd.local_index(cut, c, np.array([x]))[0]) for c in range(3)]
+        for l in range(4 ** cut.n_cuts):
+            d = fd.label_digits(l, cut.n_cuts)
+            t = 1.0
+            for c in range(3):
+                t *= ents[c][fd.row_of(cut, c, d)][xc[c]]
+            tot += abs(t)
+    tot *= 2.0 ** -cut.n_cuts
+    k = metrics.kappa(ents, cut, np.abs(p).sum())
+    assert abs(k * np.abs(p).sum() - tot) < 1e-13 * tot
+    assert k > 1.5          # signed entries cancel: the abs() matters here
