@@ -3,9 +3,10 @@
 Default workload (the headline metric): n=24 seeded random U3+CZ circuit
 (depth 8) cut by K=2 wires into two 13-qubit subcircuits; entry tensors
 16 x 2^11 and 16 x 2^13 from noiseless simulation; 2^24 output probabilities.
-A step is one complete library call: entry row flags (early termination), the
-term sum on matrix cores, the single write of every output and the FP64 total
-mass.  The FP32 form (metric) and the plain FP64 form run on the same inputs;
+A step is one complete library call: the term sum on matrix cores (all 16
+terms are kept: with at most 16 terms a dead term only adds exact zeros, so no
+row-flag pass runs), the single write of every output with per-tile FP64
+partial sums, and the ordered FP64 total mass.  The FP32 form (metric) and the plain FP64 form run on the same inputs;
 output buffers rotate over >= 1 GiB so the 256 MB last-level cache cannot hold
 the writes.
 

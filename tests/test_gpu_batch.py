@@ -127,3 +127,46 @@ def test_batch_strips_equal_single_calls():
         p1, m1 = cqc.reconstruct_fd(ents[k], cuts[k], precision="fp32")
         assert torch.equal(batch.outs[k], p1), k
         assert abs(float(batch.mass[k]) - float(m1)) <= 1e-12 * max(1.0, abs(float(m1))), k
+
+
+def test_batch_fp32_wide_queue_equals_single_calls():
+    """FP32 instances whose steps reach the persistent wide kernel inside a
+    batch (64 terms over at least 2^22 outputs per step group): two 11-qubit
+    subcircuits with three cuts, and a chain of three whose intermediate and
+    final steps both qualify, next to small instances.  The FP32 wide queue
+    runs; every output equals the one-instance call bit for bit; the wide
+    instances' outputs match the oracle on a sample (relative L1 <= 1e-6 and
+    every element within its rounding bound)."""
+    _gpu()
+    from oracle import native
+    from tests.gpu_util import elementwise_ok, U32
+    C = W.CutMap
+    cuts_w = [C(22, [11, 11], [0, 0, 0], [1, 1, 1], list(range(22))),
+              C(23, [8, 8, 7], [0, 0, 0, 1, 1, 1], [1, 1, 1, 2, 2, 2], list(range(23))),
+              C(12, [6, 6], [0, 0], [1, 1], list(range(12))),
+              C(9, [4, 5], [0, 0, 0], [1, 1, 1], [5, 0, 3, 8, 1, 2, 4, 7, 6]),
+              C(13, [4, 5, 4], [0, 1, 1], [1, 2, 2], list(range(13)))]
+    host = [[E.astype(np.float32) for E in W.random_entries(c, seed=800 + i)] for i, c in enumerate(cuts_w)]
+    ents = [[torch.from_numpy(E).cuda() for E in h] for h in host]
+    cuts = [cqc.CutMap.from_workload(c) for c in cuts_w]
+    batch = cqc.Batch(ents, cuts, precision="fp32")
+    with cqc.trace() as tr:
+        batch.run()
+        torch.cuda.synchronize()
+    assert "wide_f32_queue" in tr.result, tr.result
+    for k in range(len(cuts)):
+        p1, m1 = cqc.reconstruct_fd(ents[k], cuts[k], precision="fp32")
+        torch.cuda.synchronize()
+        assert torch.equal(batch.outs[k], p1), k
+        assert abs(float(batch.mass[k]) - float(m1)) <= 1e-12 * max(1.0, abs(float(m1))), k
+    for k in (0, 1):
+        xs = W.sample_outputs(cuts_w[k].n, 4096, seed=810 + k)
+        got = batch.outs[k][torch.from_numpy(xs).cuda()].double().cpu().numpy()
+        e64 = oracle_inputs(host[k])
+        ref = native.reconstruct(e64, cuts_w[k], xs)
+        T = native.reconstruct([np.abs(E) for E in e64], cuts_w[k], xs)
+        err = metrics.rel_l1(got, ref)
+        print(f"wide queue instance {k}: sampled rel_l1={err:.3e}")
+        assert err <= 1e-6
+        ok, info = elementwise_ok(got, ref, T, U32, 64 + 64)
+        assert ok, (k, info)

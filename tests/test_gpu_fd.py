@@ -162,6 +162,42 @@ def test_fd_c3_sampled(prec):
     del p
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16x6"])
+def test_fd_c3_full_vector(prec):
+    """n=30, K=6, three subcircuits: all 2^30 outputs against the blocked FP64
+    oracle, 16 blocks of 2^26 (each a contiguous range of the global vector),
+    so the relative L1 error is the whole vector's, with every element inside
+    its rounding bound."""
+    _gpu()
+    from oracle import blocked
+    inst = W.config_instance("c3")
+    host, dev = to_dev(inst.entries, torch.float32)
+    cut = cqc.CutMap.from_workload(inst.cut)
+    p, mass = cqc.reconstruct_fd(dev, cut, precision=prec)
+    torch.cuda.synchronize()
+    e64 = oracle_inputs(host)
+    a64 = [np.abs(E) for E in e64]
+    top = 4
+    span = 2 ** (inst.n - top)
+    num = den = 0.0
+    worst = 0.0
+    for b in range(2 ** top):
+        got = p[b * span:(b + 1) * span].cpu().numpy().astype(np.float64)
+        ref = blocked.reconstruct_block(e64, inst.cut, top, b)
+        T = blocked.reconstruct_block(a64, inst.cut, top, b)
+        err = np.abs(got - ref)
+        num += float(err.sum())
+        den += float(np.abs(ref).sum())
+        tol = 4.0 * (sum_terms(prec, 64 + 64) + 2) * U32 * T
+        worst = max(worst, float(np.max(err / tol)))
+    rel = num / den
+    print(f"c3 {prec} full-vector rel_l1={rel:.3e} worst err/bound={worst:.3f} mass={float(mass.cpu())!r}")
+    assert rel <= 1e-6
+    assert worst <= 1.0
+    assert abs(float(mass.cpu()) - 1.0) <= 1e-5
+    del p
+
+
 def test_fd_bitwise_repeatable():
     _gpu()
     inst = W.make_instance((6, 6), (3,), 6, seed=5)
@@ -189,11 +225,11 @@ def test_fd_mixed_dtypes(in_dt, out_dt, prec):
 @pytest.mark.parametrize("prec,shape", [("fp32", ((6, 6), (2,), 6)), ("fp64", ((4, 4), (3,), 6)),
                                         ("bf16x6", ((6, 6), (3,), 6)), ("fp32", ((4, 4), (3,), 6))])
 def test_fd_mass_fresh_across_calls(prec, shape):
-    """The FP64 mass is reduced inside the last contraction (the block that
-    finishes last adds every block's partial) and the ticket counter must be
-    left at zero: the same prepared call, run again after the entries are
-    scaled by 2 in place, must report exactly twice the mass (outputs scale
-    exactly by 2, and the partials are added in the same order)."""
+    """The FP64 mass is the ordered sum of per-tile partials that the last
+    contraction writes, added by a separate final pass: the same prepared call,
+    run again after the entries are scaled by 2 in place, must report exactly
+    twice the mass (outputs scale exactly by 2, and the partials are added in
+    the same order), so no partial or total survives from the previous run."""
     _gpu()
     own, bridges, layers = shape
     inst = W.make_instance(own, bridges, layers, seed=21)
