@@ -22,7 +22,9 @@
  *   - All validation happens on the host before anything is enqueued: on any
  *     non-zero status nothing was launched and no output was touched.
  *   - The caller owns every buffer, including the workspace; the library keeps
- *     no device allocations of its own.
+ *     no device allocations of its own, except the fixed workspace array of
+ *     cqc_reconstruct_fd_noalloc (CQC_NOALLOC_WORKSPACE_BYTES per GPU that
+ *     loads the library, held until the process ends).
  *   - Values are never clamped: negative reconstructed probabilities (possible
  *     with finite-shot entries, Section 3.2.3) are returned as they are.
  *   - Early termination (Section 4.2): a label assignment whose factor row in
@@ -110,6 +112,28 @@ int cqc_fd_workspace_size(const cqc_instance *inst, int32_t n_inst, cqc_dtype in
 int cqc_reconstruct_fd(const cqc_instance *inst, int32_t n_inst, cqc_dtype in_t,
                        cqc_dtype out_t, cqc_precision prec, void *workspace,
                        size_t ws_bytes, hipStream_t stream);
+
+/* cqc_reconstruct_fd without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops and
+ * harnesses that forbid allocation).  Same arguments, kernels, results and
+ * error behaviour as cqc_reconstruct_fd; the workspace is instead a fixed
+ * 256-byte-aligned device array inside the library, of
+ * CQC_NOALLOC_WORKSPACE_BYTES on each GPU (the device that `stream` runs on;
+ * the current device for the null stream).  This call allocates nothing:
+ * no hipMalloc/hipFree and no allocating library routine.  Its device
+ * address is looked up once per device on the first call there.
+ *   - A call whose cqc_fd_workspace_size() exceeds the array fails with
+ *     CQC_ERR_WORKSPACE before anything is enqueued.
+ *   - Every call on one GPU shares that GPU's array, which keeps the last
+ *     call's contents; nothing in it needs to start at zero (every byte a
+ *     call reads was written earlier in that call).  Calls that overlap on
+ *     one GPU (several streams, or several host threads) race on it and give
+ *     undefined results: serialise them.
+ *   - n_inst > 1 takes the batched path, which uploads its tables into the
+ *     array and synchronises `stream` once, as cqc_batch_create does. */
+#define CQC_NOALLOC_WORKSPACE_BYTES ((size_t)32 << 20)
+int cqc_reconstruct_fd_noalloc(const cqc_instance *inst, int32_t n_inst, cqc_dtype in_t,
+                               cqc_dtype out_t, cqc_precision prec, hipStream_t stream);
 
 /* Prepared batches (the batched form of cqc_reconstruct_fd).  A batch of
  * independent instances of uneven n and K is reconstructed by a fixed, small

@@ -99,7 +99,7 @@ class FDCall:
     stream with one library call."""
 
     def __init__(self, entries_list, cuts, precision="fp32", out_dtype=None, outs=None,
-                 with_mass=True, workspace=None):
+                 with_mass=True, workspace=None, noalloc=False):
         if isinstance(cuts, CutMap):
             cuts, entries_list = [cuts], [entries_list]
         self.cuts = list(cuts)
@@ -131,8 +131,16 @@ class FDCall:
         _lib.check(_lib.lib().cqc_fd_workspace_size(self._insts, n_inst, self._in_t, self._out_t,
                                                     self.prec, ctypes.byref(nb)))
         self.ws_bytes = int(nb.value)
-        self.ws = workspace if workspace is not None else torch.empty(
-            max(self.ws_bytes, 256), dtype=torch.uint8, device=dev)
+        self.noalloc = bool(noalloc)
+        if self.noalloc:
+            # run() uses the library's fixed workspace array (cqc_reconstruct_fd_noalloc)
+            if self.ws_bytes > _lib.NOALLOC_WORKSPACE_BYTES:
+                raise ValueError(f"needs {self.ws_bytes} bytes of workspace; the static workspace "
+                                 f"holds {_lib.NOALLOC_WORKSPACE_BYTES}")
+            self.ws = None
+        else:
+            self.ws = workspace if workspace is not None else torch.empty(
+                max(self.ws_bytes, 256), dtype=torch.uint8, device=dev)
         self._fn = _lib.lib().cqc_reconstruct_fd
 
     def set_outputs(self, outs):
@@ -142,6 +150,10 @@ class FDCall:
 
     def run(self, stream=None):
         s = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        if self.noalloc:
+            _lib.check(_lib.lib().cqc_reconstruct_fd_noalloc(self._insts, self.n_inst, self._in_t,
+                                                             self._out_t, self.prec, s))
+            return
         _lib.check(self._fn(self._insts, self.n_inst, self._in_t, self._out_t, self.prec,
                             self.ws.data_ptr(), self.ws_bytes, s))
 

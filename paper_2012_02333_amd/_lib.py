@@ -21,7 +21,9 @@ EXPORTS = [
     "cqc_version", "cqc_selftest_mfma", "cqc_batch_create", "cqc_batch_run", "cqc_batch_destroy",
     "cqc_batch_backward_workspace_size", "cqc_batch_backward_create", "cqc_batch_backward_run",
     "cqc_batch_backward_destroy", "cqc_build_entries", "cqc_chi2", "cqc_xent_grad", "cqc_tune_reset",
+    "cqc_reconstruct_fd_noalloc",
 ]
+NOALLOC_WORKSPACE_BYTES = 32 << 20
 
 
 class CqcCut(ctypes.Structure):
@@ -103,6 +105,7 @@ def lib():
     L.cqc_chi2.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, i64, vp, vp, sz, vp]
     L.cqc_xent_grad.argtypes = [vp, vp, ctypes.c_int, i64, vp, vp, vp, sz, vp]
     L.cqc_tune_reset.argtypes = []
+    L.cqc_reconstruct_fd_noalloc.argtypes = [P(CqcInstance), i32, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
     for name in EXPORTS:
         f = getattr(L, name)
         if f.restype is None or f.restype is ctypes.c_int:

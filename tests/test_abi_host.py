@@ -239,3 +239,20 @@ def test_xent_grad_validation():
     assert L.cqc_xent_grad(p, t, 0, 10, None, None, None, 0, None) == 1
     assert L.cqc_xent_grad(p, t, 0, 10, g, loss, None, 0, None) == 4
     assert L.cqc_xent_grad(p, t, 0, 10, g, loss, ws, 100, None) == 4
+
+
+def test_noalloc_rejects_before_enqueue():
+    """The fixed-workspace FD call validates like cqc_reconstruct_fd, and
+    rejects a call whose workspace exceeds its array (n = 30 with three cuts
+    per boundary needs about 72 MiB) before touching any device."""
+    L = _lib.lib()
+    big = _inst(30, [9, 9, 12], [(0, 1)] * 3 + [(1, 2)] * 3, list(range(30)))
+    rc, need = ws_size(big)
+    assert rc == 0 and need > _lib.NOALLOC_WORKSPACE_BYTES
+    assert L.cqc_reconstruct_fd_noalloc(ctypes.byref(big), 1, 0, 0, 1, None) == 4
+    assert b"static workspace" in L.cqc_last_error_detail()
+    bad = _inst(24, [11, 12], [(0, 1), (0, 1)], list(range(24)))   # sum f != n
+    assert L.cqc_reconstruct_fd_noalloc(ctypes.byref(bad), 1, 0, 0, 1, None) == 2
+    ok = _inst(24, [11, 13], [(0, 1), (0, 1)], list(range(24)))
+    assert L.cqc_reconstruct_fd_noalloc(ctypes.byref(ok), 1, 0, 0, 9, None) == 1   # unknown precision
+    assert L.cqc_reconstruct_fd_noalloc(None, 1, 0, 0, 1, None) == 1
