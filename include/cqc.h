@@ -290,7 +290,12 @@ int cqc_xent_grad(const void *p, const void *t, cqc_dtype dt, int64_t n, void *g
  * is the one-bin-per-recursion search; BFS gives the same records for every
  * bins_per_round.
  * This call is host-driven: it synchronises `stream` once per round (and once
- * per extra candidate refill) and returns after the last recursion completed. */
+ * per extra candidate refill) and returns after the last recursion completed.
+ * For that per-round read-back of the selected bins the library keeps a small
+ * pool of page-locked host buffers (hipHostMalloc, about 9 KiB each: 64
+ * slots of 8 ranked bins and a mass; one per concurrently running query,
+ * reused and held until the process ends); if page-locked memory cannot be
+ * had, pageable memory is used with the same results. */
 typedef enum { CQC_DD_HEAVIEST = 0, CQC_DD_DFS = 1, CQC_DD_BFS = 2 } cqc_dd_strategy;
 
 typedef struct {

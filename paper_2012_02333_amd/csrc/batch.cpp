@@ -139,7 +139,7 @@ static Status build_batch(const cqc_instance *inst, int32_t n_inst, cqc_dtype in
           a.partials = reinterpret_cast<double *>(ws + L.partials_off);
           MassDesc md;
           md.partials = a.partials;
-          md.count = a.nblocks;
+          md.count = kPartialsPerTile * a.nblocks;
           md.mass = inst[i].mass;
           B.mass.push_back(md);
         }

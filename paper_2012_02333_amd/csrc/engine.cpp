@@ -56,7 +56,7 @@ NetLayout layout_net(const Plan &plan, Acc acc, size_t base) {
     }
   }
   L.partials_off = off;
-  off = align_up(off + 8 * (size_t)max_final_blocks, 256);
+  off = align_up(off + 8 * (size_t)kPartialsPerTile * (size_t)max_final_blocks, 256);
   // label lists of every step that may run on the wide kernel
   L.list_off.assign(plan.steps.size(), SIZE_MAX);
   if (acc != Acc::F64) {
@@ -206,7 +206,7 @@ Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &en
       }
       if (mass) a.partials = reinterpret_cast<double *>(ws + L.partials_off);
       CQC_TRY(launch_contract(sa, out_double, cfg, a, s));
-      if (mass) CQC_TRY(launch_mass_final(a.partials, a.nblocks, mass, s));
+      if (mass) CQC_TRY(launch_mass_final(a.partials, kPartialsPerTile * a.nblocks, mass, s));
     }
   }
   return Status::ok();

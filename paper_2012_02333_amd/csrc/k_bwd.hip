@@ -35,18 +35,6 @@ template <> struct BOp<double> {
   }
 };
 
-__device__ __forceinline__ int brow_of(const DigitMapDev &m, int s, int r) {
-  int row = 0;
-#pragma unroll 1
-  for (int i = 0; i < m.n; ++i) {
-    const int v = ((m.srcmask >> i) & 1u) ? r : s;
-    const uint64_t w = i < 10 ? m.shifts[0] : m.shifts[1];
-    const int sh = (int)((w >> (6 * (i < 10 ? i : i - 10))) & 63);
-    row = (row << 2) | ((v >> sh) & 3);
-  }
-  return row;
-}
-
 template <typename T>
 __device__ __forceinline__ void load4m(const T *p, int64_t c, int64_t lim, T *v) {
   // v[t] = p[c + t] for c + t < lim, else 0 (c is a multiple of 4)
@@ -103,7 +91,7 @@ __device__ __forceinline__ void bwd_x_block(const BwdArgs &a, int64_t blk) {
   for (int sb = 0; sb < SB; ++sb) {
     const int s = (ss * SB + sb) * 16 + l16;
     sok[sb] = s < SN;
-    yrow[sb] = sok[sb] ? brow_of(a.my, s, rY) : 0;
+    yrow[sb] = sok[sb] ? row_of(a.my, s, rY) : 0;
   }
   V acc[SB][MB];
 #pragma unroll
@@ -161,7 +149,7 @@ __device__ __forceinline__ void bwd_x_block(const BwdArgs &a, int64_t blk) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int s = (ss * SB + sb) * 16 + (Op::kConsecutive ? 4 * lg + r : lg + 4 * r);
-        if (s < SN && m < M) part[(int64_t)brow_of(a.mx, s, rX) * M + m] = acc[sb][mb][r];
+        if (s < SN && m < M) part[(int64_t)row_of(a.mx, s, rX) * M + m] = acc[sb][mb][r];
       }
     }
 }
@@ -195,7 +183,7 @@ __device__ __forceinline__ void bwd_y_block(const BwdArgs &a, int64_t blk) {
   for (int sb = 0; sb < SB; ++sb) {
     const int s = (ss * SB + sb) * 16 + l16;
     sok[sb] = s < SN;
-    xrow[sb] = sok[sb] ? brow_of(a.mx, s, rX) : 0;
+    xrow[sb] = sok[sb] ? row_of(a.mx, s, rX) : 0;
   }
   V acc[SB][NB];
 #pragma unroll
@@ -250,7 +238,7 @@ __device__ __forceinline__ void bwd_y_block(const BwdArgs &a, int64_t blk) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int s = (ss * SB + sb) * 16 + (Op::kConsecutive ? 4 * lg + r : lg + 4 * r);
-        if (s < SN && n < N) part[(int64_t)brow_of(a.my, s, rY) * N + n] = acc[sb][nb][r];
+        if (s < SN && n < N) part[(int64_t)row_of(a.my, s, rY) * N + n] = acc[sb][nb][r];
       }
     }
 }
@@ -289,7 +277,7 @@ __device__ __forceinline__ void bwd_block_staged(const BwdArgs &a, int64_t blk) 
   const int sr = tid >> 2, sq = tid & 3;
   const int s_st = ss * 64 + sr;
   const bool st_ok = s_st < SN;
-  const float *lrow = L + (int64_t)(st_ok ? brow_of(YS ? a.mx : a.my, s_st, YS ? rX : rY) : 0) * INNER;
+  const float *lrow = L + (int64_t)(st_ok ? row_of(YS ? a.mx : a.my, s_st, YS ? rX : rY) : 0) * INNER;
   float g[8];
   auto gload = [&](int64_t n0) {
     const int64_t c = n0 + 8 * sq;
@@ -362,7 +350,7 @@ __device__ __forceinline__ void bwd_block_staged(const BwdArgs &a, int64_t blk) 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int s = (ss * SB + sb) * 16 + 4 * lg + r;
-        if (s < SN && o < OUT) part[(int64_t)brow_of(YS ? a.my : a.mx, s, rO) * OUT + o] = acc[sb][ob][r];
+        if (s < SN && o < OUT) part[(int64_t)row_of(YS ? a.my : a.mx, s, rO) * OUT + o] = acc[sb][ob][r];
       }
     }
 }

@@ -66,7 +66,6 @@ __device__ __forceinline__ void contract_tile(const ContractArgs &a, uint32_t bl
 
   __shared__ int2 lst[256 + 16];
   __shared__ int wcnt[4];
-  __shared__ double red[4];
   __shared__ int64_t rowoff[MODE == kModeFinalDeposit ? BM : 1];
   __shared__ int64_t coloff[MODE == kModeFinalDeposit ? BN : 1];
 
@@ -221,8 +220,8 @@ __device__ __forceinline__ void contract_tile(const ContractArgs &a, uint32_t bl
     return;
   }
   if (a.partials) {
-    const double tot = block_sum_f64(msum, red);
-    if (tid == 0) a.partials[blk] = tot;
+    const double tot = wave_sum_f64(msum);
+    if (lane == 0) a.partials[kPartialsPerTile * blk + wave] = tot;
   }
 }
 
@@ -239,7 +238,6 @@ __device__ __forceinline__ void contract_small_tile(const ContractArgs &a, uint3
   using V = typename Op::V;
 
   __shared__ int2 lst[16];
-  __shared__ double red[4];
   // FP32 store staging: one 16 x TN slice per wave, so each store instruction
   // writes whole TN-wide row segments instead of 64-byte pieces.
   constexpr bool kStage = Op::kConsecutive && sizeof(O) == 4 && MODE != kModeFinalDeposit && TN >= 32;
@@ -418,8 +416,8 @@ __device__ __forceinline__ void contract_small_tile(const ContractArgs &a, uint3
     return;
   }
   if (a.partials) {
-    const double tot = block_sum_f64(msum, red);
-    if (tid == 0) a.partials[blk] = tot;
+    const double tot = wave_sum_f64(msum);
+    if (lane == 0) a.partials[kPartialsPerTile * blk + wave] = tot;
   }
 }
 
@@ -439,7 +437,6 @@ __device__ __forceinline__ void contract_small_strip(const ContractArgs &a, uint
   using Op = MfmaOp<float>;
   using V = typename Op::V;
   __shared__ float stage[4 * 16 * SLD];
-  __shared__ double red[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t tilesN = (uint32_t)a.tilesN, groups = (uint32_t)a.tilesM / R;
   const uint32_t per_batch = groups * tilesN;
@@ -516,8 +513,9 @@ __device__ __forceinline__ void contract_small_strip(const ContractArgs &a, uint
     if (MODE == kModeIntermediate) {
       if (a.flagZ && tm == 0 && tn == 0 && tid == 0) a.flagZ[batch] = nSv > 0;
     } else if (a.partials) {
-      const double tot = block_sum_f64(msum, red);
-      if (tid == 0) a.partials[(int64_t)batch * a.tilesM * a.tilesN + (int64_t)tm * tilesN + tn] = tot;
+      const double tot = wave_sum_f64(msum);
+      const int64_t tile = (int64_t)batch * a.tilesM * a.tilesN + (int64_t)tm * tilesN + tn;
+      if (lane == 0) a.partials[kPartialsPerTile * tile + wave] = tot;
     }
   }
 }

@@ -1,20 +1,9 @@
 // Dynamic-definition kernels (Algorithm 1, Section 4.3): merging subcircuit
 // entries over their merged qubits, and selecting the heaviest bins.
-#include "kernels.hpp"
+#include "kdev.hpp"
 #include "dd.hpp"
 
 namespace cqc {
-
-__device__ __forceinline__ int64_t dep_bits(int64_t v, const BitPos &pos, int nbits) {
-  int64_t out = 0;
-#pragma unroll 1
-  for (int j = 0; j < nbits; ++j) {
-    const uint64_t w = pos.w[0] * (j / 10 == 0) + pos.w[1] * (j / 10 == 1) + pos.w[2] * (j / 10 == 2) +
-                       pos.w[3] * (j / 10 == 3) + pos.w[4] * (j / 10 == 4);
-    out |= ((v >> j) & 1) << ((w >> (6 * (j % 10))) & 63);
-  }
-  return out;
-}
 
 // E'_c[r][a] = sum_m E_c[r][dep(a, active) | zoom | dep(m, merged)], summed in
 // FP64.  With >= 64 merged combinations one wave takes each (output, chunk of
@@ -43,7 +32,7 @@ __global__ __launch_bounds__(256) void k_dd_merge(const MergeArgs a) {
     const int64_t clen = nmerge >> lc;
     const int lane = threadIdx.x & 63;
     const int64_t r = o >> d.n_active, av = o & ((int64_t(1) << d.n_active) - 1);
-    const int64_t base = (ash >= 0 ? av << ash : dep_bits(av, d.active_pos, d.n_active)) | d.zoom_value;
+    const int64_t base = (ash >= 0 ? av << ash : deposit(av, d.active_pos, d.n_active)) | d.zoom_value;
     const I *row = E + r * f;
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     const int64_t m1 = (ch + 1) * clen;
@@ -52,7 +41,7 @@ __global__ __launch_bounds__(256) void k_dd_merge(const MergeArgs a) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int64_t m = m0 + u * 64;
-        v[u] = m < m1 ? (double)row[base | (msh >= 0 ? m << msh : dep_bits(m, d.merged_pos, d.n_merged))] : 0.0;
+        v[u] = m < m1 ? (double)row[base | (msh >= 0 ? m << msh : deposit(m, d.merged_pos, d.n_merged))] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) acc[u] += v[u];
@@ -91,11 +80,11 @@ __global__ __launch_bounds__(256) void k_dd_merge(const MergeArgs a) {
     const int64_t o = (bid - d.block_start) * 256 + threadIdx.x;
     if (o >= nout) return;
     const int64_t r = o >> d.n_active, av = o & ((int64_t(1) << d.n_active) - 1);
-    const int64_t base = (ash >= 0 ? av << ash : dep_bits(av, d.active_pos, d.n_active)) | d.zoom_value;
+    const int64_t base = (ash >= 0 ? av << ash : deposit(av, d.active_pos, d.n_active)) | d.zoom_value;
     const I *row = E + r * f;
     double s = 0.0;
     for (int64_t m = 0; m < nmerge; ++m)
-      s += (double)row[base | (msh >= 0 ? m << msh : dep_bits(m, d.merged_pos, d.n_merged))];
+      s += (double)row[base | (msh >= 0 ? m << msh : deposit(m, d.merged_pos, d.n_merged))];
     Out[o] = (O)s;
   }
 }

@@ -253,7 +253,6 @@ __device__ __forceinline__ void wide_run(Seq &seq) {
   static_assert(kOpBytes >= 4 * 16 * kStLd * 4, "epilogue staging fits in the operand area");
   static_assert(NP != 0 || kOpBytes >= 4 * 32 * kStLd * 4, "32-row staging slices fit in the operand area");
   __shared__ __attribute__((aligned(16))) unsigned char smem[kOpBytes];
-  __shared__ double red[4];
   __shared__ int64_t rowoff[MODE == kModeFinalDeposit ? kWB : 1];
   __shared__ int64_t coloff[MODE == kModeFinalDeposit ? kWB : 1];
 
@@ -527,8 +526,8 @@ __device__ __forceinline__ void wide_run(Seq &seq) {
     }
     double *partials = uni(a.partials);
     if (MODE != kModeIntermediate && partials) {
-      const double tot = block_sum_f64(msum, red);
-      if (tid == 0) gbl(partials)[t.blk] = tot;
+      const double tot = wave_sum_f64(msum);
+      if (lane == 0) gbl(partials)[kPartialsPerTile * t.blk + wave] = tot;
     }
   };
 

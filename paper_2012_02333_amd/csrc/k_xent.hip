@@ -15,12 +15,11 @@
 #include <cstdint>
 #include <string>
 
-#include "common.hpp"
+#include "kdev.hpp"
 
 namespace cqc {
 
 constexpr int kXentMaxBlocks = 1024;
-constexpr double kXentFloor = 1e-30;
 
 typedef float xf4 __attribute__((ext_vector_type(4)));
 
@@ -48,9 +47,8 @@ __device__ __forceinline__ void xstore4(T *p, int64_t i, const T (&v)[4]) {
 
 template <bool LOSS, typename T>
 __device__ __forceinline__ T xent_one(T p, T t, double &loss) {
-  const bool live = (double)p > kXentFloor;
-  if constexpr (LOSS) loss -= (double)t * log(live ? (double)p : kXentFloor);
-  return live ? -t / p : T(0);
+  if constexpr (LOSS) loss -= (double)t * log((double)p > kXentFloor ? (double)p : kXentFloor);
+  return xent_grad_of(p, t);
 }
 
 template <bool VEC, bool LOSS, typename T>

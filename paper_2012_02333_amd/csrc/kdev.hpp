@@ -86,17 +86,20 @@ template <> __device__ __forceinline__ void store4<double>(double *p, const doub
   reinterpret_cast<double2 *>(p)[1] = make_double2(v[2], v[3]);
 }
 
-// Block-wide FP64 sum in a fixed order (wave butterfly, then waves 0..3).
-__device__ __forceinline__ double block_sum_f64(double v, double *red) {
+// Gradient of the cross-entropy L = -sum_x t_x log max(p_x, 1e-30) with respect
+// to p_x: -t_x / p_x above the floor, 0 at or below it (flat there).  The floor
+// test is made on p widened to FP64, the division in T.
+constexpr double kXentFloor = 1e-30;
+template <typename T>
+__device__ __forceinline__ T xent_grad_of(T p, T t) {
+  return (double)p > kXentFloor ? -t / p : T(0);
+}
+
+// Wave-wide FP64 sum in a fixed order (butterfly); every lane gets the total.
+__device__ __forceinline__ double wave_sum_f64(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x == 0) t = ((red[0] + red[1]) + red[2]) + red[3];
-  __syncthreads();
-  return t;
+  return v;
 }
 
 // Largest d with prefix[d] <= item (the step a work-queue item belongs to).

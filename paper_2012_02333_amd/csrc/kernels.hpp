@@ -59,6 +59,12 @@ struct ContractArgs {
   int64_t nbatch;
 };
 
+// FP64 mass partials: every wave of a final-step tile (four per block) stores
+// the FP64 sum of the outputs it wrote at partials[kPartialsPerTile * tile +
+// wave], so no block barrier stands between a tile's stores and the next
+// tile; the final pass adds them in index order.
+constexpr int kPartialsPerTile = 4;
+
 // Workspace of the label lists of a step run by the wide kernel.
 // Operands of the wide kernel are addressed with 32-bit byte offsets.
 constexpr int64_t kWideMaxOperandElems = int64_t(1) << 30;

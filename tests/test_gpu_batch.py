@@ -46,8 +46,12 @@ def test_batch_equals_single_calls(prec, dtype):
         if k < 6:
             e64 = oracle_inputs([E.astype(np_dt) for E in inst.entries])
             ref = fd.reconstruct(e64, inst.cut)
-            tol = 1e-12 if prec == "fp64" else REL_L1[prec] * max(1.0, metrics.kappa(e64, inst.cut, np.abs(ref).sum()))
-            assert metrics.rel_l1(call.outs[k].double().cpu().numpy(), ref) <= tol
+            # simulated circuits: the flat relative-L1 bar of each precision
+            tol = 1e-12 if prec == "fp64" else REL_L1[prec]
+            err = metrics.rel_l1(call.outs[k].double().cpu().numpy(), ref)
+            print(f"batch {prec} instance {k}: rel_l1={err:.3e} "
+                  f"kappa={metrics.kappa(e64, inst.cut, np.abs(ref).sum()):.2f}")
+            assert err <= tol
 
 
 def test_batch_structures_mixed():

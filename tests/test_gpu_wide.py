@@ -40,11 +40,14 @@ def _check(cut, ents, prec, xs=None, out_dtype=None):
     err = metrics.rel_l1(got, ref)
     kap = metrics.kappa(e64, cut, np.abs(ref).sum()) if xs is None else 1.0
     print(f"{prec}: rel_l1={err:.3e} kappa={kap:.2f}")
-    assert err <= REL_L1[prec] * max(1.0, kap)
+    # FP32 and BF16X6: the flat 1e-6 bar (kappa is a diagnostic); BF16X3's
+    # bar is its dropped part, 1.2e-5 of T_x, hence kappa-scaled
+    bar = REL_L1[prec] * (max(1.0, kap) if prec == "bf16x3" else 1.0)
+    assert err <= bar
     ok, info = elementwise_ok(got, ref, abs_bound(e64, cut, xs), U32, sum_terms(prec, 4 ** cut.n_cuts))
     assert ok, info
     if xs is None:
-        assert abs(float(mass.cpu()) - ref.sum()) <= REL_L1[prec] * max(1.0, kap) * np.abs(ref).sum()
+        assert abs(float(mass.cpu()) - ref.sum()) <= bar * np.abs(ref).sum()
     return p
 
 
