@@ -41,9 +41,18 @@ struct BatchBuild {
   std::vector<size_t> desc_off, prefix_off, bprefix_off;
 };
 
-static int queue_cfg(Acc acc, const Step &st) {
-  const int c = choose_tile(step_acc(acc, st.wide_ok(), (int)st.S.size()), (int)st.S.size(), st.logM, st.logN, st.wide_ok(),
-                            st.nbatch);
+// Tile of a step in a batched launch: the autotuner's choice for the step's
+// shape class (the cache single calls consult) where a queue kernel has that
+// tile and the operands fit it, else the built-in rule.  The queue kernels
+// have no 256 x 16 form; its steps take the 16 x 64 tile.
+static int queue_cfg(Acc acc, const Step &st, int mode, bool out_double) {
+  const Acc sa = step_acc(acc, st.wide_ok(), (int)st.S.size());
+  const int nS = (int)st.S.size();
+  int c = choose_tile(sa, nS, st.logM, st.logN, st.wide_ok(), st.nbatch);
+  int tc = 0, xcd = 0;
+  if (tuned_choice(sa, mode, nS <= 2, st.logM, st.logN, nS, out_double, &tc, &xcd) && tile_ok(sa, tc) &&
+      (tc != kTileW || st.wide_ok()))
+    c = tc;
   return c == kTileT ? kTileS : c;
 }
 
@@ -104,7 +113,8 @@ static Status build_batch(const cqc_instance *inst, int32_t n_inst, cqc_dtype in
       a.nS = (int)st.S.size();
       a.nRX = (int)st.RX.size();
       a.nRY = (int)st.RY.size();
-      const int cfg = queue_cfg(B.acc, st);
+      const int step_mode = !last ? kModeIntermediate : (is_blocked(p, st) ? kModeFinalBlocked : kModeFinalDeposit);
+      const int cfg = queue_cfg(B.acc, st, step_mode, acc_double);
       const TileShape sh = tile_shape(cfg);
       a.tilesM = (int)(((int64_t(1) << st.logM) + sh.bm - 1) / sh.bm);
       a.tilesN = (int)(((int64_t(1) << st.logN) + sh.bn - 1) / sh.bn);

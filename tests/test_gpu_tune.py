@@ -121,3 +121,36 @@ def test_wide_entry_skipped_where_operands_do_not_fit(tune_env):
     ref = fd.reconstruct(e64, cut)
     ok, info = elementwise_ok(p.double().cpu().numpy(), ref, abs_bound(e64, cut), U32, sum_terms("fp32", 4))
     assert ok, info
+
+
+def test_cache_entry_changes_the_batched_kernel(tune_env):
+    """The batched launch consults the same shape-class cache: two instances
+    with f = (7, 9) and two cuts run the two-tile strip queue by default; a
+    cache line naming the 16 x 64 tile for that class makes the batch run the
+    16 x 64 work-queue kernel, every output equal to the (equally tuned)
+    one-instance call and within the oracle's rounding bound."""
+    _gpu()
+    insts = [W.make_instance((7, 7), (2,), 6, seed=86 + k) for k in range(2)]
+    assert all(list(i.cut.f) == [7, 9] for i in insts)
+    hosts, devs = zip(*[to_dev(i.entries, torch.float32) for i in insts])
+    cuts = [cqc.CutMap.from_workload(i.cut) for i in insts]
+
+    def run_batch():
+        b = cqc.Batch([list(d) for d in devs], cuts, precision="fp32")
+        with cqc.trace() as tr:
+            b.run()
+            torch.cuda.synchronize()
+        return b, tr.result
+    b0, kt0 = run_batch()
+    assert "contract_strip_queue" in kt0, list(kt0)
+    with open(tune_env, "w") as fh:
+        fh.write("0 1 1 7 9 2 0 2 0 1.000\n")
+    cqc.tune_reset()
+    b1, kt1 = run_batch()
+    assert "contract_small_queue" in kt1 and "contract_strip_queue" not in kt1, list(kt1)
+    for k, inst in enumerate(insts):
+        p1, _ = cqc.reconstruct_fd(list(devs[k]), cuts[k], precision="fp32")
+        torch.cuda.synchronize()
+        assert torch.equal(b1.outs[k], p1), k
+        assert _check(b1.outs[k], hosts[k], inst.cut) <= 1e-6
+        assert _check(b0.outs[k], hosts[k], inst.cut) <= 1e-6
