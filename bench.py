@@ -347,23 +347,27 @@ def bench_dd(args, torch, cqc, W):
                 records=[{"parent": r["parent"], "mass": r["mass"]} for r in recs])
     if not args.no_cpu:
         from oracle import dd, native  # CPU-baseline leg only
+        threads = native.max_threads()
         e64_np = [E.astype(np.float64) for E in e32_np]
         role = [dd.ACTIVE if q < a else dd.MERGED for q in range(inst.n)]
         t0 = time.perf_counter()
-        merged = dd.merge_entries(e64_np, inst.cut, role)
+        merged = native.dd_merge(e64_np, inst.cut, role, threads)
         t_merge = time.perf_counter() - t0
         g = bins[0].cpu().numpy()
         rng = np.random.default_rng(12)
         probe = np.sort(rng.choice(2 ** a, 256, replace=False))
-        ref = dd.bins_from_merged(merged, inst.cut, role, probe)
+        ref = native.dd_bins(merged, inst.cut, role, probe, threads)
         out["err_rel_l1_recursion1_sampled"] = float(np.abs(g[probe] - ref).sum() / np.abs(ref).sum())
         rate, size, reps, el = _cpu_rate(
-            lambda m: dd.bins_from_merged(merged, inst.cut, role, np.sort(rng.choice(2 ** a, m, replace=False))),
-            2 ** a, args.cpu_seconds, 64)
-        out["cpu_baseline"] = {"value": rate, "unit": "bins/s", "cores": 1, "kind": "oracle",
-                               "sample": f"recursion 1: merge ({t_merge:.2f} s, not in the rate) then {size} "
-                                         f"seeded bins x {reps} repetitions ({el:.1f} s), numpy FP64 "
-                                         f"definition over 4^8 terms"}
+            lambda m: native.dd_bins(merged, inst.cut, role, np.sort(rng.choice(2 ** a, m, replace=False)), threads),
+            2 ** a, args.cpu_seconds, 1024)
+        full = 2 ** a / (t_merge + 2 ** a / rate)
+        out["cpu_baseline"] = {"value": full, "unit": "bins/s", "cores": threads, "kind": "oracle",
+                               "cpu_model": _cpu_model(),
+                               "sample": f"recursion 1 by the C/OpenMP twin: merge ({t_merge:.3f} s) plus {size} "
+                                         f"seeded bins x {reps} repetitions ({el:.1f} s) of the per-bin FP64 "
+                                         f"definition over 4^8 terms, scaled to 2^{a} bins; "
+                                         f"rate = 2^{a} / (merge + scaled bin time)"}
     return out
 
 
@@ -453,7 +457,8 @@ def bench_dd_scale(args, torch, cqc, W):
                  "bins": "fp32", "seed": W.DD_SCALE["seed"]},
                 roof, kernels_ms_per_call=per_call, mass=recs[0]["mass"])
     if not args.no_cpu:
-        from oracle import dd  # CPU-baseline leg only
+        from oracle import native  # CPU-baseline leg only
+        threads = native.max_threads()
         role = recs[0]["role"]
         rng = np.random.default_rng(13)
         probe = np.sort(rng.choice(2 ** a, 64, replace=False))
@@ -462,16 +467,20 @@ def bench_dd_scale(args, torch, cqc, W):
         torch.cuda.empty_cache()
         e64_np = [E.astype(np.float64) for E in ents]
         t0 = time.perf_counter()
-        merged = dd.merge_entries(e64_np, wcut, role)
+        merged = native.dd_merge(e64_np, wcut, role, threads)
         t_merge = time.perf_counter() - t0
-        ref = dd.bins_from_merged(merged, wcut, role, probe)
+        del e64_np
+        ref = native.dd_bins(merged, wcut, role, probe, threads)
         out["err_rel_l1_sampled"] = float(np.abs(got - ref).sum() / np.abs(ref).sum())
         rate, size, reps, el = _cpu_rate(
-            lambda m: dd.bins_from_merged(merged, wcut, role, np.sort(rng.choice(2 ** a, m, replace=False))),
-            2 ** a, args.cpu_seconds, 64)
-        out["cpu_baseline"] = {"value": rate, "unit": "bins/s", "cores": 1, "kind": "oracle",
-                               "sample": f"merge ({t_merge:.1f} s, not in the rate) then {size} seeded bins x "
-                                         f"{reps} repetitions ({el:.1f} s), numpy FP64 definition over 4^8 terms"}
+            lambda m: native.dd_bins(merged, wcut, role, np.sort(rng.choice(2 ** a, m, replace=False)), threads),
+            2 ** a, args.cpu_seconds, 1024)
+        full = 2 ** a / (t_merge + 2 ** a / rate)
+        out["cpu_baseline"] = {"value": full, "unit": "bins/s", "cores": threads, "kind": "oracle",
+                               "cpu_model": _cpu_model(),
+                               "sample": f"the C/OpenMP twin: merge ({t_merge:.1f} s) plus {size} seeded bins x "
+                                         f"{reps} repetitions ({el:.1f} s) of the per-bin FP64 definition over "
+                                         f"4^8 terms, scaled to 2^{a} bins; rate = 2^{a} / (merge + scaled bin time)"}
     return out
 
 
@@ -494,16 +503,19 @@ def bench_chi2(args, torch, cqc, W):
     out = _line("chi2", "chi-square distance outcomes/s (Eq. 16, FP32 inputs, FP64 terms)", n / (ms * 1e-3),
                 "outcomes/s", steps, warmup, ms, "f32", {"n": n}, roof, kernels_ms=kt)
     if not args.no_cpu:
-        from oracle import metrics  # CPU-baseline leg only
-        m = 1 << 24
+        from oracle import native  # CPU-baseline leg only
+        threads = native.max_threads()
+        m = 1 << 26
         an, bn = a[:m].double().cpu().numpy(), b[:m].double().cpu().numpy()
         t0, reps = time.perf_counter(), 0
         while time.perf_counter() - t0 < args.cpu_seconds / 2:
-            metrics.chi2(an, bn)
+            native.chi2(an, bn, threads)
             reps += 1
         el = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": m * reps / el, "unit": "outcomes/s", "cores": 1, "kind": "oracle",
-                               "sample": f"first 2^24 outcomes x {reps} repetitions ({el:.1f} s), numpy FP64"}
+        out["cpu_baseline"] = {"value": m * reps / el, "unit": "outcomes/s", "cores": threads, "kind": "oracle",
+                               "cpu_model": _cpu_model(),
+                               "sample": f"first 2^26 outcomes x {reps} repetitions ({el:.1f} s), "
+                                         f"C/OpenMP FP64 twin of Eq. 16"}
     return out
 
 

@@ -219,3 +219,35 @@ def test_unknown_strategy():
     inst = W.make_instance((2, 2), (1,), 4, seed=1)
     with pytest.raises(ValueError):
         dd.reconstruct(inst.entries, inst.cut, 2, 2, strategy="random")
+
+
+@pytest.mark.parametrize("case", ["recursion1", "zoomed", "permuted"])
+def test_c_twin_dd_merge_and_bins_bitwise(case):
+    """The C/OpenMP twin of the DD merge and bins (used for CPU timing) equals
+    the Python oracle bit for bit: same additions in the same order."""
+    from oracle import native
+    if case == "permuted":
+        cut = W.CutMap(n=10, f=[4, 3, 3], edge_up=[0, 1, 0], edge_down=[1, 2, 2],
+                       out_qubit=[7, 2, 9, 0, 5, 3, 8, 1, 4, 6])
+        ents = W.random_entries(cut, seed=44)
+    else:
+        inst = W.make_instance((3, 2, 3), (2, 2), 4, seed=45)
+        cut, ents = inst.cut, inst.entries
+    n = cut.n
+    role = [dd.MERGED] * n
+    if case == "recursion1":
+        for q in range(4):
+            role[q] = dd.ACTIVE
+    else:
+        for q, v in ((0, 1), (3, 0), (5, 1)):
+            role[q] = v
+        for q in (1, 2, 6, 8):
+            role[q] = dd.ACTIVE
+    m_py = dd.merge_entries(ents, cut, role)
+    m_c = native.dd_merge(ents, cut, role, threads=4)
+    for a, b in zip(m_py, m_c):
+        assert np.array_equal(a, b)
+    b_py = dd.bins_from_merged(m_py, cut, role)
+    assert np.array_equal(native.dd_bins(m_c, cut, role, threads=3), b_py)
+    sel = np.array([0, 3, 7, 15], dtype=np.int64)
+    assert np.array_equal(native.dd_bins(m_c, cut, role, sel), b_py[sel])

@@ -178,3 +178,19 @@ def test_kappa_equals_brute_force_abs_term_sum():
     k = metrics.kappa(ents, cut, np.abs(p).sum())
     assert abs(k * np.abs(p).sum() - tot) < 1e-13 * tot
     assert k > 1.5          # signed entries cancel: the abs() matters here
+
+
+def test_c_twin_chi2():
+    """The C/OpenMP chi-square twin: the closed form on a hand case (zero-sum
+    terms skipped), and the numpy oracle to rounding on a large random pair
+    for several thread counts."""
+    a = np.array([0.5, 0.5, 0.0, 0.0])
+    b = np.array([0.25, 0.75, 0.0, 0.0])
+    assert abs(native.chi2(a, b) - (0.0625 / 0.75 + 0.0625 / 1.25)) < 1e-16
+    rng = np.random.default_rng(5)
+    x, y = rng.random(100003), rng.random(100003)
+    x[::7] = 0.0
+    y[::7] = 0.0
+    ref = metrics.chi2(x, y)
+    for t in (1, 3, 8):
+        assert abs(native.chi2(x, y, threads=t) - ref) <= 1e-12 * ref
