@@ -314,11 +314,32 @@ def bench_dd(args, torch, cqc, W):
     warmup = args.warmup if args.warmup is not None else 2
     holder = {}
 
+    # the device-resident query (every pick on the device, no host round
+    # trip), captured once in a graph and replayed: the timed step
+    q = cqc.DDQuery(e32, cut, a, R, precision="fp32")
+    q.run()
+    torch.cuda.synchronize()
+    gs = torch.cuda.Stream()
+    gs.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(gs):
+        q.run()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=gs):
+            q.run()
+    torch.cuda.synchronize()
+    ms = _sync_time(lambda i: graph.replay(), steps, warmup, torch)
+    kt = _traced(lambda i: q.run(), steps, cqc, torch)
+    ms_eager = _sync_time(lambda i: q.run(), steps, warmup, torch)
+    bins, recs = q.result()
+
+    # the host-driven query (a read-back and host pick per recursion)
     def step(i):
         holder["r"] = cqc.reconstruct_dd(e32, cut, a, R, precision="fp32")
-    ms = _sync_time(step, steps, warmup, torch)
-    kt = _traced(step, steps, cqc, torch)
-    bins, recs = holder["r"]
+    ms_host = _sync_time(step, steps, warmup, torch)
+    bins_h, recs_h = holder["r"]
+    same_host = ([r["parent"] for r in recs_h] == [r["parent"] for r in recs] and
+                 [r["mass"] for r in recs_h] == [r["mass"] for r in recs] and bool(torch.equal(bins_h, bins)))
 
     # the same search with four bins per host round trip: the four refinements
     # of the first recursion have no merged qubits, so they are the same four
@@ -341,8 +362,10 @@ def bench_dd(args, torch, cqc, W):
     out = _line("c4", "DD reconstructed bins/s n=40,K=8 (2^20 bins x 5 recursions, FP32 term sum, FP64 bins)",
                 bins_total / (ms * 1e-3), "bins/s", steps, warmup, ms, "f32",
                 {"n": inst.n, "K": inst.K, "n_active": a, "recursions": nrec, "precision": "fp32",
-                 "seed": W.RECIPES["c4"]["seed"]},
+                 "seed": W.RECIPES["c4"]["seed"], "query": "device-resident, graph replay"},
                 roof, us_per_recursion=1e3 * ms / nrec, kernels_ms_per_call=per_call,
+                device_query_eager={"ms_per_step": ms_eager},
+                host_driven_query={"ms_per_step": ms_host, "same_records_and_bins": same_host},
                 four_bins_per_round={"ms_per_step": ms4, "same_records": same4},
                 records=[{"parent": r["parent"], "mass": r["mass"]} for r in recs])
     if not args.no_cpu:

@@ -329,6 +329,33 @@ int cqc_reconstruct_dd(const cqc_instance *inst, cqc_dtype in_t, cqc_precision p
                        int32_t *n_done, void *workspace, size_t ws_bytes,
                        hipStream_t stream);
 
+/* Device-resident dynamic definition: the same search as cqc_reconstruct_dd
+ * (Algorithm 1, Section 4.3; same bins, records and masses, bit for bit) with
+ * every decision taken on the device, so a query enqueues all its recursions
+ * without a host round trip and can be captured in a HIP graph and replayed.
+ * Each recursion's bin is picked by a kernel from per-recursion windows of
+ * the best not-yet-expanded bins that top-T passes keep in the query state;
+ * a window that runs out is refilled on the device.  One bin is expanded per
+ * recursion: bins_per_round must be 0 or 1 (CQC_ERR_UNSUPPORTED otherwise).
+ * cqc_dd_query_create validates and plans the query, binds the entries,
+ * `bins` (DEVICE, as for cqc_reconstruct_dd), `records` (DEVICE
+ * [n_recursions]) and `n_done` (DEVICE, one int32: the recursions run), writes
+ * its tables into `workspace` (DEVICE, at least cqc_dd_query_workspace_size()
+ * bytes, 256-byte aligned, kept allocated and unmodified while the query
+ * exists) and synchronises `stream` once.
+ * cqc_dd_query_run enqueues one complete query (only kernel launches: no
+ * synchronisation, no allocation, no host read); records past n_done are
+ * not written.  Runs of one query on different streams must not overlap.
+ * cqc_dd_query_destroy frees the host-side handle only. */
+typedef struct cqc_dd_query_s *cqc_dd_query;
+int cqc_dd_query_workspace_size(const cqc_instance *inst, cqc_dtype in_t, cqc_precision prec,
+                                const cqc_dd_params *p, size_t *bytes);
+int cqc_dd_query_create(const cqc_instance *inst, cqc_dtype in_t, cqc_precision prec,
+                        const cqc_dd_params *p, void *bins, cqc_dd_record *records, int32_t *n_done,
+                        void *workspace, size_t ws_bytes, hipStream_t stream, cqc_dd_query *out);
+int cqc_dd_query_run(cqc_dd_query q, hipStream_t stream);
+int cqc_dd_query_destroy(cqc_dd_query q);
+
 /* Adjoint of the FD build: given G = dL/dp (DEVICE [2^n] per instance, dtype
  * in_t), writes dL/dE_c for every subcircuit (DEVICE, same layout and dtype
  * as E_c):

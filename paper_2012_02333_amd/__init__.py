@@ -393,15 +393,77 @@ def reconstruct_dd(entries, cut, n_active, n_recursions, first_active=None, prec
                                     ctypes.byref(params), bins.data_ptr(), recs,
                                     ctypes.byref(done), ws.data_ptr(), int(nb.value),
                                     _stream_ptr(dev)))
+    return bins[:done.value], _decode_records(recs, done.value, cut.n)
+
+
+def _decode_records(recs, n, n_cut_qubits):
     out = []
-    for r in range(done.value):
+    for r in range(n):
         rec = recs[r]
-        role = [int(rec.role[q]) for q in range(cut.n)]
+        role = [int(rec.role[q]) for q in range(n_cut_qubits)]
         parent = (int(rec.parent_rec), int(rec.parent_bin))
         out.append(dict(parent=parent, n_active=int(rec.n_active), mass=float(rec.mass), role=role,
-                        active=[q for q in range(cut.n) if role[q] == -2],
+                        active=[q for q in range(n_cut_qubits) if role[q] == -2],
                         depth=0 if parent[0] < 0 else out[parent[0]]["depth"] + 1))
-    return bins[:done.value], out
+    return out
+
+
+class DDQuery:
+    """A prepared device-resident dynamic-definition query
+    (cqc_dd_query_create): the bins, records and recursion count live in
+    device memory and run() enqueues the whole search with no host round
+    trip, so it can be captured in a CUDA/HIP graph.  Same search and results
+    as reconstruct_dd with one bin per round.  result() reads the records
+    back (one copy) -> (bins [R_done, 2^a], records list)."""
+
+    def __init__(self, entries, cut, n_active, n_recursions, first_active=None, precision="fp32",
+                 strategy="heaviest", bins_dtype=torch.float64):
+        if strategy not in DD_STRATEGIES:
+            raise ValueError(f"unknown strategy {strategy!r}")
+        if bins_dtype not in (torch.float64, torch.float32):
+            raise ValueError("bins_dtype must be float64 or float32")
+        in_dt = _check_entries(entries, cut)
+        dev = entries[0].device
+        self.entries, self.cut, self.device = list(entries), cut, dev
+        self._ptrs = (ctypes.c_void_p * len(entries))(*[E.data_ptr() for E in entries])
+        self._inst = _lib.CqcInstance(cut.c, self._ptrs, None, None)
+        self._fa = None
+        if first_active is not None:
+            self._fa = (ctypes.c_int32 * len(first_active))(*[int(q) for q in first_active])
+        self._params = _lib.CqcDDParams(int(n_active), int(n_recursions), self._fa, DD_STRATEGIES[strategy], 1,
+                                        1 if bins_dtype == torch.float32 else 0)
+        L = _lib.lib()
+        nb = ctypes.c_size_t(0)
+        _lib.check(L.cqc_dd_query_workspace_size(ctypes.byref(self._inst), _DT[in_dt], PREC[precision],
+                                                 ctypes.byref(self._params), ctypes.byref(nb)))
+        self.ws = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=dev)
+        a = min(int(n_active), cut.n)
+        self.R = int(n_recursions)
+        self.bins = torch.empty((self.R, 2 ** a), dtype=bins_dtype, device=dev)
+        self.records = torch.zeros(self.R * ctypes.sizeof(_lib.CqcDDRecord), dtype=torch.uint8, device=dev)
+        self.n_done = torch.zeros(1, dtype=torch.int32, device=dev)
+        h = ctypes.c_void_p(0)
+        _lib.check(L.cqc_dd_query_create(ctypes.byref(self._inst), _DT[in_dt], PREC[precision],
+                                         ctypes.byref(self._params), self.bins.data_ptr(), self.records.data_ptr(),
+                                         self.n_done.data_ptr(), self.ws.data_ptr(), self.ws.numel(),
+                                         _stream_ptr(dev), ctypes.byref(h)))
+        self._h = h
+
+    def run(self, stream=None):
+        s = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        _lib.check(_lib.lib().cqc_dd_query_run(self._h, s))
+
+    def result(self):
+        done = int(self.n_done.cpu()[0])
+        raw = self.records.cpu().numpy().tobytes()
+        recs = (_lib.CqcDDRecord * self.R).from_buffer_copy(raw)
+        return self.bins[:done], _decode_records(recs, done, self.cut.n)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.lib().cqc_dd_query_destroy(h)
+            self._h = None
 
 
 def reconstruct_backward(entries, cut, grad_out, precision="fp32"):

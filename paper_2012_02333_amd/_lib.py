@@ -21,7 +21,8 @@ EXPORTS = [
     "cqc_version", "cqc_selftest_mfma", "cqc_batch_create", "cqc_batch_run", "cqc_batch_destroy",
     "cqc_batch_backward_workspace_size", "cqc_batch_backward_create", "cqc_batch_backward_run",
     "cqc_batch_backward_destroy", "cqc_build_entries", "cqc_chi2", "cqc_xent_grad", "cqc_tune_reset",
-    "cqc_reconstruct_fd_noalloc",
+    "cqc_reconstruct_fd_noalloc", "cqc_dd_query_workspace_size", "cqc_dd_query_create", "cqc_dd_query_run",
+    "cqc_dd_query_destroy",
 ]
 NOALLOC_WORKSPACE_BYTES = 32 << 20
 
@@ -105,6 +106,11 @@ def lib():
     L.cqc_chi2.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, i64, vp, vp, sz, vp]
     L.cqc_xent_grad.argtypes = [vp, vp, ctypes.c_int, i64, vp, vp, vp, sz, vp]
     L.cqc_tune_reset.argtypes = []
+    L.cqc_dd_query_workspace_size.argtypes = [P(CqcInstance), ctypes.c_int, ctypes.c_int, P(CqcDDParams), P(sz)]
+    L.cqc_dd_query_create.argtypes = [P(CqcInstance), ctypes.c_int, ctypes.c_int, P(CqcDDParams), vp, vp, vp, vp,
+                                      sz, vp, P(vp)]
+    L.cqc_dd_query_run.argtypes = [vp, vp]
+    L.cqc_dd_query_destroy.argtypes = [vp]
     L.cqc_reconstruct_fd_noalloc.argtypes = [P(CqcInstance), i32, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
     for name in EXPORTS:
         f = getattr(L, name)

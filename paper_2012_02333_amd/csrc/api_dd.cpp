@@ -20,7 +20,7 @@
 #include <memory>
 #include <mutex>
 
-#include "dd.hpp"
+#include "ddplan.hpp"
 
 namespace cqc {
 
@@ -32,34 +32,45 @@ static int contiguous_shift(const std::vector<int> &pos) {
   return pos.empty() ? 0 : pos[0];
 }
 
-struct DepthPlan {
-  std::vector<int> active;                   // ascending qubit ids
-  std::vector<char> zoomed;                  // per qubit
-  bool has_merged = false;
-  std::vector<std::vector<int>> act_local;   // per subcircuit: active local bits j (ascending)
-  std::vector<std::vector<int>> mrg_local;   // per subcircuit: merged local bits j
-  NetLayout net;
-  std::vector<size_t> merged_off;
-  std::vector<size_t> part_off;              // chunk sums of long merges (SIZE_MAX: none)
-  size_t end = 0;
-};
-
-// what a round reads back per recursion: its top-T candidates and its mass
-struct DdSlot {
-  TopOut top;
-  double mass;
-};
-
-constexpr int kDdMaxPerRound = 64;
-
-struct DdPlan {
-  CutInfo cut;
-  Acc acc;
-  int a = 0, R = 0, strategy = 0, per_round = 1;
-  bool bins_f32 = false;
-  std::vector<DepthPlan> depths;
-  size_t topk_off = 0, out_off = 0, bytes = 0;
-};
+void dd_merge_args(const DdPlan &d, const DepthPlan &dp, const void *const *entries, char *ws, bool in_double,
+                   const int64_t *zoom, const int64_t *const *zoom_dev, MergeArgs *ma, int64_t *blocks,
+                   std::vector<const void *> *merged) {
+  const bool acc_double = d.acc == Acc::F64;
+  std::memset(ma, 0, sizeof(*ma));
+  *blocks = 0;
+  merged->assign(d.cut.nsub, nullptr);
+  for (int c = 0; c < d.cut.nsub; ++c) {
+    const int f = d.cut.f[c];
+    // every bit active, in local order, and no conversion: the merged
+    // tensor is the entry tensor itself
+    if (dp.mrg_local[c].empty() && (int)dp.act_local[c].size() == f && in_double == acc_double) {
+      (*merged)[c] = entries[c];
+      continue;
+    }
+    MergeDesc &md = ma->d[ma->n++];
+    md.src = entries[c];
+    md.dst = ws + dp.merged_off[c];
+    (*merged)[c] = md.dst;
+    md.rows = int64_t(1) << (2 * d.cut.inc[c].size());
+    md.f = f;
+    md.n_active = (int)dp.act_local[c].size();
+    md.n_merged = (int)dp.mrg_local[c].size();
+    std::vector<int> apos, mpos;
+    for (int k = md.n_active - 1; k >= 0; --k) apos.push_back(f - 1 - dp.act_local[c][k]);
+    for (int k = md.n_merged - 1; k >= 0; --k) mpos.push_back(f - 1 - dp.mrg_local[c][k]);
+    md.active_pos = pack_pos(apos);
+    md.merged_pos = pack_pos(mpos);
+    md.active_shift = contiguous_shift(apos);
+    md.merged_shift = contiguous_shift(mpos);
+    md.log_chunks = merge_log_chunks(md.n_merged);
+    md.seg = merge_segmented(md.n_merged, md.active_shift, md.merged_shift) ? 1 : 0;
+    md.part = md.log_chunks > 0 ? reinterpret_cast<double *>(ws + dp.part_off[c]) : nullptr;
+    md.zoom_value = zoom ? zoom[c] : 0;
+    md.zoom_dev = zoom_dev ? zoom_dev[c] : nullptr;
+    md.block_start = *blocks;
+    *blocks += merge_blocks(md.rows << md.n_active, md.n_merged, md.seg != 0);
+  }
+}
 
 static Status build_dd(const cqc_instance *inst, cqc_dtype in_t, cqc_precision prec,
                        const cqc_dd_params *p, DdPlan *out) {
@@ -263,8 +274,8 @@ static bool dd_key(const cqc_instance *inst, cqc_dtype in_t, cqc_precision prec,
   return true;
 }
 
-static Status cached_dd(const cqc_instance *inst, cqc_dtype in_t, cqc_precision prec, const cqc_dd_params *p,
-                        std::shared_ptr<const DdPlan> *out) {
+Status cached_dd(const cqc_instance *inst, cqc_dtype in_t, cqc_precision prec, const cqc_dd_params *p,
+                 std::shared_ptr<const DdPlan> *out) {
   static std::mutex mu;
   static std::map<std::vector<int64_t>, std::shared_ptr<const DdPlan>> cache;
   std::vector<int64_t> key;
@@ -440,45 +451,17 @@ int cqc_reconstruct_dd(const cqc_instance *inst, cqc_dtype in_t, cqc_precision p
       const DepthPlan &dp = d.depths[rs.depth];
       // merge (FP64 accumulate) the entries over the merged qubits
       MergeArgs ma;
-      std::memset(&ma, 0, sizeof(ma));
       int64_t blocks = 0;
-      std::vector<const void *> merged(d.cut.nsub);
+      std::vector<const void *> merged;
+      std::vector<int64_t> zoomv(d.cut.nsub, 0);
       for (int c = 0; c < d.cut.nsub; ++c) {
         const int f = d.cut.f[c];
-        // every bit active, in local order, and no conversion: the merged
-        // tensor is the entry tensor itself
-        if (dp.mrg_local[c].empty() && (int)dp.act_local[c].size() == f && in_double == acc_double) {
-          merged[c] = inst->entries[c];
-          continue;
-        }
-        MergeDesc &md = ma.d[ma.n++];
-        md.src = inst->entries[c];
-        md.dst = ws + dp.merged_off[c];
-        merged[c] = md.dst;
-        md.rows = int64_t(1) << (2 * d.cut.inc[c].size());
-        md.f = f;
-        md.n_active = (int)dp.act_local[c].size();
-        md.n_merged = (int)dp.mrg_local[c].size();
-        std::vector<int> apos, mpos;
-        for (int k = md.n_active - 1; k >= 0; --k) apos.push_back(f - 1 - dp.act_local[c][k]);
-        for (int k = md.n_merged - 1; k >= 0; --k) mpos.push_back(f - 1 - dp.mrg_local[c][k]);
-        md.active_pos = pack_pos(apos);
-        md.merged_pos = pack_pos(mpos);
-        md.active_shift = contiguous_shift(apos);
-        md.merged_shift = contiguous_shift(mpos);
-        md.log_chunks = merge_log_chunks(md.n_merged);
-        md.seg = merge_segmented(md.n_merged, md.active_shift, md.merged_shift) ? 1 : 0;
-        md.part = md.log_chunks > 0 ? reinterpret_cast<double *>(ws + dp.part_off[c]) : nullptr;
-        int64_t zv = 0;
         for (int j = 0; j < f; ++j) {
-          const int q = d.cut.qubits[c][j];
-          auto it = rs.zoomval.find(q);
-          if (it != rs.zoomval.end() && it->second) zv |= int64_t(1) << (f - 1 - j);
+          auto it = rs.zoomval.find(d.cut.qubits[c][j]);
+          if (it != rs.zoomval.end() && it->second) zoomv[c] |= int64_t(1) << (f - 1 - j);
         }
-        md.zoom_value = zv;
-        md.block_start = blocks;
-        blocks += merge_blocks(md.rows << md.n_active, md.n_merged, md.seg != 0);
       }
+      dd_merge_args(d, dp, inst->entries, ws, in_double, zoomv.data(), nullptr, &ma, &blocks, &merged);
       st = launch_dd_merge(ma, blocks, in_double, acc_double, stream);
       if (!st.good()) return st.code;
       // term sum onto the 2^#active bins (FP64 or FP32 output, FP64 bin mass)

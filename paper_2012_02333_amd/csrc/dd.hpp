@@ -23,6 +23,7 @@ struct MergeDesc {
   int32_t seg;            // short merge over the lowest bits with the active bits right above:
                           //   a row's outputs are consecutive runs of 2^n_merged elements
   int64_t zoom_value;     // fixed bits of the zoomed qubits at their local positions
+  const int64_t *zoom_dev;  // if set: the zoom value is read from device memory instead
   BitPos active_pos;      // active bit j (from least significant) -> local position
   BitPos merged_pos;
   int64_t block_start;
@@ -31,6 +32,8 @@ struct MergeDesc {
 struct MergeArgs {
   MergeDesc d[CQC_MAX_SUB];
   int32_t n;
+  const int32_t *gate;    // device-side predicate, as in ContractArgs
+  int32_t gate_val;
 };
 
 struct TopOut {
@@ -59,7 +62,24 @@ Status launch_dd_merge(const MergeArgs &a, int64_t blocks, bool in_double, bool 
 size_t topk_scratch_bytes(int64_t count, int t);
 // Best t bins ranked strictly after (after_v, after_i) in the order
 // (value descending, index ascending); missing places get index INT64_MAX.
+// gate / gate_val: an optional device-side predicate (see ContractArgs).
 Status launch_topk(const void *bins, bool bins_f32, int64_t count, int t, void *scratch, TopOut *out,
-                   double after_v, int64_t after_i, hipStream_t s);
+                   double after_v, int64_t after_i, hipStream_t s, const int32_t *gate = nullptr,
+                   int32_t gate_val = 0);
+// A top-kTopT request whose parameters live in device memory (written by an
+// earlier kernel of the same stream): when active, rank row `row` of the bins
+// (row * stride elements in), its first `count` bins, strictly after
+// (after_v, after_i), into *out.
+struct TopReq {
+  int32_t active;
+  int32_t row;
+  int64_t count;
+  double after_v;
+  int64_t after_i;
+  TopOut *out;
+};
+// Scratch and grid are sized for max_count bins (any count the request may carry).
+Status launch_topk_req(const void *bins, bool bins_f32, int64_t stride, int64_t max_count, void *scratch,
+                       const TopReq *req, hipStream_t s);
 
 }  // namespace cqc

@@ -109,7 +109,7 @@ BitPos pack_pos(const std::vector<int> &pos) {
 
 Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &entries,
                void *out, bool out_double, double *mass, bool compute_entry_flags,
-               hipStream_t s, bool skip_final) {
+               hipStream_t s, bool skip_final, const int32_t *gate, int32_t gate_val) {
   const Plan &p = L.plan;
   const size_t nt = p.tensors.size();
   std::vector<const void *> tptr(nt, nullptr);
@@ -137,6 +137,8 @@ Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &en
     }
     fa.n = n;
     fa.is_double = L.acc == Acc::F64;
+    fa.gate = gate;
+    fa.gate_val = gate_val;
     if (p.single) {
       fa.d[0].unit = ws + L.t_off[1];
       fa.d[0].unit_flag = reinterpret_cast<int32_t *>(ws + L.f_off[1]);
@@ -151,6 +153,8 @@ Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &en
     std::memset(&a, 0, sizeof(a));
     a.X = tptr[st.x];
     a.Y = tptr[st.y];
+    a.gate = gate;
+    a.gate_val = gate_val;
     if (need_flags) {
       a.flagX = reinterpret_cast<const int32_t *>(ws + L.f_off[st.x]);
       a.flagY = reinterpret_cast<const int32_t *>(ws + L.f_off[st.y]);
@@ -206,7 +210,7 @@ Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &en
       }
       if (mass) a.partials = reinterpret_cast<double *>(ws + L.partials_off);
       CQC_TRY(launch_contract(sa, out_double, cfg, a, s));
-      if (mass) CQC_TRY(launch_mass_final(a.partials, kPartialsPerTile * a.nblocks, mass, s));
+      if (mass) CQC_TRY(launch_mass_final(a.partials, kPartialsPerTile * a.nblocks, mass, s, gate, gate_val));
     }
   }
   return Status::ok();

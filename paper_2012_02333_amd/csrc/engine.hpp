@@ -28,9 +28,11 @@ NetLayout layout_net(const Plan &plan, Acc acc, size_t base);
 // entry tensors must already be computed into their f_off slots unless
 // compute_entry_flags is set.
 // skip_final: run every step but the last (the intermediates the adjoint needs).
+// gate / gate_val: an optional device-side predicate stamped on every launch
+// (see ContractArgs).
 Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &entries,
                void *out, bool out_double, double *mass, bool compute_entry_flags,
-               hipStream_t s, bool skip_final = false);
+               hipStream_t s, bool skip_final = false, const int32_t *gate = nullptr, int32_t gate_val = 0);
 
 DigitMapDev to_dev(const DigitMap &m);
 // Whether any step (all but the last if skip_final) compacts its terms by the

@@ -33,7 +33,8 @@ namespace cqc {
 // per block, which on a multi-XCD part writes back the L2 - full of freshly
 // written outputs - once per block.)
 __global__ __launch_bounds__(1024) void k_mass_final(const double *partials, int64_t count,
-                                                     double *mass) {
+                                                     double *mass, const int32_t *gate, int32_t gate_val) {
+  if (gated_off(gate, gate_val)) return;
   // thread t adds partials t + 1024 (8 q + u) into accumulator u (eight loads
   // in flight per thread), then the accumulators and the threads are combined
   // in a fixed tree: the same order for every call of the same count
@@ -537,6 +538,7 @@ __global__ __launch_bounds__(256) void k_contract_strip_queue(const ContractArgs
 
 template <typename O, int MODE>
 __global__ __launch_bounds__(256) void k_contract_strip(const ContractArgs a) {
+  if (gated_off(a.gate, a.gate_val)) return;
   const int64_t ns = a.nblocks / kStripRows;
   const uint32_t s = a.xcd_remap ? (uint32_t)xcd_remap(blockIdx.x, ns) : blockIdx.x;
   contract_small_strip<O, MODE>(a, s);
@@ -545,6 +547,7 @@ __global__ __launch_bounds__(256) void k_contract_strip(const ContractArgs a) {
 // ---- launch wrappers: one step per launch, or a work queue over many steps
 template <typename T, typename O, int BM, int BN, int WM, int WN, int MODE, bool SMALL>
 __global__ __launch_bounds__(256) void k_contract(const ContractArgs a) {
+  if (gated_off(a.gate, a.gate_val)) return;
   const uint32_t blk = a.xcd_remap ? (uint32_t)xcd_remap(blockIdx.x, a.nblocks) : blockIdx.x;
   if (SMALL) contract_small_tile<T, O, BM, BN, WM, WN, MODE>(a, blk);
   else contract_tile<T, O, BM, BN, WM, WN, MODE>(a, blk);
@@ -619,6 +622,7 @@ __device__ __forceinline__ void flags_chunk(const FlagDesc &d, int64_t rc, bool 
 }
 
 __global__ __launch_bounds__(256) void k_row_flags(const FlagArgs a) {
+  if (gated_off(a.gate, a.gate_val)) return;
   const int64_t bid = blockIdx.x;
   int i = 0;
   while (i + 1 < a.n && bid >= a.d[i + 1].block_start) ++i;
@@ -804,8 +808,9 @@ Status launch_contract(Acc acc, bool out_double, int cfg, const ContractArgs &a,
                     : launch_contract_t<double, float>(cfg, a, s);
 }
 
-Status launch_mass_final(const double *partials, int64_t count, double *mass, hipStream_t s) {
-  return launch("mass_final", k_mass_final, dim3(1), dim3(1024), 0, s, partials, count, mass);
+Status launch_mass_final(const double *partials, int64_t count, double *mass, hipStream_t s,
+                         const int32_t *gate, int32_t gate_val) {
+  return launch("mass_final", k_mass_final, dim3(1), dim3(1024), 0, s, partials, count, mass, gate, gate_val);
 }
 
 Status launch_row_flags_table(const FlagDesc *descs, int32_t n, int64_t total_blocks, bool is_double,

@@ -14,6 +14,7 @@ namespace cqc {
 // combinations one thread takes each output, in ascending m.
 template <typename I, typename O>
 __global__ __launch_bounds__(256) void k_dd_merge(const MergeArgs a) {
+  if (gated_off(a.gate, a.gate_val)) return;
   const int64_t bid = blockIdx.x;
   int i = 0;
   while (i + 1 < a.n && bid >= a.d[i + 1].block_start) ++i;
@@ -24,6 +25,7 @@ __global__ __launch_bounds__(256) void k_dd_merge(const MergeArgs a) {
   const int64_t nmerge = int64_t(1) << d.n_merged;
   const int64_t f = int64_t(1) << d.f;
   const int ash = d.active_shift, msh = d.merged_shift;
+  const int64_t zoom = d.zoom_dev ? *d.zoom_dev : d.zoom_value;
   if (nmerge >= 64) {
     const int lc = d.log_chunks;
     const int64_t w = (bid - d.block_start) * 4 + (threadIdx.x >> 6);
@@ -32,7 +34,7 @@ __global__ __launch_bounds__(256) void k_dd_merge(const MergeArgs a) {
     const int64_t clen = nmerge >> lc;
     const int lane = threadIdx.x & 63;
     const int64_t r = o >> d.n_active, av = o & ((int64_t(1) << d.n_active) - 1);
-    const int64_t base = (ash >= 0 ? av << ash : deposit(av, d.active_pos, d.n_active)) | d.zoom_value;
+    const int64_t base = (ash >= 0 ? av << ash : deposit(av, d.active_pos, d.n_active)) | zoom;
     const I *row = E + r * f;
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     const int64_t m1 = (ch + 1) * clen;
@@ -66,7 +68,7 @@ __global__ __launch_bounds__(256) void k_dd_merge(const MergeArgs a) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int64_t g = g0 + u * 256;
-      v[u] = g < total ? (double)E[(g / rowlen) * f + (d.zoom_value | (g % rowlen))] : 0.0;
+      v[u] = g < total ? (double)E[(g / rowlen) * f + (zoom | (g % rowlen))] : 0.0;
     }
     const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -80,7 +82,7 @@ __global__ __launch_bounds__(256) void k_dd_merge(const MergeArgs a) {
     const int64_t o = (bid - d.block_start) * 256 + threadIdx.x;
     if (o >= nout) return;
     const int64_t r = o >> d.n_active, av = o & ((int64_t(1) << d.n_active) - 1);
-    const int64_t base = (ash >= 0 ? av << ash : deposit(av, d.active_pos, d.n_active)) | d.zoom_value;
+    const int64_t base = (ash >= 0 ? av << ash : deposit(av, d.active_pos, d.n_active)) | zoom;
     const I *row = E + r * f;
     double s = 0.0;
     for (int64_t m = 0; m < nmerge; ++m)
@@ -93,6 +95,7 @@ __global__ __launch_bounds__(256) void k_dd_merge(const MergeArgs a) {
 // chunk order.  Descriptors without chunks have no blocks here.
 template <typename O>
 __global__ __launch_bounds__(256) void k_dd_merge_chunks(const MergeArgs a) {
+  if (gated_off(a.gate, a.gate_val)) return;
   const int64_t bid = blockIdx.x;
   int i = 0;
   while (i + 1 < a.n && bid >= a.d[i + 1].chunk_block_start) ++i;
@@ -215,7 +218,18 @@ __device__ __forceinline__ void block_top(Cand (&m)[kTopT], Cand *out) {
 // ranking can be skipped when more candidates are needed).
 template <typename B>
 __global__ __launch_bounds__(256) void k_topk_stage1(const B *bins, int64_t count, int64_t per_block,
-                                                     Cand *partial, double after_v, int64_t after_i) {
+                                                     Cand *partial, double after_v, int64_t after_i,
+                                                     const int32_t *gate, int32_t gate_val, const TopReq *req,
+                                                     int64_t stride) {
+  if (gated_off(gate, gate_val)) return;
+  if (req) {   // parameters from device memory; the grid covers the largest count
+    if (!req->active) return;
+    bins += (int64_t)req->row * stride;
+    count = req->count;
+    per_block = (count + gridDim.x - 1) / gridDim.x;
+    after_v = req->after_v;
+    after_i = req->after_i;
+  }
   Cand m[kTopT];
 #pragma unroll
   for (int k = 0; k < kTopT; ++k) m[k] = kNoCand;
@@ -249,7 +263,13 @@ __global__ __launch_bounds__(256) void k_topk_stage1(const B *bins, int64_t coun
 // Stage 2: one block of 256 threads ranks all stage-1 candidates (at most
 // 1024 blocks x kTopT), eight loads in flight per thread at a time, and
 // writes the best t.  Four waves keep the block-wide rounds cheap.
-__global__ __launch_bounds__(256) void k_topk_stage2(const Cand *partial, int64_t count, int t, TopOut *out) {
+__global__ __launch_bounds__(256) void k_topk_stage2(const Cand *partial, int64_t count, int t, TopOut *out,
+                                                     const int32_t *gate, int32_t gate_val, const TopReq *req) {
+  if (gated_off(gate, gate_val)) return;
+  if (req) {
+    if (!req->active) return;
+    out = req->out;
+  }
   __shared__ Cand res[kTopT];
   Cand m[kTopT];
 #pragma unroll
@@ -302,7 +322,7 @@ size_t topk_scratch_bytes(int64_t count, int t) {
 }
 
 Status launch_topk(const void *bins, bool bins_f32, int64_t count, int t, void *scratch, TopOut *out,
-                   double after_v, int64_t after_i, hipStream_t s) {
+                   double after_v, int64_t after_i, hipStream_t s, const int32_t *gate, int32_t gate_val) {
   if (count < 1) return Status::fail(CQC_ERR_INVALID_ARG, "top-k over no bins");
   const int64_t blocks = std::min<int64_t>(1024, (count + 2047) / 2048);
   const int64_t per_block = (count + blocks - 1) / blocks;
@@ -310,12 +330,32 @@ Status launch_topk(const void *bins, bool bins_f32, int64_t count, int t, void *
   Cand *partial = static_cast<Cand *>(scratch);
   if (bins_f32)
     CQC_TRY(launch("topk_stage1", k_topk_stage1<float>, dim3((unsigned)blocks), dim3(256), 0, s,
-                   static_cast<const float *>(bins), count, per_block, partial, after_v, after_i));
+                   static_cast<const float *>(bins), count, per_block, partial, after_v, after_i, gate, gate_val,
+                   (const TopReq *)nullptr, (int64_t)0));
   else
     CQC_TRY(launch("topk_stage1", k_topk_stage1<double>, dim3((unsigned)blocks), dim3(256), 0, s,
-                   static_cast<const double *>(bins), count, per_block, partial, after_v, after_i));
+                   static_cast<const double *>(bins), count, per_block, partial, after_v, after_i, gate, gate_val,
+                   (const TopReq *)nullptr, (int64_t)0));
   return launch("topk_stage2", k_topk_stage2, dim3(1), dim3(256), 0, s, static_cast<const Cand *>(partial),
-                blocks * kTopT, t, out);
+                blocks * kTopT, t, out, gate, gate_val, (const TopReq *)nullptr);
+}
+
+Status launch_topk_req(const void *bins, bool bins_f32, int64_t stride, int64_t max_count, void *scratch,
+                       const TopReq *req, hipStream_t s) {
+  if (max_count < 1) return Status::fail(CQC_ERR_INVALID_ARG, "top-k over no bins");
+  const int64_t blocks = std::min<int64_t>(1024, (max_count + 2047) / 2048);
+  Cand *partial = static_cast<Cand *>(scratch);
+  const int32_t *no_gate = nullptr;
+  if (bins_f32)
+    CQC_TRY(launch("topk_req_stage1", k_topk_stage1<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                   static_cast<const float *>(bins), max_count, (int64_t)0, partial, 0.0, (int64_t)0, no_gate, 0,
+                   req, stride));
+  else
+    CQC_TRY(launch("topk_req_stage1", k_topk_stage1<double>, dim3((unsigned)blocks), dim3(256), 0, s,
+                   static_cast<const double *>(bins), max_count, (int64_t)0, partial, 0.0, (int64_t)0, no_gate, 0,
+                   req, stride));
+  return launch("topk_req_stage2", k_topk_stage2, dim3(1), dim3(256), 0, s, static_cast<const Cand *>(partial),
+                blocks * kTopT, kTopT, (TopOut *)nullptr, no_gate, 0, req);
 }
 
 }  // namespace cqc

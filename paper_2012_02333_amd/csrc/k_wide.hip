@@ -110,7 +110,10 @@ __device__ __forceinline__ void label_list(const ContractArgs &a, int64_t batch)
   }
 }
 
-__global__ __launch_bounds__(256) void k_label_list(const ContractArgs a) { label_list(a, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_label_list(const ContractArgs a) {
+  if (gated_off(a.gate, a.gate_val)) return;
+  label_list(a, blockIdx.x);
+}
 
 __global__ __launch_bounds__(256) void k_label_list_table(const ContractArgs *descs, const int64_t *bprefix,
                                                           int ndesc) {
@@ -611,6 +614,7 @@ template <int NP> struct WideOcc { static constexpr int kWaves = 2; };
 template <int NP, typename O, int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WideOcc<NP>::kWaves, WideOcc<NP>::kWaves)))
 void k_wide(const ContractArgs a) {
+  if (gated_off(a.gate, a.gate_val)) return;
   StridedSeq seq(a);
   wide_run<NP, O, MODE>(seq);
 }

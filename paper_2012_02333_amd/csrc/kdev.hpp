@@ -51,6 +51,9 @@ __device__ inline int64_t deposit(int64_t v, const BitPos &pos, int nbits) {
   return out;
 }
 
+// A launch whose device-side predicate is set and false does nothing.
+__device__ __forceinline__ bool gated_off(const int32_t *gate, int32_t val) { return gate && *gate != val; }
+
 // A row is live if any of its chunk flags is set.
 __device__ __forceinline__ int row_live(const int32_t *flags, int nch, int row) {
   int any = 0;

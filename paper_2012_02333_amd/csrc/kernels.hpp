@@ -57,6 +57,11 @@ struct ContractArgs {
   int32_t *counts;   // [nbatch] live labels
   int32_t list_ld;   // pairs per batch entry: 4^nS rounded up to a multiple of 32
   int64_t nbatch;
+  // device-side predicate: when gate is set, the launch does nothing unless
+  // *gate == gate_val (a dynamic-definition query enqueues the kernels of
+  // every depth a recursion can have, and runs only the one its pick chose)
+  const int32_t *gate;
+  int32_t gate_val;
 };
 
 // FP64 mass partials: every wave of a final-step tile (four per block) stores
@@ -94,6 +99,8 @@ struct FlagArgs {
   FlagDesc d[CQC_MAX_SUB + 1];
   int32_t n;
   int32_t is_double;
+  const int32_t *gate;   // as in ContractArgs
+  int32_t gate_val;
 };
 
 // Arithmetic of a plan.  BF16X6 and BF16X3 keep every tensor in FP32 and
@@ -126,7 +133,8 @@ inline Acc step_acc(Acc acc, bool wide_ok, int nS) {
 }
 
 Status launch_row_flags(const FlagArgs &a, int64_t total_blocks, hipStream_t s);
-Status launch_mass_final(const double *partials, int64_t count, double *mass, hipStream_t s);
+Status launch_mass_final(const double *partials, int64_t count, double *mass, hipStream_t s,
+                         const int32_t *gate = nullptr, int32_t gate_val = 0);
 
 // One launch over many contraction steps of the same kernel configuration:
 // descs[d] in device memory, prefix[d] = first queue item of step d (items of

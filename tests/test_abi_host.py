@@ -256,3 +256,24 @@ def test_noalloc_rejects_before_enqueue():
     ok = _inst(24, [11, 13], [(0, 1), (0, 1)], list(range(24)))
     assert L.cqc_reconstruct_fd_noalloc(ctypes.byref(ok), 1, 0, 0, 9, None) == 1   # unknown precision
     assert L.cqc_reconstruct_fd_noalloc(None, 1, 0, 0, 1, None) == 1
+
+
+def test_dd_query_validation():
+    """The device-resident DD query plans on the host: one bin per recursion
+    only, and the same parameter checks as the host-driven query."""
+    L = _lib.lib()
+    inst = _inst(12, [6, 6], [(0, 1), (0, 1)], list(range(12)))
+    nb = ctypes.c_size_t(0)
+    ok = _lib.CqcDDParams(4, 5, None, 0, 1, 0)
+    assert L.cqc_dd_query_workspace_size(ctypes.byref(inst), 0, 1, ctypes.byref(ok), ctypes.byref(nb)) == 0
+    assert nb.value > 0
+    rounds = _lib.CqcDDParams(4, 5, None, 0, 4, 0)
+    assert L.cqc_dd_query_workspace_size(ctypes.byref(inst), 0, 1, ctypes.byref(rounds), ctypes.byref(nb)) == 3
+    bad = _lib.CqcDDParams(0, 5, None, 0, 1, 0)
+    assert L.cqc_dd_query_workspace_size(ctypes.byref(inst), 0, 1, ctypes.byref(bad), ctypes.byref(nb)) == 1
+    h = ctypes.c_void_p(0)
+    # NULL outputs, and a workspace smaller than the query needs: nothing enqueued
+    assert L.cqc_dd_query_create(ctypes.byref(inst), 0, 1, ctypes.byref(ok), None, None, None, None, 0, None,
+                                 ctypes.byref(h)) == 1
+    assert L.cqc_dd_query_create(ctypes.byref(inst), 0, 1, ctypes.byref(ok), 0x1000, 0x2000, 0x3000, 0x4000,
+                                 16, None, ctypes.byref(h)) == 4

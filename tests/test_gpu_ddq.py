@@ -1,0 +1,123 @@
+"""The device-resident dynamic-definition query (cqc_dd_query_*): every pick
+of Algorithm 1 made by a kernel, the whole query enqueued at once.
+
+It runs the same kernels on the same inputs as the host-driven query with one
+bin per round, so its bins, records, masses and recursion count must equal
+that query's bit for bit - for every search strategy, FP64 and FP32 term sums,
+FP64 and FP32 bins, queries whose candidate windows run out and are refilled
+on the device, and searches that stop early; a captured graph replays it."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import dd
+from tests.gpu_util import to_dev
+
+pytestmark = pytest.mark.gpu
+cqc = pytest.importorskip("paper_2012_02333_amd")
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _same(host, dev, bins_h, bins_d):
+    """Equal records, and equal bins: the first 2^n_active of each row (a
+    recursion with fewer active qubits leaves the rest of its row unwritten)."""
+    assert len(host) == len(dev)
+    for r, rec in enumerate(host):
+        nb = 2 ** rec["n_active"]
+        assert torch.equal(bins_h[r, :nb], bins_d[r, :nb]), r
+    for r, (a, b) in enumerate(zip(host, dev)):
+        assert a["parent"] == b["parent"], r
+        assert a["n_active"] == b["n_active"] and a["role"] == b["role"], r
+        assert a["mass"] == b["mass"] or (a["mass"] != a["mass"] and b["mass"] != b["mass"]), r
+
+
+CASES = {
+    # (own, bridges, layers, n_active, recursions): a deeper tree; windows that
+    # run out and are refilled (16 bins, 13 picks from the first recursion);
+    # a search that stops early (fewer candidates than recursions)
+    "deep": ((3, 2, 3), (2, 2), 4, 3, 9),
+    "refill": ((3, 3), (2,), 4, 4, 14),
+    "stops": ((2, 2), (1,), 4, 3, 12),
+}
+
+
+@pytest.mark.parametrize("strategy", ["heaviest", "dfs", "bfs"])
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("prec,dt,bins_dt", [("fp64", torch.float64, torch.float64),
+                                             ("fp32", torch.float32, torch.float64),
+                                             ("fp32", torch.float32, torch.float32)])
+def test_ddq_equals_host_query(strategy, case, prec, dt, bins_dt):
+    _gpu()
+    own, bridges, layers, a, R = CASES[case]
+    inst = W.make_instance(own, bridges, layers, seed=91)
+    _, ents = to_dev(inst.entries, dt)
+    cut = cqc.CutMap.from_workload(inst.cut)
+    bins_h, recs_h = cqc.reconstruct_dd(ents, cut, a, R, precision=prec, strategy=strategy, bins_dtype=bins_dt)
+    q = cqc.DDQuery(ents, cut, a, R, precision=prec, strategy=strategy, bins_dtype=bins_dt)
+    q.run()
+    torch.cuda.synchronize()
+    bins_d, recs_d = q.result()
+    print(f"{case} {strategy} {prec}: {len(recs_d)} of {R} recursions")
+    _same(recs_h, recs_d, bins_h, bins_d)
+    if case == "stops":
+        assert len(recs_d) < R
+    if case == "refill" and strategy == "heaviest":
+        assert sum(1 for r in recs_d if r["parent"][0] == 0) > 8   # more picks than one window
+
+
+def test_ddq_first_active_and_repeat_runs():
+    """An explicit first active set; a second run of the same prepared query
+    (state reset on the device) gives the same result."""
+    _gpu()
+    inst = W.make_instance((3, 2, 3), (2, 2), 4, seed=92)
+    _, ents = to_dev(inst.entries, torch.float64)
+    cut = cqc.CutMap.from_workload(inst.cut)
+    first = [9, 2, 5]
+    bins_h, recs_h = cqc.reconstruct_dd(ents, cut, 3, 7, first_active=first, precision="fp64")
+    q = cqc.DDQuery(ents, cut, 3, 7, first_active=first, precision="fp64")
+    for _ in range(2):
+        q.bins.fill_(-1.0)
+        q.run()
+        torch.cuda.synchronize()
+        bins_d, recs_d = q.result()
+        _same(recs_h, recs_d, bins_h, bins_d)
+
+
+def test_ddq_graph_replay_c4():
+    """The DD workload (n=40, K=8, 2^20 bins, 5 recursions), captured in a
+    graph: every replay (with eager work and the outputs overwritten in
+    between) equals the host-driven query."""
+    _gpu()
+    inst = W.config_instance("c4")
+    a, R = W.DD_C4["n_active"], W.DD_C4["n_recursions"]
+    _, ents = to_dev(inst.entries, torch.float32)
+    cut = cqc.CutMap.from_workload(inst.cut)
+    bins_h, recs_h = cqc.reconstruct_dd(ents, cut, a, R, precision="fp32")
+    q = cqc.DDQuery(ents, cut, a, R, precision="fp32")
+    q.run()
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        q.run()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            q.run()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        q.bins.fill_(-1.0)
+        q.records.zero_()
+        q.n_done.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        bins_d, recs_d = q.result()
+        _same(recs_h, recs_d, bins_h, bins_d)
