@@ -346,6 +346,12 @@ int cqc_reconstruct_dd(const cqc_instance *inst, cqc_dtype in_t, cqc_precision p
  * cqc_dd_query_run enqueues one complete query (only kernel launches: no
  * synchronisation, no allocation, no host read); records past n_done are
  * not written.  Runs of one query on different streams must not overlap.
+ * cqc_dd_query_run_range enqueues recursions [first, first + count) only:
+ * first = 0 starts a new search; first > 0 resumes the search the query's
+ * workspace holds after recursion first - 1 (the bins, records and query
+ * state left by earlier runs of this query must be unmodified), so a search
+ * can be run in pieces and inspected in between with results equal to one
+ * run.  Resuming a search that stopped early runs nothing.
  * cqc_dd_query_destroy frees the host-side handle only. */
 typedef struct cqc_dd_query_s *cqc_dd_query;
 int cqc_dd_query_workspace_size(const cqc_instance *inst, cqc_dtype in_t, cqc_precision prec,
@@ -354,6 +360,7 @@ int cqc_dd_query_create(const cqc_instance *inst, cqc_dtype in_t, cqc_precision 
                         const cqc_dd_params *p, void *bins, cqc_dd_record *records, int32_t *n_done,
                         void *workspace, size_t ws_bytes, hipStream_t stream, cqc_dd_query *out);
 int cqc_dd_query_run(cqc_dd_query q, hipStream_t stream);
+int cqc_dd_query_run_range(cqc_dd_query q, int32_t first, int32_t count, hipStream_t stream);
 int cqc_dd_query_destroy(cqc_dd_query q);
 
 /* Adjoint of the FD build: given G = dL/dp (DEVICE [2^n] per instance, dtype

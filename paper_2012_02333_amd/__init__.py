@@ -453,6 +453,12 @@ class DDQuery:
         s = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
         _lib.check(_lib.lib().cqc_dd_query_run(self._h, s))
 
+    def run_range(self, first, count, stream=None):
+        """Recursions [first, first + count): first = 0 starts a search, a
+        later first resumes the one this query holds."""
+        s = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        _lib.check(_lib.lib().cqc_dd_query_run_range(self._h, int(first), int(count), s))
+
     def result(self):
         done = int(self.n_done.cpu()[0])
         raw = self.records.cpu().numpy().tobytes()

@@ -22,7 +22,7 @@ EXPORTS = [
     "cqc_batch_backward_workspace_size", "cqc_batch_backward_create", "cqc_batch_backward_run",
     "cqc_batch_backward_destroy", "cqc_build_entries", "cqc_chi2", "cqc_xent_grad", "cqc_tune_reset",
     "cqc_reconstruct_fd_noalloc", "cqc_dd_query_workspace_size", "cqc_dd_query_create", "cqc_dd_query_run",
-    "cqc_dd_query_destroy",
+    "cqc_dd_query_destroy", "cqc_dd_query_run_range",
 ]
 NOALLOC_WORKSPACE_BYTES = 32 << 20
 
@@ -110,6 +110,7 @@ def lib():
     L.cqc_dd_query_create.argtypes = [P(CqcInstance), ctypes.c_int, ctypes.c_int, P(CqcDDParams), vp, vp, vp, vp,
                                       sz, vp, P(vp)]
     L.cqc_dd_query_run.argtypes = [vp, vp]
+    L.cqc_dd_query_run_range.argtypes = [vp, i32, i32, vp]
     L.cqc_dd_query_destroy.argtypes = [vp]
     L.cqc_reconstruct_fd_noalloc.argtypes = [P(CqcInstance), i32, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
     for name in EXPORTS:

@@ -100,7 +100,9 @@ static Status ddq_create(const cqc_instance *inst, cqc_dtype in_t, cqc_precision
   return Status::ok();
 }
 
-static Status ddq_run(const cqc_dd_query_s *q, hipStream_t s) {
+// Enqueues recursions [k0, k1); k0 = 0 starts a new search (state reset),
+// k0 > 0 continues the one the query state holds.
+static Status ddq_run(const cqc_dd_query_s *q, int k0, int k1, hipStream_t s) {
   const DdPlan &d = *q->plan;
   const bool acc_double = d.acc == Acc::F64;
   const int64_t stride = int64_t(1) << d.a;
@@ -108,8 +110,8 @@ static Status ddq_run(const cqc_dd_query_s *q, hipStream_t s) {
   DdqState *st = q->st;
   char *ws = q->ws;
   const int D = (int)d.depths.size();
-  CQC_TRY(launch_ddq_init(st, s));
-  for (int k = 0; k < d.R; ++k) {
+  if (k0 == 0) CQC_TRY(launch_ddq_init(st, s));
+  for (int k = k0; k < k1; ++k) {
     if (k > 0) {
       CQC_TRY(launch_topk_req(q->bins, d.bins_f32, stride, stride, ws + d.topk_off, &st->refill, s));
       CQC_TRY(launch_ddq_pick(st, k, s));
@@ -169,7 +171,14 @@ int cqc_dd_query_create(const cqc_instance *inst, cqc_dtype in_t, cqc_precision 
 
 int cqc_dd_query_run(cqc_dd_query q, hipStream_t stream) {
   if (!q) return Status::fail(CQC_ERR_INVALID_ARG, "query is NULL").code;
-  return ddq_run(q, stream).code;
+  return ddq_run(q, 0, q->plan->R, stream).code;
+}
+
+int cqc_dd_query_run_range(cqc_dd_query q, int32_t first, int32_t count, hipStream_t stream) {
+  if (!q) return Status::fail(CQC_ERR_INVALID_ARG, "query is NULL").code;
+  if (first < 0 || count < 0 || (int64_t)first + count > q->plan->R)
+    return Status::fail(CQC_ERR_INVALID_ARG, "recursion range outside [0, n_recursions)").code;
+  return ddq_run(q, first, first + count, stream).code;
 }
 
 int cqc_dd_query_destroy(cqc_dd_query q) {

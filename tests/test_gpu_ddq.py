@@ -121,3 +121,46 @@ def test_ddq_graph_replay_c4():
         torch.cuda.synchronize()
         bins_d, recs_d = q.result()
         _same(recs_h, recs_d, bins_h, bins_d)
+
+
+@pytest.mark.parametrize("strategy", ["heaviest", "dfs"])
+def test_ddq_resume_in_pieces(strategy):
+    """A search run as recursions [0, 3), then [3, 6), then [6, R) (the
+    records inspected in between) equals one run; resuming a search that
+    stopped early adds nothing."""
+    _gpu()
+    own, bridges, layers, a, R = CASES["deep"]
+    inst = W.make_instance(own, bridges, layers, seed=93)
+    _, ents = to_dev(inst.entries, torch.float64)
+    cut = cqc.CutMap.from_workload(inst.cut)
+    q = cqc.DDQuery(ents, cut, a, R, precision="fp64", strategy=strategy)
+    q.run()
+    torch.cuda.synchronize()
+    bins_1, recs_1 = q.result()
+    bins_1 = bins_1.clone()
+    q2 = cqc.DDQuery(ents, cut, a, R, precision="fp64", strategy=strategy)
+    q2.run_range(0, 3)
+    torch.cuda.synchronize()
+    assert len(q2.result()[1]) == 3
+    q2.run_range(3, 3)
+    torch.cuda.synchronize()
+    assert q2.result()[1] == recs_1[:6]
+    q2.run_range(6, R - 6)
+    torch.cuda.synchronize()
+    bins_2, recs_2 = q2.result()
+    _same(recs_1, recs_2, bins_1, bins_2)
+    # a search that stopped: a further piece runs nothing
+    own, bridges, layers, a, R = CASES["stops"]
+    inst = W.make_instance(own, bridges, layers, seed=94)
+    _, ents = to_dev(inst.entries, torch.float64)
+    cut = cqc.CutMap.from_workload(inst.cut)
+    q3 = cqc.DDQuery(ents, cut, a, R, precision="fp64", strategy=strategy)
+    q3.run_range(0, R - 1)
+    torch.cuda.synchronize()
+    n1 = len(q3.result()[1])
+    assert n1 < R - 1
+    q3.run_range(R - 1, 1)
+    torch.cuda.synchronize()
+    assert len(q3.result()[1]) == n1
+    with pytest.raises(cqc.CqcError):
+        q3.run_range(R - 1, 2)
