@@ -66,6 +66,22 @@ NetLayout layout_net(const Plan &plan, Acc acc, size_t base) {
       off = align_up(off + wide_list_bytes((int)st.S.size(), st.nbatch), 256);
     }
   }
+  // bfloat16 parts of the operands of split-form wide steps (split once per
+  // call, not once per tile)
+  L.xs_off.assign(plan.steps.size(), SIZE_MAX);
+  L.ys_off.assign(plan.steps.size(), SIZE_MAX);
+  if (is_split(acc)) {
+    for (size_t i = 0; i < plan.steps.size(); ++i) {
+      const Step &st = plan.steps[i];
+      if (!is_split(step_acc(acc, st.wide_ok(), (int)st.S.size()))) continue;
+      const size_t parts = (size_t)split_parts(acc);
+      const TensorSpec &X = plan.tensors[st.x], &Y = plan.tensors[st.y];
+      L.xs_off[i] = off;
+      off = align_up(off + parts * 2 * (size_t)(X.rows() * X.cols()), 256);
+      L.ys_off[i] = off;
+      off = align_up(off + parts * 2 * (size_t)(Y.rows() * Y.cols()), 256);
+    }
+  }
   L.bytes = off;
   return L;
 }
@@ -187,6 +203,18 @@ Status run_net(const NetLayout &L, char *ws, const std::vector<const void *> &en
     a.tilesN = (int)(((int64_t(1) << st.logN) + sh.bn - 1) / sh.bn);
     a.nblocks = (int64_t)a.tilesM * a.tilesN * st.nbatch;
     a.xcd_remap = (xcd && a.nblocks % 8 == 0) ? 1 : 0;
+    if (cfg == kTileW && is_split(sa) && L.xs_off[i] != SIZE_MAX && !gate) {
+      // split both operands into their bfloat16 parts once, for every tile
+      const TensorSpec &X = p.tensors[st.x], &Y = p.tensors[st.y];
+      a.xplane = X.rows() * X.cols();
+      a.yplane = Y.rows() * Y.cols();
+      a.Xs = ws + L.xs_off[i];
+      a.Ys = ws + L.ys_off[i];
+      CQC_TRY(launch_presplit(split_parts(sa), static_cast<const float *>(a.X), ws + L.xs_off[i], a.xplane,
+                              a.xplane, s));
+      CQC_TRY(launch_presplit(split_parts(sa), static_cast<const float *>(a.Y), ws + L.ys_off[i], a.yplane,
+                              a.yplane, s));
+    }
     if (!last) {
       a.mode = kModeIntermediate;
       a.Z = ws + L.t_off[st.z];

@@ -18,6 +18,8 @@ struct NetLayout {
   std::vector<int64_t> nblocks;
   size_t partials_off = 0;
   std::vector<size_t> list_off;  // per step: label lists of the wide kernel (SIZE_MAX: none)
+  std::vector<size_t> xs_off, ys_off;  // per step: bfloat16 parts of X and Y for a split-form
+                                       //   wide step (SIZE_MAX: none)
   size_t bytes = 0;            // end offset (relative to the layout base)
 };
 

@@ -248,8 +248,12 @@ struct QueueSeq {
 };
 
 // NP: bfloat16 parts per operand (3: BF16X6, 2: BF16X3), 0 for the FP32 form.
-template <int NP, typename O, int MODE, class Seq>
+// PS (split forms): the operands come already split into bfloat16 part planes
+// (ContractArgs::Xs, Ys), so staging only repacks them; otherwise every tile
+// splits the FP32 operands it stages.
+template <int NP, typename O, int MODE, bool PS, class Seq>
 __device__ __forceinline__ void wide_run(Seq &seq) {
+  static_assert(!PS || NP > 0, "pre-split operands are for the split forms");
   static_assert(NP == 0 || NP == 2 || NP == 3, "FP32, BF16X3 or BF16X6");
   // operand staging area: FP32 [256 columns][kF32Ld]; split forms [NP parts][256][kB16Ld]
   constexpr int kOpBytes = NP ? NP * 2 * kWB * kB16Ld * 2 : 2 * kWB * kF32Ld * 4;
@@ -295,7 +299,8 @@ __device__ __forceinline__ void wide_run(Seq &seq) {
   // read element 0), so all kWC loads of a chunk are in flight together; the
   // invalid ones are zeroed only when the chunk is written to LDS.
   constexpr int kH = kWC / 2;      // terms per staging wave and chunk
-  float pre[2][kH][2];
+  float pre[2][PS ? 1 : kH][2];
+  uint32_t pre16[2][PS ? kH : 1][PS ? NP : 1];   // pre-split: parts of the lane's two columns, per term
   uint32_t okrow[2] = {0u, 0u};    // wave-uniform: term k of this wave's half is live
   bool colok[2][2] = {{true, true}, {true, true}};   // this lane's two columns lie inside the operand
   auto gload = [&](auto B, const ContractArgs &a, const WideTile &t, int ch) {
@@ -316,12 +321,25 @@ __device__ __forceinline__ void wide_run(Seq &seq) {
     okrow[b] = nv >= kH ? 0xffffu : (nv <= 0 ? 0u : (1u << nv) - 1u);
     // ld is a power of two >= 2 (steps with a one-column operand do not run
     // here): both columns are inside or both outside
-    const uint32_t col4 = colok[b][1] ? (uint32_t)colv * 4u : 0u;
+    if constexpr (PS) {
+      // part p of the two columns: 4 bytes at plane p, row offset / 2 (the
+      // list holds FP32 byte offsets)
+      const char *pb = reinterpret_cast<const char *>(roleX ? uni(a.Xs) : uni(a.Ys));
+      const int64_t plane2 = 2 * (roleX ? uni(a.xplane) : uni(a.yplane));
+      const uint32_t col2 = colok[b][1] ? (uint32_t)colv * 2u : 0u;
 #pragma unroll
-    for (int k = 0; k < kH; ++k) {
-      const f32x2 v = *(gptr<const f32x2>)(gbl(srcb) + (offs[k] + col4));
-      pre[b][k][0] = v[0];
-      pre[b][k][1] = v[1];
+      for (int k = 0; k < kH; ++k)
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+          pre16[b][k][p] = *(gptr<const uint32_t>)(gbl(pb) + p * plane2 + ((offs[k] >> 1) + col2));
+    } else {
+      const uint32_t col4 = colok[b][1] ? (uint32_t)colv * 4u : 0u;
+#pragma unroll
+      for (int k = 0; k < kH; ++k) {
+        const f32x2 v = *(gptr<const f32x2>)(gbl(srcb) + (offs[k] + col4));
+        pre[b][k][0] = v[0];
+        pre[b][k][1] = v[1];
+      }
     }
   };
   auto stage = [&](auto B) {
@@ -342,6 +360,30 @@ __device__ __forceinline__ void wide_run(Seq &seq) {
             *reinterpret_cast<float4 *>(cp + 8 * g8 + 4 * h) =
                 make_float4(val(8 * g8 + h, j), val(8 * g8 + 2 + h, j), val(8 * g8 + 4 + h, j), val(8 * g8 + 6 + h, j));
       }
+    } else if constexpr (PS) {
+      // repack: the 8 terms of column j of one part, two terms per 32 bits
+      // (low half = column 2 lane, high half = column 2 lane + 1 in the
+      // loaded words); dead terms and outside columns give zeros
+      __bf16 *bp = reinterpret_cast<__bf16 *>(smem);
+      auto w = [&](int k, int p) -> uint32_t {
+        return (colok[b][0] && ((okrow[b] >> k) & 1u)) ? pre16[b][k][p] : 0u;
+      };
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int o = 0; o < 2; ++o) {
+          const int pos = 16 * half + 8 * o;
+#pragma unroll
+          for (int p = 0; p < NP; ++p) {
+            uint32_t q[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const uint32_t lo = w(8 * o + 2 * u, p), hi = w(8 * o + 2 * u + 1, p);
+              q[u] = j == 0 ? ((lo & 0xffffu) | (hi << 16)) : ((lo >> 16) | (hi & 0xffff0000u));
+            }
+            *reinterpret_cast<uint4 *>(bp + (p * 2 * kWB + col0 + j) * kB16Ld + pos) = make_uint4(q[0], q[1], q[2], q[3]);
+          }
+        }
     } else {
       __bf16 *bp = reinterpret_cast<__bf16 *>(smem);
 #pragma unroll
@@ -611,12 +653,12 @@ __device__ __forceinline__ void wide_run(Seq &seq) {
 // the LDS but not the registers without spilling, and measure slower.
 template <int NP> struct WideOcc { static constexpr int kWaves = 2; };
 
-template <int NP, typename O, int MODE>
+template <int NP, typename O, int MODE, bool PS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WideOcc<NP>::kWaves, WideOcc<NP>::kWaves)))
 void k_wide(const ContractArgs a) {
   if (gated_off(a.gate, a.gate_val)) return;
   StridedSeq seq(a);
-  wide_run<NP, O, MODE>(seq);
+  wide_run<NP, O, MODE, PS>(seq);
 }
 
 template <int NP, int MODE>
@@ -626,7 +668,35 @@ void k_wide_queue(const ContractArgs *__restrict__ descs,
                                                     unsigned long long *queue, int64_t total) {
   __shared__ int64_t slot[2];
   QueueSeq seq{descs, prefix, ndesc, queue, total, slot};
-  wide_run<NP, float, MODE>(seq);
+  wide_run<NP, float, MODE, false>(seq);
+}
+
+// The split of the wide kernel's staging (split3), once per operand element:
+// part p of element i at dst[p * plane + i].  Four elements per thread.
+template <int NP, bool VEC>
+__global__ __launch_bounds__(256) void k_presplit(const float *src, __bf16 *dst, int64_t count, int64_t plane) {
+  const int64_t n4 = count >> 2;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x) {
+    float v[4];
+    if constexpr (VEC) {
+      const float4 q = reinterpret_cast<const float4 *>(src)[i];
+      v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] = src[4 * i + e];
+    }
+    __bf16 part[3][4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) split3(v[e], &part[0][e], &part[1][e], &part[2][e]);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+      bf16x4 o;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) o[e] = part[p][e];
+      *reinterpret_cast<bf16x4 *>(dst + p * plane + 4 * i) = o;
+    }
+  }
 }
 // ---------------------------------------------------------------------------
 bool wide_fits(const ContractArgs &a) {
@@ -672,12 +742,20 @@ template <> struct WideNames<3> {
   static constexpr const char *fin = "wide_bf16x6_final", *mid = "wide_bf16x6_inter", *queue = "wide_bf16x6_queue";
 };
 
+template <int NP, typename O, bool PS>
+static Status launch_wide_ps(const ContractArgs &a, hipStream_t s) {
+  if (a.mode == kModeFinalBlocked) return launch_persistent(WideNames<NP>::fin, k_wide<NP, O, kModeFinalBlocked, PS>, a, s);
+  if (a.mode == kModeFinalDeposit) return launch_persistent(WideNames<NP>::fin, k_wide<NP, O, kModeFinalDeposit, PS>, a, s);
+  return launch_persistent(WideNames<NP>::mid, k_wide<NP, float, kModeIntermediate, PS>, a, s);
+}
+
 template <int NP, typename O>
 static Status launch_wide_t(const ContractArgs &a, hipStream_t s) {
   CQC_TRY(launch("label_list", k_label_list, dim3((unsigned)a.nbatch), dim3(256), 0, s, a));
-  if (a.mode == kModeFinalBlocked) return launch_persistent(WideNames<NP>::fin, k_wide<NP, O, kModeFinalBlocked>, a, s);
-  if (a.mode == kModeFinalDeposit) return launch_persistent(WideNames<NP>::fin, k_wide<NP, O, kModeFinalDeposit>, a, s);
-  return launch_persistent(WideNames<NP>::mid, k_wide<NP, float, kModeIntermediate>, a, s);
+  if constexpr (NP > 0) {
+    if (a.Xs && a.Ys) return launch_wide_ps<NP, O, true>(a, s);
+  }
+  return launch_wide_ps<NP, O, false>(a, s);
 }
 
 template <int NP>
@@ -695,6 +773,21 @@ Status launch_contract_wide(int parts, bool out_double, const ContractArgs &a, h
     case 2: return launch_wide_np<2>(out_double, a, s);
     case 3: return launch_wide_np<3>(out_double, a, s);
     default: return Status::fail(CQC_ERR_INVALID_ARG, "wide contraction: unknown operand split");
+  }
+}
+
+Status launch_presplit(int parts, const float *src, void *dst, int64_t count, int64_t plane, hipStream_t s) {
+  if (count % 4 || plane < count) return Status::fail(CQC_ERR_INVALID_ARG, "presplit: bad element count");
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((count / 4 + 255) / 256, 8192));
+  const bool vec = (reinterpret_cast<uintptr_t>(src) & 15) == 0;
+  __bf16 *d = static_cast<__bf16 *>(dst);
+  const dim3 g((unsigned)blocks), b(256);
+  switch (parts) {
+    case 2: return vec ? launch("presplit", k_presplit<2, true>, g, b, 0, s, src, d, count, plane)
+                       : launch("presplit", k_presplit<2, false>, g, b, 0, s, src, d, count, plane);
+    case 3: return vec ? launch("presplit", k_presplit<3, true>, g, b, 0, s, src, d, count, plane)
+                       : launch("presplit", k_presplit<3, false>, g, b, 0, s, src, d, count, plane);
+    default: return Status::fail(CQC_ERR_INVALID_ARG, "presplit: parts must be 2 or 3");
   }
 }
 

@@ -62,6 +62,12 @@ struct ContractArgs {
   // every depth a recursion can have, and runs only the one its pick chose)
   const int32_t *gate;
   int32_t gate_val;
+  // split-BF16 wide steps: the operands already split into bfloat16 parts,
+  // part p of X at Xs + p * xplane elements (same layout as X), or null (the
+  // wide kernel splits while staging)
+  const void *Xs;
+  const void *Ys;
+  int64_t xplane, yplane;
 };
 
 // FP64 mass partials: every wave of a final-step tile (four per block) stores
@@ -168,6 +174,9 @@ Status launch_row_flags_table(const FlagDesc *descs, int32_t n, int64_t total_bl
 Status launch_mass_table(const MassDesc *descs, int32_t n, hipStream_t s);
 Status launch_contract(Acc acc, bool out_double, int cfg, const ContractArgs &a, hipStream_t s);
 Status launch_contract_wide(int parts, bool out_double, const ContractArgs &a, hipStream_t s);
+// Splits `count` floats (a multiple of 4) into `parts` bfloat16 planes of
+// `plane` elements each (the same split as the wide kernel's staging).
+Status launch_presplit(int parts, const float *src, void *dst, int64_t count, int64_t plane, hipStream_t s);
 // Whether both operands of a step are within the wide kernel's 2^30-element addressing.
 bool wide_fits(const ContractArgs &a);
 Status launch_contract_wide_queue(int parts, int mode, const QueueLaunch &q, hipStream_t s);
