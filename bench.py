@@ -569,36 +569,80 @@ def bench_batch(args, torch, cqc, W):
         bwd.run()
     steps = args.steps or 20
     warmup = args.warmup if args.warmup is not None else 3
+
+    def graphed(fn):
+        fn()
+        torch.cuda.synchronize()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(s):
+            fn()
+            torch.cuda.synchronize()
+            with torch.cuda.graph(graph, stream=s):
+                fn()
+        torch.cuda.synchronize()
+        return graph
+
+    graph2 = graphed(body)
+    ms2 = _sync_time(lambda i: graph2.replay(), steps, warmup, torch)
+    kt2 = _traced(lambda i: body(), 3, cqc, torch)
+    del graph2
+    # the same step with the cross-entropy gradient computed inside the
+    # kernels that produce p (cqc_batch_create_xent): p itself is not kept
+    t_split = list(torch.split(t_flat, sizes))
+    xb = cqc.Batch(ents, cuts, precision="fp32", targets=t_split, grads=grads_out, keep_outputs=False,
+                   with_mass=False)
+    xbwd = cqc.BatchBackward(xb, grads_out)
+
+    def fused():
+        xb.run()
+        xbwd.run()
+    graph = graphed(fused)
+    ms = _sync_time(lambda i: graph.replay(), steps, warmup, torch)
+    kt = _traced(lambda i: fused(), 3, cqc, torch)
+    # identical gradients to the two-pass step
     body()
     torch.cuda.synchronize()
-    s = torch.cuda.Stream()
-    s.wait_stream(torch.cuda.current_stream())
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.stream(s):
-        body()
-        torch.cuda.synchronize()
-        with torch.cuda.graph(graph, stream=s):
-            body()
+    g_two = [[g.clone() for g in gl] for gl in bwd.grads]
+    graph.replay()
     torch.cuda.synchronize()
-    ms = _sync_time(lambda i: graph.replay(), steps, warmup, torch)
-    kt = _traced(lambda i: body(), 3, cqc, torch)
+    same = all(torch.equal(a, b) for ga, gb in zip(g_two, xbwd.grads) for a, b in zip(ga, gb))
+    del graph
+    xl = cqc.Batch(ents, cuts, precision="fp32", targets=t_split, grads=grads_out, keep_outputs=False,
+                   with_loss=True)
+    xlb = cqc.BatchBackward(xl, grads_out)
+
+    def fused_loss():
+        xl.run()
+        xlb.run()
+    graph_l = graphed(fused_loss)
+    ms_l = _sync_time(lambda i: graph_l.replay(), steps, warmup, torch)
+    del graph_l
     outputs = sum(2 ** i.n for i in insts)
-    # roofline of the step: per instance the larger of its HBM time (write p,
-    # read p, t and G for the adjoint) and its FP32 matrix-core time
+    # roofline of the step: per instance the larger of its HBM time (read t,
+    # write G, read G in the adjoint: 12 bytes per output, p never leaving the
+    # chip) and its FP32 matrix-core time (forward and both adjoint sides)
     roof_s = 0.0
     for c, i in zip(cuts, insts):
         _, macs = cqc.cost(c)
-        byts = 4.0 * 2 ** i.n * 5
+        byts = 4.0 * 2 ** i.n * 3
         roof_s += max(byts / (HBM_PEAK_GBS * 1e9), 3 * 2 * macs / (FP32_PEAK_TFS * 1e12))
     name, (cnt, tot) = max(kt.items(), key=lambda kv: kv[1][1])
     roof = {"bound": "mixed", "achieved": roof_s * 1e3, "peak": ms, "unit": "ms per step (roofline vs measured)",
             "frac": roof_s * 1e3 / ms, "traffic": None, "dominant_kernel": name,
             "dominant_kernel_ms_per_step": tot / 3,
-            "note": "per instance max(HBM bytes / 8 TB/s, 3 x forward flops / 157.3 TF)"}
+            "note": "per instance max(12 bytes per output / 8 TB/s, 3 x forward flops / 157.3 TF)"}
     out = _line("c5", "batched FD forward + adjoint outputs/s (256 instances, n 12..24, K 1..4, graph replay)",
                 outputs / (ms * 1e-3), "probs/s", steps, warmup, ms, "f32",
-                {"instances": len(insts), "sum_2^n": outputs, "precision": "fp32", "seed": 5},
+                {"instances": len(insts), "sum_2^n": outputs, "precision": "fp32", "seed": 5,
+                 "step": "forward with the cross-entropy gradient in its final kernels, then the adjoint"},
                 roof, kernels_ms_per_step={k: v[1] / 3 for k, v in kt.items()})
+    out["two_pass"] = {"ms_per_step": ms2, "value": outputs / (ms2 * 1e-3),
+                       "step": "forward writing p, one cross-entropy gradient pass, adjoint",
+                       "kernels_ms_per_step": {k: v[1] / 3 for k, v in kt2.items()},
+                       "same_entry_gradients_as_fused": same}
+    out["fused_with_loss"] = {"ms_per_step": ms_l, "value": outputs / (ms_l * 1e-3)}
     if not args.no_cpu:
         from oracle import native, metrics  # CPU-baseline leg only
         threads = native.max_threads()

@@ -142,10 +142,11 @@ int cqc_reconstruct_fd_noalloc(const cqc_instance *inst, int32_t n_inst, cqc_dty
  * instances' intermediate contractions first, then all final ones, each
  * group drained from a cost-ordered work queue) and one pass for every FP64
  * mass.
- * cqc_batch_create validates and plans the batch, writes its descriptor tables
- * into `workspace` (at least cqc_fd_workspace_size() bytes for the same
- * instances, which must stay allocated and unmodified by the caller while the
- * batch exists) and synchronises `stream` once.  Entry, output and mass
+ * cqc_batch_create validates and plans the batch (n_inst >= 2, else
+ * CQC_ERR_INVALID_ARG), writes its descriptor tables into `workspace` (at
+ * least cqc_fd_workspace_size() bytes for the same instances, which must stay
+ * allocated and unmodified by the caller while the batch exists) and
+ * synchronises `stream` once.  Entry, output and mass
  * pointers are bound at creation.  The output dtype must be the precision's
  * (F32 for FP32, F64 for FP64).
  * cqc_batch_run enqueues only kernel launches, with no host synchronisation
@@ -158,6 +159,33 @@ int cqc_batch_create(const cqc_instance *inst, int32_t n_inst, cqc_dtype in_t, c
                      cqc_batch *out);
 int cqc_batch_run(cqc_batch batch, hipStream_t stream);
 int cqc_batch_destroy(cqc_batch batch);
+
+/* A prepared batch whose final contraction steps also evaluate a
+ * cross-entropy against a target distribution (the loss the adjoint below is
+ * driven by; the paper itself trains nothing).  For every output p_x of
+ * instance i and the target t_x at the same position (targets[i]: DEVICE
+ * [2^n_i], output dtype, global output order) the kernel that computes p_x
+ * writes
+ *     grads[i][x] = -t_x / p_x if p_x > 1e-30, else 0
+ * (DEVICE [2^n_i], output dtype) - bitwise what cqc_xent_grad gives for the
+ * same p and t - so no separate pass over p is needed.  inst[i].out may be
+ * NULL: p is then not written at all.  losses: HOST array of n_inst DEVICE
+ * pointers, or NULL; losses[i] (if set) receives
+ *     L_i = -sum_x t_x log max(p_x, 1e-30)
+ * (logarithms in the output precision - FP32 outputs: about 1e-7 relative
+ * per term, the size of p's own rounding - and the terms summed in FP64 in
+ * the fixed order of the mass, so L_i is bitwise reproducible).  An instance with
+ * a loss must have inst[i].mass NULL; without one, inst[i].mass works as in
+ * cqc_batch_create.  grads[i] may equal targets[i] (each element is read
+ * before it is overwritten); no other two of the buffers may overlap.  The
+ * workspace size, cqc_batch_run, cqc_batch_destroy and
+ * cqc_batch_backward_create (grad_out = grads) are those of the plain batch.
+ * Errors: those of cqc_batch_create; CQC_ERR_INVALID_ARG for NULL targets or
+ * grads arrays or entries, or a loss together with a mass. */
+int cqc_batch_create_xent(const cqc_instance *inst, int32_t n_inst, cqc_dtype in_t, cqc_dtype out_t,
+                          cqc_precision prec, const void *const *targets, void *const *grads,
+                          double *const *losses, void *workspace, size_t ws_bytes, hipStream_t stream,
+                          cqc_batch *out);
 
 /* Adjoint of a prepared batch (the gradient of Section 3.2.3's linear map;
  * the paper has no gradients): for every instance i, dL/dE_c for each entry

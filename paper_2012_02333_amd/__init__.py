@@ -113,7 +113,7 @@ class FDCall:
         dev = self.entries_list[0][0].device
         self.device = dev
         n_inst = len(self.cuts)
-        self.outs = outs if outs is not None else [
+        self.outs = list(outs) if outs is not None else [
             torch.empty(2 ** c.n, dtype=self.out_dtype, device=dev) for c in self.cuts]
         self.mass = torch.zeros(n_inst, dtype=torch.float64, device=dev) if with_mass else None
         Arr = _lib.CqcInstance * n_inst
@@ -123,7 +123,7 @@ class FDCall:
             ptrs = (ctypes.c_void_p * len(ents))(*[E.data_ptr() for E in ents])
             self._keep.append(ptrs)
             self._insts[i] = _lib.CqcInstance(
-                c.c, ptrs, self.outs[i].data_ptr(),
+                c.c, ptrs, self.outs[i].data_ptr() if self.outs[i] is not None else None,
                 (self.mass.data_ptr() + 8 * i) if with_mass else None)
         self.n_inst = n_inst
         self._in_t, self._out_t = _DT[self.in_dtype], _DT[self.out_dtype]
@@ -162,16 +162,60 @@ class Batch(FDCall):
     """A prepared batch of instances (cqc_batch_create): the descriptor tables
     are uploaded once; run() enqueues a fixed handful of kernel launches and is
     safe to capture into a CUDA/HIP graph.  Outputs and masses are bound at
-    construction."""
+    construction.
 
-    def __init__(self, entries_list, cuts, precision="fp32", outs=None, with_mass=True):
+    With targets (one per instance, the output dtype and size) the batch is
+    the cross-entropy form (cqc_batch_create_xent): every run also writes
+    dL/dp = -t/p (0 where p <= 1e-30) into self.grads (the given grads, else
+    new tensors) from inside the kernels that compute p, and, with with_loss,
+    L_i = -sum t log max(p, 1e-30) into self.losses[i] (FP64) in place of the
+    mass.  keep_outputs=False writes no p at all (self.outs[i] is None)."""
+
+    def __init__(self, entries_list, cuts, precision="fp32", outs=None, with_mass=True, targets=None,
+                 grads=None, with_loss=False, keep_outputs=True):
+        if targets is None and (grads is not None or with_loss or not keep_outputs):
+            raise ValueError("grads, with_loss and keep_outputs=False need targets")
+        if targets is not None:
+            if with_loss:
+                with_mass = False
+            if not keep_outputs:
+                if outs is not None:
+                    raise ValueError("keep_outputs=False takes no outs")
+                outs = [None] * len(cuts)
         super().__init__(entries_list, cuts, precision, None, outs, with_mass)
         if self.n_inst < 2:
             raise ValueError("a batch needs at least two instances")
         h = ctypes.c_void_p(0)
         s = torch.cuda.current_stream(self.device).cuda_stream
-        _lib.check(_lib.lib().cqc_batch_create(self._insts, self.n_inst, self._in_t, self._out_t, self.prec,
-                                               self.ws.data_ptr(), self.ws_bytes, s, ctypes.byref(h)))
+        self.targets = self.grads = self.losses = None
+        if targets is None:
+            _lib.check(_lib.lib().cqc_batch_create(self._insts, self.n_inst, self._in_t, self._out_t, self.prec,
+                                                   self.ws.data_ptr(), self.ws_bytes, s, ctypes.byref(h)))
+        else:
+            targets = list(targets)
+            if len(targets) != self.n_inst:
+                raise ValueError("one target per instance")
+            if grads is None:
+                grads = [torch.empty(2 ** c.n, dtype=self.out_dtype, device=self.device) for c in self.cuts]
+            grads = list(grads)
+            if len(grads) != self.n_inst:
+                raise ValueError("one gradient buffer per instance")
+            for c, t, g in zip(self.cuts, targets, grads):
+                for x, what in ((t, "target"), (g, "gradient")):
+                    if (x.shape != (2 ** c.n,) or x.dtype != self.out_dtype or x.device != self.device
+                            or not x.is_contiguous()):
+                        raise ValueError(f"each {what} must be a contiguous [2^n] tensor of the output "
+                                         "dtype on the batch's device")
+            self.targets, self.grads = targets, grads
+            self.losses = torch.zeros(self.n_inst, dtype=torch.float64, device=self.device) if with_loss else None
+            n = self.n_inst
+            self._tp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in targets])
+            self._gp = (ctypes.c_void_p * n)(*[g.data_ptr() for g in grads])
+            self._lp = (ctypes.c_void_p * n)(*[self.losses.data_ptr() + 8 * i for i in range(n)]) \
+                if with_loss else None
+            _lib.check(_lib.lib().cqc_batch_create_xent(self._insts, n, self._in_t, self._out_t, self.prec,
+                                                        self._tp, self._gp, self._lp, self.ws.data_ptr(),
+                                                        self.ws_bytes, s, ctypes.byref(h)))
         self._h = h
 
     def set_outputs(self, outs):
@@ -199,8 +243,9 @@ class BatchBackward:
     def __init__(self, batch, grads_out):
         if len(grads_out) != batch.n_inst:
             raise ValueError("one dL/dp per instance")
-        for g, o in zip(grads_out, batch.outs):
-            if g.shape != o.shape or g.dtype != o.dtype or g.device != o.device or not g.is_contiguous():
+        for g, c in zip(grads_out, batch.cuts):
+            if (g.shape != (2 ** c.n,) or g.dtype != batch.out_dtype or g.device != batch.device
+                    or not g.is_contiguous()):
                 raise ValueError("each dL/dp must match its instance's output (shape, dtype, device, contiguous)")
         self.batch = batch
         self.grads_out = list(grads_out)

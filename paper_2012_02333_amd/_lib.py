@@ -22,7 +22,7 @@ EXPORTS = [
     "cqc_batch_backward_workspace_size", "cqc_batch_backward_create", "cqc_batch_backward_run",
     "cqc_batch_backward_destroy", "cqc_build_entries", "cqc_chi2", "cqc_xent_grad", "cqc_tune_reset",
     "cqc_reconstruct_fd_noalloc", "cqc_dd_query_workspace_size", "cqc_dd_query_create", "cqc_dd_query_run",
-    "cqc_dd_query_destroy", "cqc_dd_query_run_range",
+    "cqc_dd_query_destroy", "cqc_dd_query_run_range", "cqc_batch_create_xent",
 ]
 NOALLOC_WORKSPACE_BYTES = 32 << 20
 
@@ -96,6 +96,8 @@ def lib():
     L.cqc_selftest_mfma.argtypes = [vp, vp]
     L.cqc_batch_create.argtypes = [P(CqcInstance), i32, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, sz, vp,
                                    P(vp)]
+    L.cqc_batch_create_xent.argtypes = [P(CqcInstance), i32, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(vp),
+                                        P(vp), P(vp), vp, sz, vp, P(vp)]
     L.cqc_batch_run.argtypes = [vp, vp]
     L.cqc_batch_destroy.argtypes = [vp]
     L.cqc_batch_backward_workspace_size.argtypes = [vp, P(sz)]

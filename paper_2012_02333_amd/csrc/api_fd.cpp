@@ -23,14 +23,14 @@ Status check_dtype(cqc_dtype t) {
 }
 
 Status plan_fd_instance(const cqc_instance &in, cqc_dtype in_t, Acc acc, size_t base,
-                               bool need_ptrs, FdInstancePlan *out) {
+                               bool need_ptrs, FdInstancePlan *out, bool out_optional) {
   FdInstancePlan ip;
   CQC_TRY(validate_cut(&in.cut, CQC_MAX_FD_QUBITS, &ip.cut));
   if (need_ptrs) {
     if (!in.entries) return Status::fail(CQC_ERR_INVALID_ARG, "entries is NULL");
     for (int c = 0; c < ip.cut.nsub; ++c)
       if (!in.entries[c]) return Status::fail(CQC_ERR_INVALID_ARG, "entries[" + std::to_string(c) + "] is NULL");
-    if (!in.out) return Status::fail(CQC_ERR_INVALID_ARG, "out is NULL");
+    if (!in.out && !out_optional) return Status::fail(CQC_ERR_INVALID_ARG, "out is NULL");
   }
   std::vector<int> bitpos(ip.cut.n);
   for (int q = 0; q < ip.cut.n; ++q) bitpos[q] = ip.cut.n - 1 - q;
@@ -54,7 +54,7 @@ Status plan_fd_instance(const cqc_instance &in, cqc_dtype in_t, Acc acc, size_t 
 
 Status fd_plans(const cqc_instance *inst, int32_t n_inst, cqc_dtype in_t, cqc_dtype out_t,
                        cqc_precision prec, bool need_ptrs, std::vector<FdInstancePlan> *plans,
-                       Acc *acc_out) {
+                       Acc *acc_out, bool out_optional) {
   if (!inst) return Status::fail(CQC_ERR_INVALID_ARG, "inst is NULL");
   if (n_inst < 1) return Status::fail(CQC_ERR_INVALID_ARG, "n_inst < 1");
   CQC_TRY(check_dtype(in_t));
@@ -65,7 +65,7 @@ Status fd_plans(const cqc_instance *inst, int32_t n_inst, cqc_dtype in_t, cqc_dt
   plans->clear();
   for (int32_t i = 0; i < n_inst; ++i) {
     FdInstancePlan ip;
-    Status st = plan_fd_instance(inst[i], in_t, acc, off, need_ptrs, &ip);
+    Status st = plan_fd_instance(inst[i], in_t, acc, off, need_ptrs, &ip, out_optional);
     if (!st.good()) {
       set_error("instance " + std::to_string(i) + ": " + error_detail());
       return st;

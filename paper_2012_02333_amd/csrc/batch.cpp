@@ -20,6 +20,15 @@
 namespace cqc {
 
 static constexpr int kFinalLevel = 1 << 20;
+
+// Cross-entropy binding of a batch (cqc_batch_create_xent): per instance the
+// target, the gradient buffer and an optional loss (host arrays of device
+// pointers).
+struct XentBind {
+  const void *const *targets;
+  void *const *grads;
+  double *const *losses;
+};
 static constexpr uint32_t kQueueGrid = 2048;
 
 struct BatchBuild {
@@ -33,6 +42,7 @@ struct BatchBuild {
   struct G {
     int level, mode, cfg;
     bool small, strip;
+    int xent;
     Acc acc;
     std::vector<std::pair<double, ContractArgs>> steps;  // (cost, args)
   };
@@ -58,13 +68,24 @@ static int queue_cfg(Acc acc, const Step &st, int mode, bool out_double) {
 
 // Builds the groups with pointers relative to `ws` (nullptr: sizes only).
 static Status build_batch(const cqc_instance *inst, int32_t n_inst, cqc_dtype in_t, cqc_dtype out_t,
-                          cqc_precision prec, bool need_ptrs, char *ws, BatchBuild *out) {
+                          cqc_precision prec, bool need_ptrs, char *ws, BatchBuild *out,
+                          const XentBind *xent = nullptr) {
   BatchBuild B;
-  CQC_TRY(fd_plans(inst, n_inst, in_t, out_t, prec, need_ptrs, &B.plans, &B.acc));
+  CQC_TRY(fd_plans(inst, n_inst, in_t, out_t, prec, need_ptrs, &B.plans, &B.acc, xent != nullptr));
+  if (xent && need_ptrs) {
+    if (!xent->targets || !xent->grads) return Status::fail(CQC_ERR_INVALID_ARG, "targets or grads is NULL");
+    for (int32_t i = 0; i < n_inst; ++i) {
+      const std::string who = "instance " + std::to_string(i) + ": ";
+      if (!xent->targets[i] || !xent->grads[i])
+        return Status::fail(CQC_ERR_INVALID_ARG, who + "target or gradient pointer is NULL");
+      if (xent->losses && xent->losses[i] && inst[i].mass)
+        return Status::fail(CQC_ERR_INVALID_ARG, who + "a loss and a mass cannot both be asked for");
+    }
+  }
   const bool acc_double = B.acc == Acc::F64;
   if ((out_t == CQC_F64) != acc_double)
     return Status::fail(CQC_ERR_UNSUPPORTED, "batched calls need the output dtype of the precision");
-  std::map<std::tuple<int, int, int, int, int>, size_t> gidx;
+  std::map<std::tuple<int, int, int, int, int, int>, size_t> gidx;
   for (int32_t i = 0; i < n_inst; ++i) {
     const FdInstancePlan &ip = B.plans[i];
     const NetLayout &L = ip.net;
@@ -144,13 +165,19 @@ static Status build_batch(const cqc_instance *inst, int32_t n_inst, cqc_dtype in
           a.posX = pack_pos(px);
           a.posY = pack_pos(py);
         }
-        if (need_ptrs && inst[i].mass) {
+        double *sum_to = need_ptrs ? inst[i].mass : nullptr;
+        if (xent && need_ptrs) {
+          a.xt = xent->targets[i];
+          a.xg = xent->grads[i];
+          if (xent->losses && xent->losses[i]) sum_to = xent->losses[i];
+        }
+        if (sum_to) {
           // per-tile partials live in this instance's (resized) partials slot
           a.partials = reinterpret_cast<double *>(ws + L.partials_off);
           MassDesc md;
           md.partials = a.partials;
           md.count = kPartialsPerTile * a.nblocks;
-          md.mass = inst[i].mass;
+          md.mass = sum_to;
           B.mass.push_back(md);
         }
       }
@@ -163,7 +190,9 @@ static Status build_batch(const cqc_instance *inst, int32_t n_inst, cqc_dtype in
       const bool strip = small && sa == Acc::F32 && cfg == kTileL && st.logM >= 7 && st.logN >= 8 &&
                          (a.mode == kModeFinalBlocked || a.mode == kModeIntermediate) && !inst_flags;
       if (strip) a.flagX = a.flagY = nullptr;
-      auto key = std::make_tuple(level, (int)a.mode, cfg, (int)small * 2 + (int)strip, (int)sa);
+      // cross-entropy form of the final step: 1 gradient, 2 gradient and loss
+      const int xe = xent == nullptr || !last ? 0 : (xent->losses && xent->losses[i] ? 2 : 1);
+      auto key = std::make_tuple(level, (int)a.mode, cfg, (int)small * 2 + (int)strip, (int)sa, xe);
       auto it = gidx.find(key);
       if (it == gidx.end()) {
         it = gidx.emplace(key, B.groups.size()).first;
@@ -173,6 +202,7 @@ static Status build_batch(const cqc_instance *inst, int32_t n_inst, cqc_dtype in
         g.cfg = cfg;
         g.small = small;
         g.strip = strip;
+        g.xent = xe;
         g.acc = sa;
         B.groups.push_back(g);
       }
@@ -243,6 +273,7 @@ static Status batch_run(cqc_batch_s *b, hipStream_t s) {
     q.grid = (uint32_t)std::min<int64_t>(G.total, kQueueGrid);
     q.bprefix = G.bprefix;
     q.btotal = G.btotal;
+    q.xent = G.xent;
     if (G.strip) CQC_TRY(launch_contract_strip_queue(G.mode, q, s));
     else CQC_TRY(launch_contract_queue(G.acc, G.mode, G.cfg, G.small, q, s));
   }
@@ -252,10 +283,11 @@ static Status batch_run(cqc_batch_s *b, hipStream_t s) {
 
 static Status batch_create(const cqc_instance *inst, int32_t n_inst, cqc_dtype in_t, cqc_dtype out_t,
                            cqc_precision prec, void *workspace, size_t ws_bytes, hipStream_t s,
-                           cqc_batch_s **out) {
+                           cqc_batch_s **out, const XentBind *xent = nullptr) {
   BatchBuild B;
   char *ws = static_cast<char *>(workspace);
-  CQC_TRY(build_batch(inst, n_inst, in_t, out_t, prec, true, ws, &B));
+  if (n_inst < 2) return Status::fail(CQC_ERR_INVALID_ARG, "a prepared batch needs at least two instances");
+  CQC_TRY(build_batch(inst, n_inst, in_t, out_t, prec, true, ws, &B, xent));
   if (!workspace || ws_bytes < B.bytes)
     return Status::fail(CQC_ERR_WORKSPACE, "workspace needs " + std::to_string(B.bytes) + " bytes");
   if (reinterpret_cast<uintptr_t>(workspace) % 256)
@@ -296,6 +328,7 @@ static Status batch_create(const cqc_instance *inst, int32_t n_inst, cqc_dtype i
     bg.cfg = G.cfg;
     bg.small = G.small;
     bg.strip = G.strip;
+    bg.xent = G.xent;
     bg.acc = G.acc;
     bg.descs = reinterpret_cast<const ContractArgs *>(ws + B.desc_off[g]);
     bg.prefix = reinterpret_cast<const int64_t *>(ws + B.prefix_off[g]);
@@ -327,6 +360,19 @@ int cqc_batch_create(const cqc_instance *inst, int32_t n_inst, cqc_dtype in_t, c
   if (!out) return Status::fail(CQC_ERR_INVALID_ARG, "out is NULL").code;
   cqc_batch_s *b = nullptr;
   Status st = batch_create(inst, n_inst, in_t, out_t, prec, workspace, ws_bytes, stream, &b);
+  if (!st.good()) return st.code;
+  *out = b;
+  return CQC_OK;
+}
+
+int cqc_batch_create_xent(const cqc_instance *inst, int32_t n_inst, cqc_dtype in_t, cqc_dtype out_t,
+                          cqc_precision prec, const void *const *targets, void *const *grads,
+                          double *const *losses, void *workspace, size_t ws_bytes, hipStream_t stream,
+                          cqc_batch *out) {
+  if (!out) return Status::fail(CQC_ERR_INVALID_ARG, "out is NULL").code;
+  const XentBind xb{targets, grads, losses};
+  cqc_batch_s *b = nullptr;
+  Status st = batch_create(inst, n_inst, in_t, out_t, prec, workspace, ws_bytes, stream, &b, &xb);
   if (!st.good()) return st.code;
   *out = b;
   return CQC_OK;

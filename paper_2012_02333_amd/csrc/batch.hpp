@@ -22,6 +22,7 @@ struct cqc_batch_s {
     int level, mode, cfg;
     bool small;
     bool strip;     // two-tile strips of the FP32 small-term kernel
+    int xent;       // final steps of the cross-entropy form: 1 gradient, 2 gradient and loss
     cqc::Acc acc;   // arithmetic of the group's steps
     const cqc::ContractArgs *descs;
     const int64_t *prefix;

@@ -27,6 +27,20 @@
 
 namespace cqc {
 
+// Cross-entropy form (XE) of four consecutive outputs o..o+3: with the FP32
+// target prefetched (pre) or loaded here.
+template <typename O>
+__device__ __forceinline__ void xent4_at(const ContractArgs &a, int64_t o, const O (&v)[4], bool pre,
+                                         const f32x4 &t, double (&c)[4], bool loss) {
+  if constexpr (std::is_same<O, float>::value) {
+    if (pre) {
+      xent_emit4(a, o, v, t, c, loss);
+      return;
+    }
+  }
+  xent_put4<O>(a, o, v, c, loss);
+}
+
 // FP64 mass: every block of the last step stores the FP64 sum of what it
 // wrote; k_mass_final then adds the partials in block order.  (A completion
 // counter in the contraction kernel would need a device-scope release fence
@@ -55,7 +69,7 @@ __global__ __launch_bounds__(1024) void k_mass_final(const double *partials, int
   if (threadIdx.x == 0) mass[0] = tsum[0];
 }
 
-template <typename T, typename O, int BM, int BN, int WM, int WN, int MODE>
+template <typename T, typename O, int BM, int BN, int WM, int WN, int MODE, int XE = 0>
 __device__ __forceinline__ void contract_tile(const ContractArgs &a, uint32_t blk_in) {
   constexpr int TM = BM / WM, TN = BN / WN;     // wave tile
   constexpr int BMB = TM / 16, BNB = TN / 16;    // 16x16 blocks per wave
@@ -158,6 +172,17 @@ __device__ __forceinline__ void contract_tile(const ContractArgs &a, uint32_t bl
   // ---- epilogue
   double msum = 0.0;
   const O scale = (O)a.scale;
+  // cross-entropy form: the targets of the whole wave tile before its first store
+  constexpr bool kPre = XE && MODE == kModeFinalBlocked && Op::kConsecutive;
+  const bool pre = kPre && mw + TM <= M && nw + TN <= N;
+  f32x4 tv[kPre ? BMB * BNB : 1];
+  if constexpr (kPre) {
+    if (pre)
+#pragma unroll
+      for (int i = 0; i < BMB; ++i)
+#pragma unroll
+        for (int j = 0; j < BNB; ++j) tv[i * BNB + j] = xent_t4(a, (mw + i * 16 + l16) * N + nw + j * 16 + 4 * lg);
+  }
 #pragma unroll
   for (int i = 0; i < BMB; ++i) {
 #pragma unroll
@@ -178,20 +203,35 @@ __device__ __forceinline__ void contract_tile(const ContractArgs &a, uint32_t bl
           O v[4];
 #pragma unroll
           for (int r = 0; r < 4; ++r) v[r] = (O)acc[i][j][r] * scale;
-          if (MODE == kModeFinalBlocked) {
-            O *Z = static_cast<O *>(a.Z) + m * N + n;
-            if (n + 3 < N) store4<O>(Z, v);
-            else
+          if constexpr (XE) {
+            if (MODE == kModeFinalBlocked && n + 3 < N) {
+              double c[4];
+              xent4_at<O>(a, m * N + n, v, pre, tv[kPre ? i * BNB + j : 0], c, XE == 2);
+              for (int r = 0; r < 4; ++r) msum += c[r];
+            } else {
               for (int r = 0; r < 4; ++r)
-                if (n + r < N) Z[r] = v[r];
+                if (n + r < N)
+                  msum += xent_put1<O>(a, MODE == kModeFinalBlocked ? m * N + n + r
+                                                                   : rowoff[m - (int64_t)tm * BM] +
+                                                                         coloff[n + r - (int64_t)tn * BN],
+                                       v[r], XE == 2);
+            }
           } else {
-            O *Z = static_cast<O *>(a.Z);
-            const int64_t ro = rowoff[m - (int64_t)tm * BM];
+            if (MODE == kModeFinalBlocked) {
+              O *Z = static_cast<O *>(a.Z) + m * N + n;
+              if (n + 3 < N) store4<O>(Z, v);
+              else
+                for (int r = 0; r < 4; ++r)
+                  if (n + r < N) Z[r] = v[r];
+            } else {
+              O *Z = static_cast<O *>(a.Z);
+              const int64_t ro = rowoff[m - (int64_t)tm * BM];
+              for (int r = 0; r < 4; ++r)
+                if (n + r < N) Z[ro + coloff[n + r - (int64_t)tn * BN]] = v[r];
+            }
             for (int r = 0; r < 4; ++r)
-              if (n + r < N) Z[ro + coloff[n + r - (int64_t)tn * BN]] = v[r];
+              if (n + r < N) msum += (double)v[r];
           }
-          for (int r = 0; r < 4; ++r)
-            if (n + r < N) msum += (double)v[r];
         }
       } else {
         // FP64: operands swapped (MFMA row <-> m), so register r of lane l holds
@@ -206,11 +246,15 @@ __device__ __forceinline__ void contract_tile(const ContractArgs &a, uint32_t bl
             static_cast<T *>(a.Z)[batch * M * N + m * N + n] = acc[i][j][r];
           } else {
             const O v = (O)acc[i][j][r] * scale;
-            if (MODE == kModeFinalBlocked)
-              static_cast<O *>(a.Z)[m * N + n] = v;
-            else
-              static_cast<O *>(a.Z)[rowoff[m - (int64_t)tm * BM] + coloff[n - (int64_t)tn * BN]] = v;
-            msum += (double)v;
+            const int64_t o = MODE == kModeFinalBlocked
+                                  ? m * N + n
+                                  : rowoff[m - (int64_t)tm * BM] + coloff[n - (int64_t)tn * BN];
+            if constexpr (XE) {
+              msum += xent_put1<O>(a, o, v, XE == 2);
+            } else {
+              static_cast<O *>(a.Z)[o] = v;
+              msum += (double)v;
+            }
           }
         }
       }
@@ -230,7 +274,7 @@ __device__ __forceinline__ void contract_tile(const ContractArgs &a, uint32_t bl
 // term stay in registers, and each 16-row block of the wave tile is written
 // as soon as its matrix-core products are done, so stores start early and
 // few registers are live (all blocks of a launch fit on the chip at once).
-template <typename T, typename O, int BM, int BN, int WM, int WN, int MODE>
+template <typename T, typename O, int BM, int BN, int WM, int WN, int MODE, int XE = 0>
 __device__ __forceinline__ void contract_small_tile(const ContractArgs &a, uint32_t blk_in) {
   constexpr int TM = BM / WM, TN = BN / WN;
   constexpr int BMB = TM / 16, BNB = TN / 16;
@@ -327,6 +371,21 @@ __device__ __forceinline__ void contract_small_tile(const ContractArgs &a, uint3
 
   double msum = 0.0;
   const O scale = (O)a.scale;
+  // cross-entropy form: the targets of the whole wave tile before its first
+  // store, in the layout of the staged row stores (else of the lanes' own runs)
+  constexpr bool kPre = XE && MODE == kModeFinalBlocked && Op::kConsecutive;
+  constexpr int kLPR = TN >= 32 ? TN / 4 : 1, kRPI = 64 / kLPR, kTQ = kStage ? 16 / kRPI : BNB;
+  const bool pre = kPre && mw + TM <= M && nw + TN <= N;
+  f32x4 tv[kPre ? BMB * kTQ : 1];
+  if constexpr (kPre) {
+    if (pre)
+#pragma unroll
+      for (int i = 0; i < BMB; ++i)
+#pragma unroll
+        for (int q = 0; q < kTQ; ++q)
+          tv[i * kTQ + q] = kStage ? xent_t4(a, (mw + i * 16 + q * kRPI + lane / kLPR) * N + nw + (lane % kLPR) * 4)
+                                   : xent_t4(a, (mw + i * 16 + l16) * N + nw + q * 16 + 4 * lg);
+  }
 #pragma unroll
   for (int i = 0; i < BMB; ++i) {
     const T *bx = bxa[i];
@@ -353,8 +412,15 @@ __device__ __forceinline__ void contract_small_tile(const ContractArgs &a, uint3
       for (int rr = 0; rr < 16; rr += RPI) {
         const int row = rr + lane / LPR, col = (lane % LPR) * 4;
         const float4 v = *reinterpret_cast<const float4 *>(st + row * SLD + col);
-        *reinterpret_cast<float4 *>(Zb + (mrow + row) * N + nw + col) = v;
-        if (MODE != kModeIntermediate) msum += ((double)v.x + (double)v.y) + ((double)v.z + (double)v.w);
+        if constexpr (XE) {
+          const float w[4] = {v.x, v.y, v.z, v.w};
+          double c[4];
+          xent4_at<float>(a, (mrow + row) * N + nw + col, w, pre, tv[kPre ? i * kTQ + rr / RPI : 0], c, XE == 2);
+          msum += (c[0] + c[1]) + (c[2] + c[3]);
+        } else {
+          *reinterpret_cast<float4 *>(Zb + (mrow + row) * N + nw + col) = v;
+          if (MODE != kModeIntermediate) msum += ((double)v.x + (double)v.y) + ((double)v.z + (double)v.w);
+        }
       }
       asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
       continue;
@@ -377,20 +443,35 @@ __device__ __forceinline__ void contract_small_tile(const ContractArgs &a, uint3
           O v[4];
 #pragma unroll
           for (int r = 0; r < 4; ++r) v[r] = (O)acc[j][r] * scale;
-          if (MODE == kModeFinalBlocked) {
-            O *Z = static_cast<O *>(a.Z) + m * N + n;
-            if (n + 3 < N) store4<O>(Z, v);
-            else
+          if constexpr (XE) {
+            if (MODE == kModeFinalBlocked && n + 3 < N) {
+              double c[4];
+              xent4_at<O>(a, m * N + n, v, pre, tv[kPre && !kStage ? i * BNB + j : 0], c, XE == 2);
+              for (int r = 0; r < 4; ++r) msum += c[r];
+            } else {
               for (int r = 0; r < 4; ++r)
-                if (n + r < N) Z[r] = v[r];
+                if (n + r < N)
+                  msum += xent_put1<O>(a, MODE == kModeFinalBlocked ? m * N + n + r
+                                                                   : rowoff[m - (int64_t)tm * BM] +
+                                                                         coloff[n + r - (int64_t)tn * BN],
+                                       v[r], XE == 2);
+            }
           } else {
-            O *Z = static_cast<O *>(a.Z);
-            const int64_t ro = rowoff[m - (int64_t)tm * BM];
+            if (MODE == kModeFinalBlocked) {
+              O *Z = static_cast<O *>(a.Z) + m * N + n;
+              if (n + 3 < N) store4<O>(Z, v);
+              else
+                for (int r = 0; r < 4; ++r)
+                  if (n + r < N) Z[r] = v[r];
+            } else {
+              O *Z = static_cast<O *>(a.Z);
+              const int64_t ro = rowoff[m - (int64_t)tm * BM];
+              for (int r = 0; r < 4; ++r)
+                if (n + r < N) Z[ro + coloff[n + r - (int64_t)tn * BN]] = v[r];
+            }
             for (int r = 0; r < 4; ++r)
-              if (n + r < N) Z[ro + coloff[n + r - (int64_t)tn * BN]] = v[r];
+              if (n + r < N) msum += (double)v[r];
           }
-          for (int r = 0; r < 4; ++r)
-            if (n + r < N) msum += (double)v[r];
         }
       } else {
         const int64_t n = nb + l16;
@@ -402,11 +483,15 @@ __device__ __forceinline__ void contract_small_tile(const ContractArgs &a, uint3
             static_cast<T *>(a.Z)[(int64_t)batch * M * N + m * N + n] = acc[j][r];
           } else {
             const O v = (O)acc[j][r] * scale;
-            if (MODE == kModeFinalBlocked)
-              static_cast<O *>(a.Z)[m * N + n] = v;
-            else
-              static_cast<O *>(a.Z)[rowoff[m - (int64_t)tm * BM] + coloff[n - (int64_t)tn * BN]] = v;
-            msum += (double)v;
+            const int64_t o = MODE == kModeFinalBlocked
+                                  ? m * N + n
+                                  : rowoff[m - (int64_t)tm * BM] + coloff[n - (int64_t)tn * BN];
+            if constexpr (XE) {
+              msum += xent_put1<O>(a, o, v, XE == 2);
+            } else {
+              static_cast<O *>(a.Z)[o] = v;
+              msum += (double)v;
+            }
           }
         }
       }
@@ -431,7 +516,7 @@ __device__ __forceinline__ void contract_small_tile(const ContractArgs &a, uint3
 // over the first tile's stores.  One partial mass per tile, as in the
 // one-tile kernel.
 
-template <typename O, int MODE>
+template <typename O, int MODE, int XE = 0>
 __device__ __forceinline__ void contract_small_strip(const ContractArgs &a, uint32_t strip) {
   static_assert(sizeof(O) == 4, "staged float4 stores: FP32 output only");
   constexpr int R = kStripRows, BM = 64, BN = 256, TN = 64, SLD = TN + 4;
@@ -481,11 +566,18 @@ __device__ __forceinline__ void contract_small_strip(const ContractArgs &a, uint
   float *st = stage + wave * 16 * SLD;
   const float sc = MODE == kModeIntermediate ? 1.0f : (float)a.scale;
   O *Zb = MODE == kModeIntermediate ? static_cast<O *>(a.Z) + (int64_t)batch * M * N : static_cast<O *>(a.Z);
+  // cross-entropy form: the targets of a whole tile, loaded before its first
+  // store (strips cover whole tiles)
+  f32x4 tv[XE ? 16 : 1];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    if (r + 1 < R) load_x(r + 1);
     const uint32_t tm = g * R + r;
     const int64_t mw = (int64_t)tm * BM;
+    if constexpr (XE)
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        tv[q] = xent_t4(a, (mw + (q >> 2) * 16 + (q & 3) * 4 + lane / 16) * N + nw + (lane % 16) * 4);
+    if (r + 1 < R) load_x(r + 1);
     double msum = 0.0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -506,8 +598,15 @@ __device__ __forceinline__ void contract_small_strip(const ContractArgs &a, uint
       for (int rr = 0; rr < 16; rr += 4) {
         const int row = rr + lane / 16, col = (lane % 16) * 4;
         const float4 v = *reinterpret_cast<const float4 *>(st + row * SLD + col);
-        *reinterpret_cast<float4 *>(Zb + (mw + i * 16 + row) * N + nw + col) = v;
-        if (MODE != kModeIntermediate) msum += ((double)v.x + (double)v.y) + ((double)v.z + (double)v.w);
+        if constexpr (XE) {
+          const float w[4] = {v.x, v.y, v.z, v.w};
+          double c[4];
+          xent_emit4(a, (mw + i * 16 + row) * N + nw + col, w, tv[XE ? 4 * i + rr / 4 : 0], c, XE == 2);
+          msum += (c[0] + c[1]) + (c[2] + c[3]);
+        } else {
+          *reinterpret_cast<float4 *>(Zb + (mw + i * 16 + row) * N + nw + col) = v;
+          if (MODE != kModeIntermediate) msum += ((double)v.x + (double)v.y) + ((double)v.z + (double)v.w);
+        }
       }
       asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     }
@@ -521,7 +620,7 @@ __device__ __forceinline__ void contract_small_strip(const ContractArgs &a, uint
   }
 }
 
-template <int MODE>
+template <int MODE, int XE>
 __global__ __launch_bounds__(256) void k_contract_strip_queue(const ContractArgs *descs, const int64_t *prefix,
                                                               int ndesc, unsigned long long *queue, int64_t total) {
   __shared__ int64_t item;
@@ -532,7 +631,7 @@ __global__ __launch_bounds__(256) void k_contract_strip_queue(const ContractArgs
     const int64_t it = item;
     if (it >= total) return;
     const int d = find_desc(prefix, ndesc, it);
-    contract_small_strip<float, MODE>(descs[d], (uint32_t)(it - prefix[d]));
+    contract_small_strip<float, MODE, XE>(descs[d], (uint32_t)(it - prefix[d]));
   }
 }
 
@@ -558,7 +657,7 @@ __global__ __launch_bounds__(256) void k_contract(const ContractArgs a) {
 // runs dry; steps are laid out most expensive first, so large instances start
 // early and small ones fill the tail.  Every block leaves once the counter
 // passes `total`.
-template <typename T, typename O, int BM, int BN, int WM, int WN, int MODE, bool SMALL>
+template <typename T, typename O, int BM, int BN, int WM, int WN, int MODE, bool SMALL, int XE>
 __global__ __launch_bounds__(256) void k_contract_queue(const ContractArgs *descs, const int64_t *prefix,
                                                         int ndesc, unsigned long long *queue, int64_t total) {
   __shared__ int64_t item;
@@ -569,8 +668,8 @@ __global__ __launch_bounds__(256) void k_contract_queue(const ContractArgs *desc
     const int64_t it = item;
     if (it >= total) return;
     const int d = find_desc(prefix, ndesc, it);
-    if (SMALL) contract_small_tile<T, O, BM, BN, WM, WN, MODE>(descs[d], (uint32_t)(it - prefix[d]));
-    else contract_tile<T, O, BM, BN, WM, WN, MODE>(descs[d], (uint32_t)(it - prefix[d]));
+    if (SMALL) contract_small_tile<T, O, BM, BN, WM, WN, MODE, XE>(descs[d], (uint32_t)(it - prefix[d]));
+    else contract_tile<T, O, BM, BN, WM, WN, MODE, XE>(descs[d], (uint32_t)(it - prefix[d]));
   }
 }
 
@@ -751,25 +850,42 @@ static Status launch_contract_m(int cfg, const ContractArgs &a, hipStream_t s) {
   return launch_contract_ms<T, O, MODE, false>(cfg, a, s);
 }
 
+template <typename T, int MODE, bool SMALL, int XE>
+static Status launch_queue_x(int cfg, const QueueLaunch &q, hipStream_t s) {
+  const dim3 grid(q.grid), block(256);
+  const char *nm = XE == 2 ? (SMALL ? "contract_small_queue_xent_loss" : "contract_queue_xent_loss")
+                   : XE ? (SMALL ? "contract_small_queue_xent" : "contract_queue_xent")
+                        : (SMALL ? "contract_small_queue" : "contract_queue");
+  switch (cfg) {
+    case kTileL: return launch(nm, k_contract_queue<T, T, 64, 256, 1, 4, MODE, SMALL, XE>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
+    case kTileM: return launch(nm, k_contract_queue<T, T, 32, 128, 1, 4, MODE, SMALL, XE>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
+    default: return launch(nm, k_contract_queue<T, T, 16, 64, 1, 4, MODE, SMALL, XE>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
+  }
+}
+
 template <typename T, int MODE, bool SMALL>
 static Status launch_queue_t(int cfg, const QueueLaunch &q, hipStream_t s) {
-  const dim3 grid(q.grid), block(256);
-  const char *nm = SMALL ? "contract_small_queue" : "contract_queue";
-  switch (cfg) {
-    case kTileL: return launch(nm, k_contract_queue<T, T, 64, 256, 1, 4, MODE, SMALL>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
-    case kTileM: return launch(nm, k_contract_queue<T, T, 32, 128, 1, 4, MODE, SMALL>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
-    default: return launch(nm, k_contract_queue<T, T, 16, 64, 1, 4, MODE, SMALL>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
+  if constexpr (MODE != kModeIntermediate) {
+    if (q.xent == 1) return launch_queue_x<T, MODE, SMALL, 1>(cfg, q, s);
+    if (q.xent == 2) return launch_queue_x<T, MODE, SMALL, 2>(cfg, q, s);
   }
+  return launch_queue_x<T, MODE, SMALL, 0>(cfg, q, s);
 }
 
 Status launch_contract_strip_queue(int mode, const QueueLaunch &q, hipStream_t s) {
   const dim3 grid(q.grid), block(256);
   if (mode == kModeIntermediate)
-    return launch("contract_strip_queue", k_contract_strip_queue<kModeIntermediate>, grid, block, 0, s, q.descs,
-                  q.prefix, q.ndesc, q.queue, q.total);
+    return launch("contract_strip_queue", k_contract_strip_queue<kModeIntermediate, 0>, grid, block, 0, s,
+                  q.descs, q.prefix, q.ndesc, q.queue, q.total);
+  if (mode == kModeFinalBlocked && q.xent == 1)
+    return launch("contract_strip_queue_xent", k_contract_strip_queue<kModeFinalBlocked, 1>, grid, block, 0, s,
+                  q.descs, q.prefix, q.ndesc, q.queue, q.total);
+  if (mode == kModeFinalBlocked && q.xent == 2)
+    return launch("contract_strip_queue_xent_loss", k_contract_strip_queue<kModeFinalBlocked, 2>, grid, block, 0,
+                  s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
   if (mode == kModeFinalBlocked)
-    return launch("contract_strip_queue", k_contract_strip_queue<kModeFinalBlocked>, grid, block, 0, s, q.descs,
-                  q.prefix, q.ndesc, q.queue, q.total);
+    return launch("contract_strip_queue", k_contract_strip_queue<kModeFinalBlocked, 0>, grid, block, 0, s,
+                  q.descs, q.prefix, q.ndesc, q.queue, q.total);
   return Status::fail(CQC_ERR_UNSUPPORTED, "two-tile strips need blocked or intermediate output");
 }
 

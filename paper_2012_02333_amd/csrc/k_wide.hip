@@ -251,7 +251,9 @@ struct QueueSeq {
 // PS (split forms): the operands come already split into bfloat16 part planes
 // (ContractArgs::Xs, Ys), so staging only repacks them; otherwise every tile
 // splits the FP32 operands it stages.
-template <int NP, typename O, int MODE, bool PS, class Seq>
+// XE: final steps of the cross-entropy form (ContractArgs::xt): 1 gradient,
+// 2 gradient and loss.
+template <int NP, typename O, int MODE, bool PS, int XE, class Seq>
 __device__ __forceinline__ void wide_run(Seq &seq) {
   static_assert(!PS || NP > 0, "pre-split operands are for the split forms");
   static_assert(NP == 0 || NP == 2 || NP == 3, "FP32, BF16X3 or BF16X6");
@@ -479,6 +481,22 @@ __device__ __forceinline__ void wide_run(Seq &seq) {
     const int64_t mw = g.m0 + wm * kWT, nw = g.n0 + wn * kWT;
     const gptr<O> Zb = gbl(uni(static_cast<O *>(a.Z))) + (MODE == kModeIntermediate ? g.batch * M * N : 0);
     constexpr bool kStage = sizeof(O) == 4 && MODE != kModeFinalDeposit;
+    // cross-entropy form: the targets of the whole wave tile (64 rows, in the
+    // staged stores' layout: row 4 q + lane / 16, columns 4 (lane % 16) + 0..3)
+    // are loaded before its first store (see xent_emit4)
+    constexpr bool kPre = XE && MODE == kModeFinalBlocked && kStage;
+    const bool pre = kPre && mw + kWT <= M && nw + kWT <= N;
+    f32x4 tv[kPre ? 16 : 1];
+    const gptr<float> XT = gbl(uni(static_cast<float *>(const_cast<void *>(a.xt))));
+    const gptr<float> XG = gbl(uni(static_cast<float *>(a.xg)));
+    const gptr<float> XZ = gbl(uni(static_cast<float *>(a.Z)));
+    constexpr bool xloss = XE == 2;
+    if constexpr (kPre) {
+      if (pre)
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          tv[q] = __builtin_nontemporal_load((gptr<f32x4>)(XT + (mw + 4 * q + lg) * N + nw + 4 * l16));
+    }
     const double sc64 = uni(a.scale);
     const float scf = MODE == kModeIntermediate ? 1.0f : (float)sc64;
     const O scale = (O)sc64;
@@ -496,17 +514,25 @@ __device__ __forceinline__ void wide_run(Seq &seq) {
         O v[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) v[r] = (O)vals[r] * scale;
-        if (MODE == kModeFinalBlocked) {
-          const gptr<O> Z = Zb + m * N + n;
+        if constexpr (XE) {
           for (int r = 0; r < 4; ++r)
-            if (n + r < N) Z[r] = v[r];
+            if (n + r < N)
+              msum += xent_put1<O>(a, MODE == kModeFinalBlocked ? m * N + n + r
+                                                               : rowoff[m - g.m0] + coloff[n + r - g.n0],
+                                   v[r], XE == 2);
         } else {
-          const int64_t ro = rowoff[m - g.m0];
+          if (MODE == kModeFinalBlocked) {
+            const gptr<O> Z = Zb + m * N + n;
+            for (int r = 0; r < 4; ++r)
+              if (n + r < N) Z[r] = v[r];
+          } else {
+            const int64_t ro = rowoff[m - g.m0];
+            for (int r = 0; r < 4; ++r)
+              if (n + r < N) Zb[ro + coloff[n + r - g.n0]] = v[r];
+          }
           for (int r = 0; r < 4; ++r)
-            if (n + r < N) Zb[ro + coloff[n + r - g.n0]] = v[r];
+            if (n + r < N) msum += (double)v[r];
         }
-        for (int r = 0; r < 4; ++r)
-          if (n + r < N) msum += (double)v[r];
       }
     };
     // a staged slice of `rows` output rows x 64 columns (this wave's LDS
@@ -515,14 +541,36 @@ __device__ __forceinline__ void wide_run(Seq &seq) {
     // and never read here, so it should not evict the operands from L2
     // (measured 5% faster for BF16X6, and the L2 holds fewer dirty lines at
     // the end)
-    auto store_slice = [&](const float *st, int rows, int64_t m0) {
+    auto store_slice = [&](const float *st, auto rows_c, int64_t m0) {
+      constexpr int rows = decltype(rows_c)::value;
       asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#pragma unroll
       for (int rr = 0; rr < rows; rr += 4) {
         const int row = rr + lg, c4 = l16 * 4;
         const float4 v = *reinterpret_cast<const float4 *>(st + row * kStLd + c4);
-        __builtin_nontemporal_store(f32x4{v.x, v.y, v.z, v.w},
-                                    (gptr<f32x4>)((gptr<float>)Zb + (m0 + row) * N + nw + c4));
-        if (MODE != kModeIntermediate) msum += ((double)v.x + (double)v.y) + ((double)v.z + (double)v.w);
+        if constexpr (XE) {
+          const float w[4] = {v.x, v.y, v.z, v.w};
+          const int64_t o = (m0 + row) * N + nw + c4;
+          double c[4];
+          if (pre) {
+            const f32x4 t = tv[kPre ? (int)((m0 - mw) / 4) + rr / 4 : 0];
+            if (XZ) *(gptr<f32x4>)(XZ + o) = f32x4{w[0], w[1], w[2], w[3]};
+            f32x4 gv;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              gv[r] = xent_grad_of(w[r], t[r]);
+              c[r] = xent_part(w[r], t[r], xloss);
+            }
+            __builtin_nontemporal_store(gv, (gptr<f32x4>)(XG + o));
+          } else {
+            xent_put4<float>(a, o, w, c, xloss);
+          }
+          msum += (c[0] + c[1]) + (c[2] + c[3]);
+        } else {
+          __builtin_nontemporal_store(f32x4{v.x, v.y, v.z, v.w},
+                                      (gptr<f32x4>)((gptr<float>)Zb + (m0 + row) * N + nw + c4));
+          if (MODE != kModeIntermediate) msum += ((double)v.x + (double)v.y) + ((double)v.z + (double)v.w);
+        }
       }
       asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     };
@@ -542,7 +590,7 @@ __device__ __forceinline__ void wide_run(Seq &seq) {
               *reinterpret_cast<float4 *>(st + i32 * kStLd + bj * 32 + 8 * q + 4 * h) =
                   make_float4(acc2[bi][bj][4 * q] * scf, acc2[bi][bj][4 * q + 1] * scf,
                               acc2[bi][bj][4 * q + 2] * scf, acc2[bi][bj][4 * q + 3] * scf);
-          store_slice(st, 32, mb);
+          store_slice(st, std::integral_constant<int, 32>{}, mb);
           continue;
         }
 #pragma unroll
@@ -562,7 +610,7 @@ __device__ __forceinline__ void wide_run(Seq &seq) {
           for (int j = 0; j < 4; ++j)
             *reinterpret_cast<float4 *>(st + l16 * kStLd + j * 16 + 4 * lg) =
                 make_float4(acc[i][j][0] * scf, acc[i][j][1] * scf, acc[i][j][2] * scf, acc[i][j][3] * scf);
-          store_slice(st, 16, mw + i * 16);
+          store_slice(st, std::integral_constant<int, 16>{}, mw + i * 16);
           continue;
         }
 #pragma unroll
@@ -658,17 +706,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WideOcc<NP>
 void k_wide(const ContractArgs a) {
   if (gated_off(a.gate, a.gate_val)) return;
   StridedSeq seq(a);
-  wide_run<NP, O, MODE, PS>(seq);
+  wide_run<NP, O, MODE, PS, 0>(seq);
 }
 
-template <int NP, int MODE>
+template <int NP, int MODE, int XE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WideOcc<NP>::kWaves, WideOcc<NP>::kWaves)))
 void k_wide_queue(const ContractArgs *__restrict__ descs,
                                                     const int64_t *__restrict__ prefix, int ndesc,
                                                     unsigned long long *queue, int64_t total) {
   __shared__ int64_t slot[2];
   QueueSeq seq{descs, prefix, ndesc, queue, total, slot};
-  wide_run<NP, float, MODE, false>(seq);
+  wide_run<NP, float, MODE, false, XE>(seq);
 }
 
 // The split of the wide kernel's staging (split3), once per operand element:
@@ -733,13 +781,16 @@ static Status launch_persistent(const char *nm, K kernel, const ContractArgs &a,
 
 template <int NP> struct WideNames;
 template <> struct WideNames<0> {
-  static constexpr const char *fin = "wide_f32_final", *mid = "wide_f32_inter", *queue = "wide_f32_queue";
+  static constexpr const char *fin = "wide_f32_final", *mid = "wide_f32_inter", *queue = "wide_f32_queue",
+                              *qx = "wide_f32_queue_xent";
 };
 template <> struct WideNames<2> {
-  static constexpr const char *fin = "wide_bf16x3_final", *mid = "wide_bf16x3_inter", *queue = "wide_bf16x3_queue";
+  static constexpr const char *fin = "wide_bf16x3_final", *mid = "wide_bf16x3_inter", *queue = "wide_bf16x3_queue",
+                              *qx = "wide_bf16x3_queue_xent";
 };
 template <> struct WideNames<3> {
-  static constexpr const char *fin = "wide_bf16x6_final", *mid = "wide_bf16x6_inter", *queue = "wide_bf16x6_queue";
+  static constexpr const char *fin = "wide_bf16x6_final", *mid = "wide_bf16x6_inter", *queue = "wide_bf16x6_queue",
+                              *qx = "wide_bf16x6_queue_xent";
 };
 
 template <int NP, typename O, bool PS>
@@ -797,11 +848,19 @@ static Status launch_wide_queue_t(int mode, const QueueLaunch &q, hipStream_t s)
   const char *nm = WideNames<NP>::queue;
   CQC_TRY(launch("label_list_table", k_label_list_table, dim3((unsigned)q.btotal), block, 0, s, q.descs, q.bprefix,
                  q.ndesc));
+  const char *nx = WideNames<NP>::qx;
+  if (mode != kModeIntermediate && q.xent) {
+    if (mode == kModeFinalBlocked)
+      return q.xent == 2 ? launch(nx, k_wide_queue<NP, kModeFinalBlocked, 2>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total)
+                         : launch(nx, k_wide_queue<NP, kModeFinalBlocked, 1>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
+    return q.xent == 2 ? launch(nx, k_wide_queue<NP, kModeFinalDeposit, 2>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total)
+                       : launch(nx, k_wide_queue<NP, kModeFinalDeposit, 1>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
+  }
   if (mode == kModeFinalBlocked)
-    return launch(nm, k_wide_queue<NP, kModeFinalBlocked>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
+    return launch(nm, k_wide_queue<NP, kModeFinalBlocked, 0>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
   if (mode == kModeFinalDeposit)
-    return launch(nm, k_wide_queue<NP, kModeFinalDeposit>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
-  return launch(nm, k_wide_queue<NP, kModeIntermediate>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
+    return launch(nm, k_wide_queue<NP, kModeFinalDeposit, 0>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
+  return launch(nm, k_wide_queue<NP, kModeIntermediate, 0>, grid, block, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
 }
 
 Status launch_contract_wide_queue(int parts, int mode, const QueueLaunch &q, hipStream_t s) {

@@ -1,6 +1,8 @@
 // Device helpers shared by the contraction kernels (gfx950 only).
 #pragma once
 
+#include <cmath>
+
 #include "kernels.hpp"
 
 namespace cqc {
@@ -96,6 +98,67 @@ constexpr double kXentFloor = 1e-30;
 template <typename T>
 __device__ __forceinline__ T xent_grad_of(T p, T t) {
   return (double)p > kXentFloor ? -t / p : T(0);
+}
+
+// Partial-sum contribution of one output p of a cross-entropy final step
+// (ContractArgs::xt): the loss term -t log max(p, 1e-30) when the loss is
+// asked for, else p itself (the mass).  The logarithm is taken in the output
+// precision (FP32 outputs: an FP32 logarithm, relative error about 1e-7 per
+// term, no larger than what FP32 rounding of p itself leaves in the term;
+// the FP64 logarithm is several times the code of the whole store path and
+// keeps the epilogues from being unrolled); terms are summed in FP64.
+__device__ __forceinline__ double xent_log_floor(float p) {
+  return (double)logf((double)p > kXentFloor ? p : (float)kXentFloor);
+}
+__device__ __forceinline__ double xent_log_floor(double p) { return log(p > kXentFloor ? p : kXentFloor); }
+template <typename T>
+__device__ __forceinline__ double xent_part(T p, T t, bool loss) {
+  return loss ? -(double)t * xent_log_floor(p) : (double)p;
+}
+
+// One output p of a cross-entropy final step at element o of the output order:
+// gradient to xg, p to z if set; returns the partial-sum contribution.
+template <typename T>
+__device__ __forceinline__ double xent_put1(const ContractArgs &a, int64_t o, T p, bool loss) {
+  const T t = static_cast<const T *>(a.xt)[o];
+  if (a.Z) static_cast<T *>(a.Z)[o] = p;
+  static_cast<T *>(a.xg)[o] = xent_grad_of(p, t);
+  return xent_part(p, t, loss);
+}
+
+// Four consecutive outputs at elements o..o+3 (o a multiple of 4): vector
+// accesses; the contributions go to c[].
+template <typename T>
+__device__ __forceinline__ void xent_put4(const ContractArgs &a, int64_t o, const T (&v)[4], double (&c)[4],
+                                          bool loss) {
+  T t[4], g[4];
+  load4<T>(static_cast<const T *>(a.xt) + o, t);
+  if (a.Z) store4<T>(static_cast<T *>(a.Z) + o, v);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) g[r] = xent_grad_of(v[r], t[r]);
+  store4<T>(static_cast<T *>(a.xg) + o, g);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) c[r] = xent_part(v[r], t[r], loss);
+}
+
+// FP32 forms with the targets loaded ahead.  A wait for a load also waits for
+// every memory access issued before it (loads and stores retire through one
+// in-order counter), so a final step that loaded t next to each store would
+// wait for its own earlier stores every time: the kernels load the targets of
+// a whole tile before its first store instead.  Targets are read once and
+// gradients written once: non-temporal accesses.
+__device__ __forceinline__ f32x4 xent_t4(const ContractArgs &a, int64_t o) {
+  return __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(static_cast<const float *>(a.xt) + o));
+}
+__device__ __forceinline__ void xent_emit4(const ContractArgs &a, int64_t o, const float (&v)[4], const f32x4 &t,
+                                           double (&c)[4], bool loss) {
+  if (a.Z) store4<float>(static_cast<float *>(a.Z) + o, v);
+  f32x4 g;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) g[r] = xent_grad_of(v[r], t[r]);
+  __builtin_nontemporal_store(g, reinterpret_cast<f32x4 *>(static_cast<float *>(a.xg) + o));
+#pragma unroll
+  for (int r = 0; r < 4; ++r) c[r] = xent_part(v[r], t[r], loss);
 }
 
 // Wave-wide FP64 sum in a fixed order (butterfly); every lane gets the total.

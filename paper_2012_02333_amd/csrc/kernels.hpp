@@ -68,6 +68,13 @@ struct ContractArgs {
   const void *Xs;
   const void *Ys;
   int64_t xplane, yplane;
+  // cross-entropy form of a final step (batched queue kernels): xt is the
+  // target t in output order; every output p gets dL/dp = -t/p (0 where p <=
+  // 1e-30) written to xg at its position, p itself is written only if Z is
+  // set, and the partial sums add the loss terms -t log max(p, 1e-30) (kernel
+  // form with the loss) or p
+  const void *xt;
+  void *xg;
 };
 
 // FP64 mass partials: every wave of a final-step tile (four per block) stores
@@ -154,6 +161,8 @@ struct QueueLaunch {
   uint32_t grid;
   const int64_t *bprefix;  // wide kernel: bprefix[d] = first batch entry of step d over the table
   int64_t btotal;          //   and the total (one label-list block per batch entry)
+  int xent = 0;            // final steps of the cross-entropy form (ContractArgs::xt):
+                           //   1 gradient (partials sum p), 2 gradient and loss
 };
 Status launch_contract_queue(Acc acc, int mode, int cfg, bool small, const QueueLaunch &q, hipStream_t s);
 // Two-tile strips of the 64 x 256 FP32 small-term kernel (FP32 output, blocked

@@ -277,3 +277,34 @@ def test_dd_query_validation():
                                  ctypes.byref(h)) == 1
     assert L.cqc_dd_query_create(ctypes.byref(inst), 0, 1, ctypes.byref(ok), 0x1000, 0x2000, 0x3000, 0x4000,
                                  16, None, ctypes.byref(h)) == 4
+
+
+def test_xent_batch_rejects_before_enqueue():
+    """cqc_batch_create_xent validates its bindings before any device work:
+    one instance, NULL target/gradient arrays or entries, and a loss together
+    with a mass are CQC_ERR_INVALID_ARG; a NULL output is allowed (p is not
+    kept), so such a batch gets as far as the workspace check."""
+    L = _lib.lib()
+    I = _lib.CqcInstance * 2
+    a = _inst(8, [4, 4], [(0, 1)], list(range(8)))
+    b = _inst(10, [5, 5], [(0, 1), (0, 1)], list(range(10)))
+    arr = I(a, b)
+    VP2 = ctypes.c_void_p * 2
+    tg, gr = VP2(0x4000, 0x5000), VP2(0x6000, 0x7000)
+    h = ctypes.c_void_p(0)
+
+    def create(n, t, g, losses, ws=0x100000, ws_bytes=1 << 40):
+        return L.cqc_batch_create_xent(arr, n, 0, 0, 1, t, g, losses, ws, ws_bytes, None, ctypes.byref(h))
+
+    assert create(1, tg, gr, None) == 1
+    assert b"two instances" in L.cqc_last_error_detail()
+    assert create(2, None, gr, None) == 1
+    assert create(2, tg, None, None) == 1
+    assert create(2, tg, VP2(0x6000, 0), None) == 1
+    arr[1].mass = 0x8000
+    assert create(2, tg, gr, VP2(0, 0x9000)) == 1
+    assert b"loss and a mass" in L.cqc_last_error_detail()
+    arr[1].mass = None
+    arr[0].out = None
+    assert create(2, tg, gr, VP2(0, 0x9000), ws_bytes=16) == 4
+    assert not h.value
