@@ -54,7 +54,7 @@ struct BwdBuild {
   std::vector<BwdGatherDesc> gathers;
   struct QG {
     int level;
-    bool y;
+    bool y, dual;
     int sb;
     std::vector<std::pair<int64_t, BwdArgs>> steps;   // (blocks, args)
   };
@@ -129,14 +129,30 @@ static Status build_bwd(const cqc_batch_s *bt, const void *const *gout, void *co
     // split-K choice per step side, and one partials region per side sized for
     // the largest step (levels run one after the other)
     std::vector<BwdSide> sx, sy;
+    std::vector<char> dual;
     size_t px_bytes = 0, py_bytes = 0;
     for (const Step &st : p.steps) {
       const TensorSpec &X = p.tensors[st.x], &Y = p.tensors[st.y];
       const int64_t M = int64_t(1) << st.logM, N = int64_t(1) << st.logN;
       const int64_t dz = st.nbatch * M * N;
       const int64_t RXn = int64_t(1) << (2 * st.RX.size()), RYn = int64_t(1) << (2 * st.RY.size());
-      sx.push_back(choose_bwd_side(N, RYn, X.rows() * M, dz, esz, kBatchBwdMinBudget));
-      sy.push_back(choose_bwd_side(M, RXn, Y.rows() * N, dz, esz, kBatchBwdMinBudget));
+      // steps of at most 16 labels: both sides in one pass over dL/dZ
+      const bool d2 = bwd_dual_ok((int)st.S.size(), M, N, !acc_double) && X.entry != -2 && Y.entry != -2;
+      dual.push_back(d2);
+      if (d2) {
+        BwdSide bx, by;
+        bx.kChunk = std::min<int64_t>(N, kDualChunk);
+        bx.kChunks = (int32_t)((N + bx.kChunk - 1) / bx.kChunk);
+        bx.P = RYn * bx.kChunks;
+        by.kChunk = kDualRows;
+        by.kChunks = (int32_t)((M + kDualRows - 1) / kDualRows);
+        by.P = RXn * by.kChunks;
+        sx.push_back(bx);
+        sy.push_back(by);
+      } else {
+        sx.push_back(choose_bwd_side(N, RYn, X.rows() * M, dz, esz, kBatchBwdMinBudget));
+        sy.push_back(choose_bwd_side(M, RXn, Y.rows() * N, dz, esz, kBatchBwdMinBudget));
+      }
       px_bytes = std::max(px_bytes, esz * (size_t)(sx.back().P * X.rows() * M));
       py_bytes = std::max(py_bytes, esz * (size_t)(sy.back().P * Y.rows() * N));
     }
@@ -166,28 +182,50 @@ static Status build_bwd(const cqc_batch_s *bt, const void *const *gout, void *co
       a.rowsY = p.tensors[st.y].rows();
       const double scale = is_last ? std::ldexp(1.0, -p.K) : 1.0;
       const int64_t M = int64_t(1) << st.logM, N = int64_t(1) << st.logN;
-      for (int side = 0; side < 2; ++side) {
-        const int t = side == 0 ? st.x : st.y;
-        const TensorSpec &T = p.tensors[t];
-        if (T.entry == -2) continue;   // unit tensor of a single subcircuit
-        const BwdSide &bs = side == 0 ? sx[s] : sy[s];
-        a.part = ws + (side == 0 ? px_off : py_off);
-        a.kChunk = bs.kChunk;
-        a.kChunks = bs.kChunks;
-        const auto key = std::make_tuple(level, side, bwd_sb(a.nS));
+      if (dual[s]) {
+        a.part = ws + px_off;
+        a.kChunk = sx[s].kChunk;
+        a.kChunks = sx[s].kChunks;
+        a.part2 = ws + py_off;
+        a.kChunks2 = sy[s].kChunks;
+        const auto key = std::make_tuple(level, 2, 1);
         auto it = gidx.find(key);
         if (it == gidx.end()) {
           it = gidx.emplace(key, B.groups.size()).first;
           BwdBuild::QG q;
           q.level = level;
-          q.y = side == 1;
-          q.sb = bwd_sb(a.nS);
+          q.y = false;
+          q.dual = true;
+          q.sb = 1;
           B.groups.push_back(q);
         }
-        B.groups[it->second].steps.push_back({bwd_blocks(a, side == 1), a});
+        B.groups[it->second].steps.push_back({bwd_dual_blocks(a, st.nbatch), a});
+      }
+      for (int side = 0; side < 2; ++side) {
+        const int t = side == 0 ? st.x : st.y;
+        const TensorSpec &T = p.tensors[t];
+        if (T.entry == -2) continue;   // unit tensor of a single subcircuit
+        const BwdSide &bs = side == 0 ? sx[s] : sy[s];
+        if (!dual[s]) {
+          a.part = ws + (side == 0 ? px_off : py_off);
+          a.kChunk = bs.kChunk;
+          a.kChunks = bs.kChunks;
+          const auto key = std::make_tuple(level, side, bwd_sb(a.nS));
+          auto it = gidx.find(key);
+          if (it == gidx.end()) {
+            it = gidx.emplace(key, B.groups.size()).first;
+            BwdBuild::QG q;
+            q.level = level;
+            q.y = side == 1;
+            q.dual = false;
+            q.sb = bwd_sb(a.nS);
+            B.groups.push_back(q);
+          }
+          B.groups[it->second].steps.push_back({bwd_blocks(a, side == 1), a});
+        }
         BwdReduceDesc r;
         std::memset(&r, 0, sizeof(r));
-        r.part = a.part;
+        r.part = ws + (side == 0 ? px_off : py_off);
         r.count = T.rows() * (side == 0 ? M : N);
         r.P = bs.P;
         r.scale = scale;
@@ -276,6 +314,7 @@ static Status bwd_create(cqc_batch_s *bt, const void *const *gout, void *const *
     put(B.prefix_off[q], prefix.data(), sizeof(int64_t) * prefix.size());
     BwdQueue bq;
     bq.y = G.y;
+    bq.dual = G.dual;
     bq.sb = G.sb;
     bq.descs = reinterpret_cast<const BwdArgs *>(ws + B.desc_off[q]);
     bq.prefix = reinterpret_cast<const int64_t *>(ws + B.prefix_off[q]);

@@ -16,7 +16,23 @@ struct BwdArgs {
   int64_t kChunk;      // inner-dimension chunk per partial (multiple of 16)
   int32_t kChunks;     // chunks per rest-label value
   int64_t rowsX, rowsY;
+  // both sides in one pass (k_bwd_dual_queue): the X side's partials go to
+  // part with column chunks of kChunk (kChunks per rY), the Y side's to part2
+  // with row tiles of kDualRows (kChunks2 per rX)
+  void *part2;
+  int32_t kChunks2;
 };
+
+// Both sides of a step from one read of dL/dZ (steps of at most 16 labels,
+// FP32, both operands at least kDualMin wide): row tile and column sub-tile
+// of the staged dL/dZ, and the column chunk of one block.
+constexpr int kDualRows = 128, kDualCols = 64, kDualChunk = 1024, kDualMin = 64;
+inline bool bwd_dual_ok(int nS, int64_t M, int64_t N, bool f32) {
+  return f32 && nS <= 2 && M >= kDualMin && N >= kDualMin;
+}
+inline int64_t bwd_dual_blocks(const BwdArgs &a, int64_t nbatch) {
+  return nbatch * (int64_t)a.kChunks2 * (int64_t)a.kChunks;
+}
 
 // Split-K choice of one side of an adjoint step: inner-dimension chunk, chunks
 // per rest-label value and partial count P = rest * chunks, the smallest
@@ -45,6 +61,7 @@ struct BwdGatherDesc {    // dst[m * N + n] = src[rowoff(m) + coloff(n)], Acc dt
 };
 struct BwdQueue {         // one persistent launch over many steps of one kernel shape
   bool y;                 // dY side (else dX)
+  bool dual = false;      // both sides in one pass (k_bwd_dual_queue; y and sb unused)
   int sb;                 // label blocks of 16 per block tile (bwd_sb)
   const BwdArgs *descs;
   const int64_t *prefix;  // [ndesc + 1] first item of each step

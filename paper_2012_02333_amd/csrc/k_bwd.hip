@@ -248,7 +248,11 @@ __device__ __forceinline__ void bwd_y_block(const BwdArgs &a, int64_t blk) {
 // loaded by every wave; the dL/dZ operand per wave from global memory, one
 // 16-index half ahead.  Y: the dY side (label rows of X over m, dZ columns);
 // else the dX side (label rows of Y over n, dZ rows).
-template <bool YS>
+// FAST: inner extent at least 16, so every chunk is a multiple of 16 and a
+// 16-index group never straddles its end; all loads are unconditional global
+// loads from clamped addresses, and nothing consumes a loaded value before
+// its use (a select right after a load would wait for it there).
+template <bool YS, bool FAST>
 __device__ __forceinline__ void bwd_block_staged(const BwdArgs &a, int64_t blk) {
   constexpr int SB = 4, OB = 4, KS = 32, LD = KS + 4;
   using Op = BOp<float>;
@@ -279,16 +283,38 @@ __device__ __forceinline__ void bwd_block_staged(const BwdArgs &a, int64_t blk) 
   const bool st_ok = s_st < SN;
   const float *lrow = L + (int64_t)(st_ok ? row_of(YS ? a.mx : a.my, s_st, YS ? rX : rY) : 0) * INNER;
   float g[8];
+  // FAST: the label slice's halves past the chunk end (chunks of 16) are
+  // zeroed when staged; a label past 4^nS reads row 0 and feeds only MFMA rows
+  // that are never stored
+  bool gok[2] = {true, true};
   auto gload = [&](int64_t n0) {
     const int64_t c = n0 + 8 * sq;
-    load4m<float>(lrow, c, k1, g);
-    load4m<float>(lrow, c + 4, k1, g + 4);
-    if (!st_ok)
-      for (int e = 0; e < 8; ++e) g[e] = 0.f;
+    if constexpr (FAST) {
+      using gfv = const __attribute__((address_space(1))) f32x4 *;
+      gok[0] = c < k1;
+      gok[1] = c + 4 < k1;
+      const f32x4 q0 = *(gfv)(lrow + (gok[0] ? c : 0));
+      const f32x4 q1 = *(gfv)(lrow + (gok[1] ? c + 4 : 0));
+#pragma unroll
+      for (int t = 0; t < 4; ++t) g[t] = q0[t], g[4 + t] = q1[t];
+    } else {
+      load4m<float>(lrow, c, k1, g);
+      load4m<float>(lrow, c + 4, k1, g + 4);
+      if (!st_ok)
+        for (int e = 0; e < 8; ++e) g[e] = 0.f;
+    }
   };
   auto sstore = [&](int buf) {
-    *reinterpret_cast<float4 *>(&ls[buf][sr][8 * sq]) = make_float4(g[0], g[1], g[2], g[3]);
-    *reinterpret_cast<float4 *>(&ls[buf][sr][8 * sq + 4]) = make_float4(g[4], g[5], g[6], g[7]);
+    if constexpr (FAST) {
+      const float z = 0.f;
+      *reinterpret_cast<float4 *>(&ls[buf][sr][8 * sq]) =
+          gok[0] ? make_float4(g[0], g[1], g[2], g[3]) : make_float4(z, z, z, z);
+      *reinterpret_cast<float4 *>(&ls[buf][sr][8 * sq + 4]) =
+          gok[1] ? make_float4(g[4], g[5], g[6], g[7]) : make_float4(z, z, z, z);
+    } else {
+      *reinterpret_cast<float4 *>(&ls[buf][sr][8 * sq]) = make_float4(g[0], g[1], g[2], g[3]);
+      *reinterpret_cast<float4 *>(&ls[buf][sr][8 * sq + 4]) = make_float4(g[4], g[5], g[6], g[7]);
+    }
   };
   float bv[2][OB][4];
   auto bload = [&](int h, int64_t n0) {
@@ -296,7 +322,22 @@ __device__ __forceinline__ void bwd_block_staged(const BwdArgs &a, int64_t blk) 
 #pragma unroll
     for (int ob = 0; ob < OB; ++ob) {
       const int64_t o = ow + ob * 16 + l16;
-      if (!YS) {
+      if constexpr (FAST) {
+        // c + 3 < k1 always (groups of 16 inside a chunk); an output column
+        // past OUT reads a clamped address and lands in an MFMA column that is
+        // never stored
+        const int64_t oc = o < OUT ? o : 0;
+        if (!YS) {
+          const f32x4 q = *(const __attribute__((address_space(1))) f32x4 *)(dZ + oc * N + c);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) bv[h][ob][t] = q[t];
+        } else {
+          const __attribute__((address_space(1))) float *q =
+              (const __attribute__((address_space(1))) float *)dZ + c * N + oc;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) bv[h][ob][t] = q[t * N];
+        }
+      } else if (!YS) {
         if (o < OUT) load4m<float>(dZ + o * N, c, k1, bv[h][ob]);
         else
           for (int t = 0; t < 4; ++t) bv[h][ob][t] = 0.f;
@@ -322,24 +363,85 @@ __device__ __forceinline__ void bwd_block_staged(const BwdArgs &a, int64_t blk) 
         for (int ob = 0; ob < OB; ++ob) acc[sb][ob] = Op::run(av[t], bv[h][ob][t], acc[sb][ob]);
     }
   };
-  if (k0 < k1) {
-    gload(k0);
-    sstore(0);
-    bload(0, k0);
-  }
-  __syncthreads();
-  int cur = 0;
-  for (int64_t n0 = k0; n0 < k1; n0 += KS) {
-    const bool more = n0 + KS < k1;
-    const bool h1 = n0 + 16 < k1;
-    if (more) gload(n0 + KS);
-    if (h1) bload(1, n0 + 16);
-    half(cur, 0);
-    if (more) bload(0, n0 + KS);
-    if (h1) half(cur, 1);
-    if (more) sstore(cur ^ 1);
+  if constexpr (FAST) {
+    // every operand of step n0 + KS (label slice and both dL/dZ halves) is
+    // loaded at the top of step n0 into a second register set; step n0 reads
+    // only registers loaded one step earlier, so its matrix-core work never
+    // waits on the loads in flight
+    float bn[2][OB][4];
+    if (k0 < k1) {
+      gload(k0);
+      sstore(0);
+      bload(0, k0);
+      if (k0 + 16 < k1) bload(1, k0 + 16);
+    }
     __syncthreads();
-    cur ^= 1;
+    int cur = 0;
+    for (int64_t n0 = k0; n0 < k1; n0 += KS) {
+      const bool more = n0 + KS < k1;
+      const bool h1 = n0 + 16 < k1;
+      const bool h1n = n0 + KS + 16 < k1;
+      if (more) {
+        gload(n0 + KS);
+        const int64_t c = n0 + KS + 4 * lg;
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+          for (int ob = 0; ob < OB; ++ob) {
+            const int64_t o = ow + ob * 16 + l16;
+            const int64_t oc = o < OUT ? o : 0;
+            // the second half of the last step may lie past the chunk: it
+            // reads the first half's address and is never used
+            const int64_t cc = hh == 0 || h1n ? c + 16 * hh : c;
+            if (!YS) {
+              const f32x4 q = *(const __attribute__((address_space(1))) f32x4 *)(dZ + oc * N + cc);
+#pragma unroll
+              for (int t = 0; t < 4; ++t) bn[hh][ob][t] = q[t];
+            } else {
+              const __attribute__((address_space(1))) float *q =
+                  (const __attribute__((address_space(1))) float *)dZ + cc * N + oc;
+#pragma unroll
+              for (int t = 0; t < 4; ++t) bn[hh][ob][t] = q[t * N];
+            }
+          }
+      }
+      // keep the loads above the matrix-core work (the scheduler would sink
+      // them next to their use to save registers, and the work would wait)
+      __builtin_amdgcn_sched_barrier(0);
+      half(cur, 0);
+      if (h1) half(cur, 1);
+      if (more) {
+        sstore(cur ^ 1);
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+          for (int ob = 0; ob < OB; ++ob)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) bv[hh][ob][t] = bn[hh][ob][t];
+      }
+      __syncthreads();
+      cur ^= 1;
+    }
+  } else {
+    if (k0 < k1) {
+      gload(k0);
+      sstore(0);
+      bload(0, k0);
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int64_t n0 = k0; n0 < k1; n0 += KS) {
+      const bool more = n0 + KS < k1;
+      const bool h1 = n0 + 16 < k1;
+      if (more) gload(n0 + KS);
+      if (h1) bload(1, n0 + 16);
+      half(cur, 0);
+      if (more) bload(0, n0 + KS);
+      if (h1) half(cur, 1);
+      if (more) sstore(cur ^ 1);
+      __syncthreads();
+      cur ^= 1;
+    }
   }
   float *part = static_cast<float *>(a.part) + p * (YS ? a.rowsY : a.rowsX) * OUT;
 #pragma unroll
@@ -358,15 +460,23 @@ __device__ __forceinline__ void bwd_block_staged(const BwdArgs &a, int64_t blk) 
 template <typename T, int SB, int MB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BwdCfg<T, SB>::kWaves, 8)))
 void k_bwd_x(const BwdArgs a) {
-  if constexpr (sizeof(T) == 4 && SB == 4 && MB == 4) bwd_block_staged<false>(a, blockIdx.x);
-  else bwd_x_block<T, SB, MB>(a, blockIdx.x);
+  if constexpr (sizeof(T) == 4 && SB == 4 && MB == 4) {
+    if (a.logN >= 4) bwd_block_staged<false, true>(a, blockIdx.x);
+    else bwd_block_staged<false, false>(a, blockIdx.x);
+  } else {
+    bwd_x_block<T, SB, MB>(a, blockIdx.x);
+  }
 }
 
 template <typename T, int SB, int NB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BwdCfg<T, SB>::kWaves, 8)))
 void k_bwd_y(const BwdArgs a) {
-  if constexpr (sizeof(T) == 4 && SB == 4 && NB == 4) bwd_block_staged<true>(a, blockIdx.x);
-  else bwd_y_block<T, SB, NB>(a, blockIdx.x);
+  if constexpr (sizeof(T) == 4 && SB == 4 && NB == 4) {
+    if (a.logM >= 4) bwd_block_staged<true, true>(a, blockIdx.x);
+    else bwd_block_staged<true, false>(a, blockIdx.x);
+  } else {
+    bwd_y_block<T, SB, NB>(a, blockIdx.x);
+  }
 }
 
 // Many adjoint steps of one shape in one persistent launch: blocks take
@@ -385,11 +495,172 @@ void k_bwd_queue(const BwdArgs *descs, const int64_t *prefix, int ndesc, unsigne
     if (it >= total) return;
     const int d = find_desc(prefix, ndesc, it);
     if constexpr (sizeof(T) == 4 && SB == 4 && MB == 4) {
-      bwd_block_staged<Y>(descs[d], it - prefix[d]);
+      const BwdArgs &a = descs[d];
+      if ((Y ? a.logM : a.logN) >= 4) bwd_block_staged<Y, true>(a, it - prefix[d]);
+      else bwd_block_staged<Y, false>(a, it - prefix[d]);
     } else {
       if (Y) bwd_y_block<T, SB, MB>(descs[d], it - prefix[d]);
       else bwd_x_block<T, SB, MB>(descs[d], it - prefix[d]);
     }
+  }
+}
+
+// ---- Both sides of a step with at most 16 labels from one read of dL/dZ.
+// A block takes one batch entry b = (rX, rY), a tile of kDualRows rows of
+// dZ_b and a chunk of kDualChunk columns, and streams the chunk through LDS in
+// sub-tiles of kDualRows x kDualCols (double-buffered: the next sub-tile's
+// loads are in flight while the current one is on the matrix cores).  Both
+// products take their dL/dZ operand from the staged sub-tile:
+//   dX[rowX(s,rX)][m] (+)= sum_n Y[rowY(s,rY)][n] dZ_b[m][n]: wave w owns rows
+//     32 w .. 32 w + 31 of the tile and accumulates over the whole chunk;
+//   dY[rowY(s,rY)][n] (+)= sum_m X[rowX(s,rX)][m] dZ_b[m][n]: wave w owns
+//     columns 16 w .. 16 w + 15 of each sub-tile and sums over the tile's rows.
+// Label s is MFMA row l % 16 (labels >= 4^nS are zero rows); lane l feeds the
+// inner indices 4 (l / 16) + t of a 16-index group to MFMA t.  The label
+// operands of the next sub-tile are loaded with its dL/dZ, so no wait inside
+// the matrix-core loop covers the staging loads.  Partials (fixed order, added
+// by the reduce pass): X side part[(rY kChunks + column chunk)][row][m], Y side
+// part2[(rX kChunks2 + row tile)][row][n].
+__device__ __forceinline__ void bwd_dual_block(const BwdArgs &a, int64_t blk) {
+  constexpr int TR = kDualRows, TC = kDualCols, LD = TC + 4;
+  using V = f32x4;
+  __shared__ float gs[2][TR][LD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, lg = lane >> 4;
+  const int64_t M = int64_t(1) << a.logM, N = int64_t(1) << a.logN;
+  const int RYn = 1 << (2 * a.nRY), SN = 1 << (2 * a.nS);
+  int64_t b = blk;
+  const int kc = (int)(b % a.kChunks); b /= a.kChunks;
+  const int mt = (int)(b % a.kChunks2); b /= a.kChunks2;
+  const int rX = (int)(b / RYn), rY = (int)(b % RYn);
+  const int64_t m0 = (int64_t)mt * TR;
+  const int64_t n0 = (int64_t)kc * a.kChunk;
+  const int64_t n1 = N < n0 + a.kChunk ? N : n0 + a.kChunk;
+  const float *X = static_cast<const float *>(a.X);
+  const float *Y = static_cast<const float *>(a.Y);
+  const float *dZ = static_cast<const float *>(a.dZ) + ((int64_t)rX * RYn + rY) * M * N;
+  // Every load below is an unconditional 16-byte global load: the column
+  // sub-tiles are always whole (N >= 64, both powers of two), and a row past M
+  // (tiles of M = 64) or a label past 4^nS reads a clamped in-range address.
+  // Rows past M are zeroed when staged (they are summed over for dY); a label
+  // past 4^nS only feeds MFMA output rows that are never stored.  Nothing
+  // consumes a loaded value before the staging point, so no wait sits between
+  // the loads and the matrix-core work they overlap.
+  auto ld = [](const float *p) {
+    const f32x4 v = *(const __attribute__((address_space(1))) f32x4 *)p;
+    return make_float4(v[0], v[1], v[2], v[3]);
+  };
+  auto sel = [](bool ok, float4 v) {
+    return make_float4(ok ? v.x : 0.f, ok ? v.y : 0.f, ok ? v.z : 0.f, ok ? v.w : 0.f);
+  };
+  // this lane's label row as an MFMA operand row (label l % 16)
+  const bool sok = l16 < SN;
+  const float *xl = X + (int64_t)(sok ? row_of(a.mx, l16, rX) : 0) * M;
+  const float *yl = Y + (int64_t)(sok ? row_of(a.my, l16, rY) : 0) * N;
+  // X operands of the tile's rows, once per block: rows m0 + 16 kr + 4 lg + t
+  float xa[TR / 16][4];
+#pragma unroll
+  for (int kr = 0; kr < TR / 16; ++kr) {
+    const int64_t m = m0 + 16 * kr + 4 * lg;
+    const float4 v = sel(m < M, ld(xl + (m < M ? m : 0)));
+    xa[kr][0] = v.x, xa[kr][1] = v.y, xa[kr][2] = v.z, xa[kr][3] = v.w;
+  }
+  // staging: thread t loads rows t / 16 + 16 j, columns 4 (t % 16) + 0..3
+  float4 gr[TR / 16];
+  float4 yn[TC / 16];
+  auto load_sub = [&](int64_t c0) {
+#pragma unroll
+    for (int j = 0; j < TR / 16; ++j) {
+      const int64_t m = m0 + (tid >> 4) + 16 * j;
+      gr[j] = ld(dZ + (m < M ? m : 0) * N + c0 + 4 * (tid & 15));
+    }
+#pragma unroll
+    for (int kq = 0; kq < TC / 16; ++kq) yn[kq] = ld(yl + c0 + 16 * kq + 4 * lg);
+  };
+  auto store_sub = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < TR / 16; ++j)
+      *reinterpret_cast<float4 *>(&gs[buf][(tid >> 4) + 16 * j][4 * (tid & 15)]) =
+          sel(m0 + (tid >> 4) + 16 * j < M, gr[j]);
+  };
+  V ax[2] = {V{0, 0, 0, 0}, V{0, 0, 0, 0}};
+  float4 yc[TC / 16];
+  const int nsub = (int)((n1 - n0) / TC);
+  load_sub(n0);
+  store_sub(0);
+#pragma unroll
+  for (int kq = 0; kq < TC / 16; ++kq) yc[kq] = yn[kq];
+  __syncthreads();
+  __attribute__((address_space(1))) float *part2 =
+      (__attribute__((address_space(1))) float *)static_cast<float *>(a.part2) +
+      ((int64_t)rX * a.kChunks2 + mt) * a.rowsY * N;
+  int yrow[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int sr = 4 * lg + r;
+    yrow[r] = sr < SN ? row_of(a.my, sr, rY) : -1;
+  }
+  for (int i = 0; i < nsub; ++i) {
+    const int cur = i & 1;
+    const int64_t c0 = n0 + (int64_t)i * TC;
+    const bool more = i + 1 < nsub;
+    if (more) load_sub(c0 + TC);
+    // dX: rows 32 w + 16 mb + l16 against the sub-tile's 64 columns
+#pragma unroll
+    for (int kq = 0; kq < TC / 16; ++kq)
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb) {
+        const float4 g = *reinterpret_cast<const float4 *>(&gs[cur][32 * wave + 16 * mb + l16][16 * kq + 4 * lg]);
+        const float gv[4] = {g.x, g.y, g.z, g.w};
+        const float yv[4] = {yc[kq].x, yc[kq].y, yc[kq].z, yc[kq].w};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) ax[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(yv[t], gv[t], ax[mb], 0, 0, 0);
+      }
+    // dY: columns 16 w + l16 over the tile's rows
+    V ay = V{0, 0, 0, 0};
+#pragma unroll
+    for (int kr = 0; kr < TR / 16; ++kr)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        ay = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[kr][t], gs[cur][16 * kr + 4 * lg + t][16 * wave + l16], ay, 0, 0, 0);
+    const int64_t n = c0 + 16 * wave + l16;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (yrow[r] >= 0) part2[(int64_t)yrow[r] * N + n] = ay[r];
+    if (more) {
+      store_sub(cur ^ 1);
+#pragma unroll
+      for (int kq = 0; kq < TC / 16; ++kq) yc[kq] = yn[kq];
+    }
+    __syncthreads();
+  }
+  __attribute__((address_space(1))) float *part =
+      (__attribute__((address_space(1))) float *)static_cast<float *>(a.part) +
+      ((int64_t)rY * a.kChunks + kc) * a.rowsX * M;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int sr = 4 * lg + r;
+    if (sr >= SN) continue;
+    const int64_t row = row_of(a.mx, sr, rX);
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+      const int64_t m = m0 + 32 * wave + 16 * mb + l16;
+      if (m < M) part[row * M + m] = ax[mb][r];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_bwd_dual_queue(const BwdArgs *descs, const int64_t *prefix, int ndesc,
+                                                        unsigned long long *queue, int64_t total) {
+  __shared__ int64_t item;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) item = (int64_t)atomicAdd(queue, 1ull);
+    __syncthreads();
+    const int64_t it = item;
+    if (it >= total) return;
+    const int d = find_desc(prefix, ndesc, it);
+    bwd_dual_block(descs[d], it - prefix[d]);
   }
 }
 
@@ -574,6 +845,11 @@ static Status launch_bwd_queue_t(const BwdQueue &q, hipStream_t s) {
 
 Status launch_bwd_queue(Acc acc, const BwdQueue &q, hipStream_t s) {
   if (q.total <= 0) return Status::ok();
+  if (q.dual) {
+    if (acc != Acc::F32) return Status::fail(CQC_ERR_INVALID_ARG, "the two-sided adjoint pass is FP32 only");
+    return launch("bwd_dual_queue", k_bwd_dual_queue, dim3(q.grid), dim3(256), 0, s, q.descs, q.prefix, q.ndesc,
+                  q.queue, q.total);
+  }
   return acc == Acc::F32 ? launch_bwd_queue_t<float>(q, s) : launch_bwd_queue_t<double>(q, s);
 }
 
