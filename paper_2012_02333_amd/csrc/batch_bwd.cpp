@@ -236,6 +236,7 @@ static Status build_bwd(const cqc_batch_s *bt, const void *const *gout, void *co
           r.out = ws + dz_off[t];
           r.out_double = acc_double ? 1 : 0;
         }
+        r.vec = !acc_double && r.count % 4 == 0 && reinterpret_cast<uintptr_t>(r.out) % 16 == 0 ? 1 : 0;
         B.red[level].push_back(r);
       }
     }
@@ -326,7 +327,7 @@ static Status bwd_create(cqc_batch_s *bt, const void *const *gout, void *const *
   }
   for (size_t l = 0; l < B.red.size(); ++l) {
     std::vector<int64_t> rstart(1, 0);
-    for (auto &r : B.red[l]) rstart.push_back(rstart.back() + blocks_of(r.count));
+    for (auto &r : B.red[l]) rstart.push_back(rstart.back() + bwd_reduce_blocks(r));
     put(B.red_off[l], B.red[l].data(), sizeof(BwdReduceDesc) * B.red[l].size());
     put(B.rstart_off[l], rstart.data(), sizeof(int64_t) * rstart.size());
     h->levels[l].red = reinterpret_cast<const BwdReduceDesc *>(ws + B.red_off[l]);

@@ -52,7 +52,12 @@ struct BwdReduceDesc {    // out[i] = scale * sum_{p < P} part[p][i], i < count
   int64_t count, P;
   double scale;
   int32_t out_double;
+  int32_t vec;            // FP32 partials, count % 4 == 0, out 16-byte aligned: four outputs per thread
 };
+// Blocks of the batched reduce for one descriptor (256 threads each).
+inline int64_t bwd_reduce_blocks(const BwdReduceDesc &r) {
+  return r.vec ? (r.count + 1023) / 1024 : (r.count + 255) / 256;
+}
 struct BwdGatherDesc {    // dst[m * N + n] = src[rowoff(m) + coloff(n)], Acc dtype
   const void *src;
   void *dst;
