@@ -210,7 +210,7 @@ static Status build_bwd(const cqc_batch_s *bt, const void *const *gout, void *co
           a.part = ws + (side == 0 ? px_off : py_off);
           a.kChunk = bs.kChunk;
           a.kChunks = bs.kChunks;
-          const auto key = std::make_tuple(level, side, bwd_sb(a.nS));
+          const auto key = std::make_tuple(level, side, bwd_sb(a.nS, side == 1, !acc_double));
           auto it = gidx.find(key);
           if (it == gidx.end()) {
             it = gidx.emplace(key, B.groups.size()).first;
@@ -218,10 +218,10 @@ static Status build_bwd(const cqc_batch_s *bt, const void *const *gout, void *co
             q.level = level;
             q.y = side == 1;
             q.dual = false;
-            q.sb = bwd_sb(a.nS);
+            q.sb = bwd_sb(a.nS, side == 1, !acc_double);
             B.groups.push_back(q);
           }
-          B.groups[it->second].steps.push_back({bwd_blocks(a, side == 1), a});
+          B.groups[it->second].steps.push_back({bwd_blocks(a, side == 1, !acc_double), a});
         }
         BwdReduceDesc r;
         std::memset(&r, 0, sizeof(r));

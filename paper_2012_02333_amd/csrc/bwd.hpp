@@ -76,8 +76,8 @@ struct BwdQueue {         // one persistent launch over many steps of one kernel
   uint32_t grid;
 };
 
-int bwd_sb(int nS);
-int64_t bwd_blocks(const BwdArgs &a, bool which_y);
+int bwd_sb(int nS, bool y, bool f32);
+int64_t bwd_blocks(const BwdArgs &a, bool which_y, bool f32);
 Status launch_bwd(Acc acc, const BwdArgs &a, bool which_y, hipStream_t s);
 Status launch_bwd_queue(Acc acc, const BwdQueue &q, hipStream_t s);
 Status launch_bwd_reduce_table(Acc acc, const BwdReduceDesc *descs, const int64_t *start, int ndesc,

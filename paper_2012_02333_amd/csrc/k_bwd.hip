@@ -58,7 +58,7 @@ __device__ __forceinline__ void load4m(const T *p, int64_t c, int64_t lim, T *v)
 // one-label-block form, two for the others (no constraint without prefetch).
 template <typename T, int SB> struct BwdCfg {
   static constexpr bool kPF = sizeof(T) == 4 && SB <= 4;
-  static constexpr int kWaves = !kPF ? 1 : (SB == 1 ? 4 : 2);
+  static constexpr int kWaves = sizeof(T) == 4 && SB == 16 ? 2 : (!kPF ? 1 : (SB == 1 ? 4 : 2));
 };
 
 // grid: x = (((p * RXn + rX) * sSuper + ss) * mTiles + mt), p = (rY, k-chunk)
@@ -243,25 +243,27 @@ __device__ __forceinline__ void bwd_y_block(const BwdArgs &a, int64_t blk) {
     }
 }
 
-// 64 label rows x 256 outputs per block (four waves of 64), the label rows'
-// 32-index slices staged in LDS once per block (double-buffered) instead of
-// loaded by every wave; the dL/dZ operand per wave from global memory, one
-// 16-index half ahead.  Y: the dY side (label rows of X over m, dZ columns);
+// 16 SB label rows x 64 OB outputs per block (four waves of 16 OB: 64 x 256
+// or 256 x 64), the label rows' 32-index slices staged in LDS once per block
+// (double-buffered) instead of loaded by every wave; the dL/dZ operand per
+// wave from global memory, one 16-index half ahead.  Y: the dY side (label rows of X over m, dZ columns);
 // else the dX side (label rows of Y over n, dZ rows).
 // FAST: inner extent at least 16, so every chunk is a multiple of 16 and a
 // 16-index group never straddles its end; all loads are unconditional global
 // loads from clamped addresses, and nothing consumes a loaded value before
 // its use (a select right after a load would wait for it there).
-template <bool YS, bool FAST>
-__device__ __forceinline__ void bwd_block_staged(const BwdArgs &a, int64_t blk) {
-  // LD = 36 floats.  The 16-byte fragment reads conflict on LDS banks at this
+constexpr int kStagedLd = 36;
+template <bool YS, bool FAST, int SB = 4, int OB = 4>
+__device__ __forceinline__ void bwd_block_staged(const BwdArgs &a, int64_t blk, float (*ls)[16 * SB][kStagedLd]) {
+  // Pitch 36 floats.  The 16-byte fragment reads conflict on LDS banks at this
   // pitch (a 40-float pitch removes that, measured) - but the kernel measured
   // 8% slower with the conflict-free pitch, so the conflicts are not what
   // bounds it
-  constexpr int SB = 4, OB = 4, KS = 32, LD = KS + 4;
+  constexpr int KS = 32;
+  static_assert(kStagedLd == KS + 4, "staging pitch");
+  constexpr int RPT = SB / 4;   // label rows staged per thread
   using Op = BOp<float>;
   using V = typename Op::V;
-  __shared__ float ls[2][64][LD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, lg = lane >> 4;
   const int64_t M = int64_t(1) << a.logM, N = int64_t(1) << a.logN;
@@ -281,12 +283,18 @@ __device__ __forceinline__ void bwd_block_staged(const BwdArgs &a, int64_t blk) 
   const int64_t ow = ot * 64 * OB + wave * 16 * OB;
   const float *L = static_cast<const float *>(YS ? a.X : a.Y);
   const float *dZ = static_cast<const float *>(a.dZ) + ((int64_t)rX * RYn + rY) * M * N;
-  // staging: thread t owns label row t >> 2, eight inner indices at 8 (t & 3)
+  // staging: thread t owns label rows t / 4 + 64 r, eight inner indices at
+  // 8 (t % 4)
   const int sr = tid >> 2, sq = tid & 3;
-  const int s_st = ss * 64 + sr;
-  const bool st_ok = s_st < SN;
-  const float *lrow = L + (int64_t)(st_ok ? row_of(YS ? a.mx : a.my, s_st, YS ? rX : rY) : 0) * INNER;
-  float g[8];
+  bool st_ok[RPT];
+  const float *lrow[RPT];
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int s_st = ss * 16 * SB + sr + 64 * r;
+    st_ok[r] = s_st < SN;
+    lrow[r] = L + (int64_t)(st_ok[r] ? row_of(YS ? a.mx : a.my, s_st, YS ? rX : rY) : 0) * INNER;
+  }
+  float g[RPT][8];
   // FAST: the label slice's halves past the chunk end (chunks of 16) are
   // zeroed when staged; a label past 4^nS reads row 0 and feeds only MFMA rows
   // that are never stored
@@ -297,27 +305,37 @@ __device__ __forceinline__ void bwd_block_staged(const BwdArgs &a, int64_t blk) 
       using gfv = const __attribute__((address_space(1))) f32x4 *;
       gok[0] = c < k1;
       gok[1] = c + 4 < k1;
-      const f32x4 q0 = *(gfv)(lrow + (gok[0] ? c : 0));
-      const f32x4 q1 = *(gfv)(lrow + (gok[1] ? c + 4 : 0));
 #pragma unroll
-      for (int t = 0; t < 4; ++t) g[t] = q0[t], g[4 + t] = q1[t];
+      for (int r = 0; r < RPT; ++r) {
+        const f32x4 q0 = *(gfv)(lrow[r] + (gok[0] ? c : 0));
+        const f32x4 q1 = *(gfv)(lrow[r] + (gok[1] ? c + 4 : 0));
+#pragma unroll
+        for (int t = 0; t < 4; ++t) g[r][t] = q0[t], g[r][4 + t] = q1[t];
+      }
     } else {
-      load4m<float>(lrow, c, k1, g);
-      load4m<float>(lrow, c + 4, k1, g + 4);
-      if (!st_ok)
-        for (int e = 0; e < 8; ++e) g[e] = 0.f;
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        load4m<float>(lrow[r], c, k1, g[r]);
+        load4m<float>(lrow[r], c + 4, k1, g[r] + 4);
+        if (!st_ok[r])
+          for (int e = 0; e < 8; ++e) g[r][e] = 0.f;
+      }
     }
   };
   auto sstore = [&](int buf) {
-    if constexpr (FAST) {
-      const float z = 0.f;
-      *reinterpret_cast<float4 *>(&ls[buf][sr][8 * sq]) =
-          gok[0] ? make_float4(g[0], g[1], g[2], g[3]) : make_float4(z, z, z, z);
-      *reinterpret_cast<float4 *>(&ls[buf][sr][8 * sq + 4]) =
-          gok[1] ? make_float4(g[4], g[5], g[6], g[7]) : make_float4(z, z, z, z);
-    } else {
-      *reinterpret_cast<float4 *>(&ls[buf][sr][8 * sq]) = make_float4(g[0], g[1], g[2], g[3]);
-      *reinterpret_cast<float4 *>(&ls[buf][sr][8 * sq + 4]) = make_float4(g[4], g[5], g[6], g[7]);
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      float *d = &ls[buf][sr + 64 * r][8 * sq];
+      if constexpr (FAST) {
+        const float z = 0.f;
+        *reinterpret_cast<float4 *>(d) =
+            gok[0] ? make_float4(g[r][0], g[r][1], g[r][2], g[r][3]) : make_float4(z, z, z, z);
+        *reinterpret_cast<float4 *>(d + 4) =
+            gok[1] ? make_float4(g[r][4], g[r][5], g[r][6], g[r][7]) : make_float4(z, z, z, z);
+      } else {
+        *reinterpret_cast<float4 *>(d) = make_float4(g[r][0], g[r][1], g[r][2], g[r][3]);
+        *reinterpret_cast<float4 *>(d + 4) = make_float4(g[r][4], g[r][5], g[r][6], g[r][7]);
+      }
     }
   };
   float bv[2][OB][4];
@@ -464,9 +482,10 @@ __device__ __forceinline__ void bwd_block_staged(const BwdArgs &a, int64_t blk) 
 template <typename T, int SB, int MB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BwdCfg<T, SB>::kWaves, 8)))
 void k_bwd_x(const BwdArgs a) {
-  if constexpr (sizeof(T) == 4 && SB == 4 && MB == 4) {
-    if (a.logN >= 4) bwd_block_staged<false, true>(a, blockIdx.x);
-    else bwd_block_staged<false, false>(a, blockIdx.x);
+  if constexpr (sizeof(T) == 4 && ((SB == 4 && MB == 4) || (SB == 16 && MB == 1))) {
+    __shared__ float ls[2][16 * SB][kStagedLd];
+    if (a.logN >= 4) bwd_block_staged<false, true, SB, MB>(a, blockIdx.x, ls);
+    else bwd_block_staged<false, false, SB, MB>(a, blockIdx.x, ls);
   } else {
     bwd_x_block<T, SB, MB>(a, blockIdx.x);
   }
@@ -475,9 +494,10 @@ void k_bwd_x(const BwdArgs a) {
 template <typename T, int SB, int NB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BwdCfg<T, SB>::kWaves, 8)))
 void k_bwd_y(const BwdArgs a) {
-  if constexpr (sizeof(T) == 4 && SB == 4 && NB == 4) {
-    if (a.logM >= 4) bwd_block_staged<true, true>(a, blockIdx.x);
-    else bwd_block_staged<true, false>(a, blockIdx.x);
+  if constexpr (sizeof(T) == 4 && ((SB == 4 && NB == 4) || (SB == 16 && NB == 1))) {
+    __shared__ float ls[2][16 * SB][kStagedLd];
+    if (a.logM >= 4) bwd_block_staged<true, true, SB, NB>(a, blockIdx.x, ls);
+    else bwd_block_staged<true, false, SB, NB>(a, blockIdx.x, ls);
   } else {
     bwd_y_block<T, SB, NB>(a, blockIdx.x);
   }
@@ -498,10 +518,11 @@ void k_bwd_queue(const BwdArgs *descs, const int64_t *prefix, int ndesc, unsigne
     const int64_t it = item;
     if (it >= total) return;
     const int d = find_desc(prefix, ndesc, it);
-    if constexpr (sizeof(T) == 4 && SB == 4 && MB == 4) {
+    if constexpr (sizeof(T) == 4 && ((SB == 4 && MB == 4) || (SB == 16 && MB == 1))) {
+      __shared__ float ls[2][16 * SB][kStagedLd];
       const BwdArgs &a = descs[d];
-      if ((Y ? a.logM : a.logN) >= 4) bwd_block_staged<Y, true>(a, it - prefix[d]);
-      else bwd_block_staged<Y, false>(a, it - prefix[d]);
+      if ((Y ? a.logM : a.logN) >= 4) bwd_block_staged<Y, true, SB, MB>(a, it - prefix[d], ls);
+      else bwd_block_staged<Y, false, SB, MB>(a, it - prefix[d], ls);
     } else {
       if (Y) bwd_y_block<T, SB, MB>(descs[d], it - prefix[d]);
       else bwd_x_block<T, SB, MB>(descs[d], it - prefix[d]);
@@ -813,17 +834,26 @@ __global__ __launch_bounds__(256) void k_bwd_prep(const BwdGatherDesc *descs, co
   }
 }
 
-// Label blocks of 16 per block tile.  Three and four shared cuts take 64
-// labels per tile: with 256 every wave of a block loads the same 256 operand
-// rows per inner step, and the operand traffic, not the matrix cores, sets the
-// time (measured 1.5x slower than 64 at four cuts, where dL/dZ is read four
-// times instead of once).  Five and more keep 256 (dL/dZ would be read 16 times).
-static int sb_for(int nS) { return nS <= 2 ? 1 : (nS <= 4 ? 4 : 16); }
+// Label blocks of 16 per block tile.  Three shared cuts take 64 labels per
+// tile.  Four take 64 on the dY side and, in FP32, 256 on the dX side: there
+// the 256 label rows of a 32-index slice are staged in LDS once per block (as
+// the 64 are), dL/dZ is read once instead of four times, and the dX launch
+// measured 9% faster; the dY side, whose dL/dZ loads are strided columns,
+// measured 5% slower with 256 and keeps 64.  (An earlier 256-label form in
+// which every wave loaded the same 256 operand rows itself was 1.5x slower
+// than 64.)  Five and more cuts take 256 (dL/dZ would otherwise be read 16
+// times).
+static int sb_for(int nS, bool y, bool f32) {
+  if (nS <= 2) return 1;
+  if (nS == 3) return 4;
+  if (nS == 4) return f32 && !y ? 16 : 4;
+  return 16;
+}
 
 template <typename T>
 static Status launch_bwd_t(const BwdArgs &a, bool which_y, hipStream_t s) {
   const int SN = 1 << (2 * a.nS);
-  const int SB = sb_for(a.nS);
+  const int SB = sb_for(a.nS, which_y, sizeof(T) == 4);
   const int sSuper = (SN + 16 * SB - 1) / (16 * SB);
   const int64_t M = int64_t(1) << a.logM, N = int64_t(1) << a.logN;
   const int RXn = 1 << (2 * a.nRX), RYn = 1 << (2 * a.nRY);
@@ -849,11 +879,11 @@ Status launch_bwd(Acc acc, const BwdArgs &a, bool which_y, hipStream_t s) {
   return acc == Acc::F32 ? launch_bwd_t<float>(a, which_y, s) : launch_bwd_t<double>(a, which_y, s);
 }
 
-int bwd_sb(int nS) { return sb_for(nS); }
+int bwd_sb(int nS, bool y, bool f32) { return sb_for(nS, y, f32); }
 
-int64_t bwd_blocks(const BwdArgs &a, bool which_y) {
+int64_t bwd_blocks(const BwdArgs &a, bool which_y, bool f32) {
   const int SN = 1 << (2 * a.nS);
-  const int SB = sb_for(a.nS);
+  const int SB = sb_for(a.nS, which_y, f32);
   const int sSuper = (SN + 16 * SB - 1) / (16 * SB);
   const int64_t M = int64_t(1) << a.logM, N = int64_t(1) << a.logN;
   const int64_t RXn = int64_t(1) << (2 * a.nRX), RYn = int64_t(1) << (2 * a.nRY);

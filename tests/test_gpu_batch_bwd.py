@@ -22,8 +22,10 @@ cqc = pytest.importorskip("paper_2012_02333_amd")
 C = W.CutMap
 # permuted output order (dL/dp gathered), Kronecker product, single
 # subcircuit, cyclic three-subcircuit graph (an intermediate level), ragged
-# widths, three and four shared cuts (label blocks of 64 and 256), a chain of
-# three with two cuts per boundary, and a larger two-cut pair
+# widths, three, four and five shared cuts (label blocks of 64, of 256 on the
+# dX side at four in FP32, of 256 at five), a chain of three with two cuts per
+# boundary, a larger two-cut pair, and a four-cut pair with several output
+# tiles and inner chunks per side
 MIXED = [C(9, [4, 5], [0, 0], [1, 1], [5, 0, 3, 8, 1, 2, 4, 7, 6]),
          C(7, [3, 4], [], [], list(range(7))),
          C(6, [6], [], [], [3, 1, 0, 5, 2, 4]),
@@ -32,7 +34,9 @@ MIXED = [C(9, [4, 5], [0, 0], [1, 1], [5, 0, 3, 8, 1, 2, 4, 7, 6]),
          C(10, [5, 5], [0, 0, 0], [1, 1, 1], list(range(10))),
          C(10, [5, 5], [0, 0, 0, 0], [1, 1, 1, 1], list(range(10))),
          C(15, [5, 5, 5], [0, 0, 1, 1], [1, 1, 2, 2], list(range(15))),
-         C(14, [7, 7], [0, 0], [1, 1], list(range(14)))]
+         C(14, [7, 7], [0, 0], [1, 1], list(range(14))),
+         C(12, [6, 6], [0] * 5, [1] * 5, list(range(12))),
+         C(17, [9, 8], [0] * 4, [1] * 4, list(range(17)))]
 
 
 def _gpu():
