@@ -339,8 +339,27 @@ __device__ __forceinline__ void bwd_block_staged(const BwdArgs &a, int64_t blk, 
     }
   };
   float bv[2][OB][4];
+  // dY side, FAST, four output blocks, at least four columns: block ob of a
+  // wave takes the columns ow + 4 j + ob (j the MFMA column), so a lane's four
+  // blocks are four adjacent columns of one dL/dZ row and come in one 16-byte
+  // load per inner index (a 256-byte row segment per 16 lanes) instead of four
+  // strided element loads
+  constexpr bool kVecY = YS && FAST && OB == 4;
+  const bool vecy = kVecY && OUT >= 4;
+  const int64_t o4 = ow + 4 * l16, oc4 = o4 < OUT ? o4 : 0;
   auto bload = [&](int h, int64_t n0) {
     const int64_t c = n0 + 4 * lg;
+    if constexpr (kVecY) {
+      if (vecy) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const f32x4 q = *(const __attribute__((address_space(1))) f32x4 *)(dZ + (c + t) * N + oc4);
+#pragma unroll
+          for (int ob = 0; ob < OB; ++ob) bv[h][ob][t] = q[ob];
+        }
+        return;
+      }
+    }
 #pragma unroll
     for (int ob = 0; ob < OB; ++ob) {
       const int64_t o = ow + ob * 16 + l16;
@@ -407,7 +426,19 @@ __device__ __forceinline__ void bwd_block_staged(const BwdArgs &a, int64_t blk, 
         gload(n0 + KS);
         const int64_t c = n0 + KS + 4 * lg;
 #pragma unroll
-        for (int hh = 0; hh < 2; ++hh)
+        for (int hh = 0; hh < 2; ++hh) {
+          if constexpr (kVecY) {
+            if (vecy) {
+              const int64_t cc = hh == 0 || h1n ? c + 16 * hh : c;
+#pragma unroll
+              for (int t = 0; t < 4; ++t) {
+                const f32x4 q = *(const __attribute__((address_space(1))) f32x4 *)(dZ + (cc + t) * N + oc4);
+#pragma unroll
+                for (int ob = 0; ob < OB; ++ob) bn[hh][ob][t] = q[ob];
+              }
+              continue;
+            }
+          }
 #pragma unroll
           for (int ob = 0; ob < OB; ++ob) {
             const int64_t o = ow + ob * 16 + l16;
@@ -426,6 +457,7 @@ __device__ __forceinline__ void bwd_block_staged(const BwdArgs &a, int64_t blk, 
               for (int t = 0; t < 4; ++t) bn[hh][ob][t] = q[t * N];
             }
           }
+        }
       }
       // keep the loads above the matrix-core work (the scheduler would sink
       // them next to their use to save registers, and the work would wait)
@@ -466,6 +498,23 @@ __device__ __forceinline__ void bwd_block_staged(const BwdArgs &a, int64_t blk, 
     }
   }
   float *part = static_cast<float *>(a.part) + p * (YS ? a.rowsY : a.rowsX) * OUT;
+  if constexpr (kVecY) {
+    if (vecy) {
+      // a lane's four output blocks are four adjacent columns (OUT, a power
+      // of two of at least four, holds whole groups of four): one 16-byte
+      // store per label row
+#pragma unroll
+      for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int s = (ss * SB + sb) * 16 + 4 * lg + r;
+          if (s < SN && o4 < OUT)
+            *reinterpret_cast<float4 *>(part + (int64_t)row_of(a.my, s, rO) * OUT + o4) =
+                make_float4(acc[sb][0][r], acc[sb][1][r], acc[sb][2][r], acc[sb][3][r]);
+        }
+      return;
+    }
+  }
 #pragma unroll
   for (int sb = 0; sb < SB; ++sb)
 #pragma unroll

@@ -24,8 +24,9 @@ C = W.CutMap
 # subcircuit, cyclic three-subcircuit graph (an intermediate level), ragged
 # widths, three, four and five shared cuts (label blocks of 64, of 256 on the
 # dX side at four in FP32, of 256 at five), a chain of three with two cuts per
-# boundary, a larger two-cut pair, and a four-cut pair with several output
-# tiles and inner chunks per side
+# boundary, a larger two-cut pair, a four-cut pair with several output tiles
+# and inner chunks per side, and three-cut pairs whose dY side has four and
+# two output columns
 MIXED = [C(9, [4, 5], [0, 0], [1, 1], [5, 0, 3, 8, 1, 2, 4, 7, 6]),
          C(7, [3, 4], [], [], list(range(7))),
          C(6, [6], [], [], [3, 1, 0, 5, 2, 4]),
@@ -36,7 +37,9 @@ MIXED = [C(9, [4, 5], [0, 0], [1, 1], [5, 0, 3, 8, 1, 2, 4, 7, 6]),
          C(15, [5, 5, 5], [0, 0, 1, 1], [1, 1, 2, 2], list(range(15))),
          C(14, [7, 7], [0, 0], [1, 1], list(range(14))),
          C(12, [6, 6], [0] * 5, [1] * 5, list(range(12))),
-         C(17, [9, 8], [0] * 4, [1] * 4, list(range(17)))]
+         C(17, [9, 8], [0] * 4, [1] * 4, list(range(17))),
+         C(10, [2, 8], [0] * 3, [1] * 3, list(range(10))),
+         C(10, [1, 9], [0] * 3, [1] * 3, list(range(10)))]
 
 
 def _gpu():
