@@ -169,11 +169,20 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
 }
 
 // Largest d with prefix[d] <= item (the step a work-queue item belongs to).
+// The table is written before the launch and only read during it, and the
+// item is the same for the whole block: the search runs on scalar loads
+// through the constant address space, which wait on the scalar counter - not
+// behind this wave's outstanding vector loads and output stores, as a chain
+// of dependent vector loads would.
 __device__ __forceinline__ int find_desc(const int64_t *prefix, int n, int64_t item) {
-  int lo = 0, hi = n - 1;   // largest d with prefix[d] <= item
+  using cp = const __attribute__((address_space(4))) int64_t *;
+  const cp tab = (cp)(const __attribute__((address_space(1))) int64_t *)prefix;
+  const int64_t it = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(item >> 32)) << 32) |
+                               (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)item));
+  int lo = 0, hi = __builtin_amdgcn_readfirstlane(n - 1);   // largest d with prefix[d] <= it
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (prefix[mid] <= item) lo = mid;
+    if (tab[mid] <= it) lo = mid;
     else hi = mid - 1;
   }
   return lo;
