@@ -99,8 +99,11 @@ static Status build_batch(const cqc_instance *inst, int32_t n_inst, cqc_dtype in
       else
         tptr[t] = ws + L.t_off[t];
     }
-    // flag descriptors of this instance's entries
-    for (size_t t = 0; t < p.tensors.size(); ++t) {
+    // flag descriptors of this instance's entries, for instances whose
+    // one-instance call computes row flags (the others run without them, as
+    // that call does)
+    const bool inst_flags = needs_flags(L, false);
+    for (size_t t = 0; t < p.tensors.size() && inst_flags; ++t) {
       const auto &T = p.tensors[t];
       if (T.entry < 0) continue;
       FlagDesc d;
@@ -117,7 +120,6 @@ static Status build_batch(const cqc_instance *inst, int32_t n_inst, cqc_dtype in
       B.flag_blocks += T.rows() * flag_chunks(T.cols());
       B.flags.push_back(d);
     }
-    const bool inst_flags = needs_flags(L, false);
     for (size_t s = 0; s < p.steps.size(); ++s) {
       const Step &st = p.steps[s];
       const bool last = s + 1 == p.steps.size();
@@ -125,8 +127,10 @@ static Status build_batch(const cqc_instance *inst, int32_t n_inst, cqc_dtype in
       std::memset(&a, 0, sizeof(a));
       a.X = tptr[st.x];
       a.Y = tptr[st.y];
-      a.flagX = reinterpret_cast<const int32_t *>(ws + L.f_off[st.x]);
-      a.flagY = reinterpret_cast<const int32_t *>(ws + L.f_off[st.y]);
+      if (inst_flags) {
+        a.flagX = reinterpret_cast<const int32_t *>(ws + L.f_off[st.x]);
+        a.flagY = reinterpret_cast<const int32_t *>(ws + L.f_off[st.y]);
+      }
       a.nchX = p.tensors[st.x].entry >= 0 ? (int)flag_chunks(p.tensors[st.x].cols()) : 1;
       a.nchY = p.tensors[st.y].entry >= 0 ? (int)flag_chunks(p.tensors[st.y].cols()) : 1;
       a.logM = st.logM;

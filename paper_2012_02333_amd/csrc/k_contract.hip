@@ -732,13 +732,17 @@ __global__ __launch_bounds__(256) void k_row_flags_table(const FlagDesc *descs, 
                                                          unsigned long long *counters, int32_t n_counters) {
   const int64_t bid = blockIdx.x;
   if (bid == 0 && (int)threadIdx.x < n_counters) counters[threadIdx.x] = 0ull;
+  if (n == 0) return;   // a batch without row flags: the counters only
+  // the table is only read during the launch: scalar loads (see find_desc)
+  using cd = const __attribute__((address_space(4))) FlagDesc *;
+  const cd tab = (cd)(const __attribute__((address_space(1))) FlagDesc *)descs;
   int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (descs[mid].block_start <= bid) lo = mid;
+    if (tab[mid].block_start <= bid) lo = mid;
     else hi = mid - 1;
   }
-  flags_chunk(descs[lo], bid - descs[lo].block_start, is_double != 0);
+  flags_chunk(descs[lo], bid - tab[lo].block_start, is_double != 0);
 }
 
 // One block per instance: its FP64 mass from the per-tile partials, in order.
@@ -931,7 +935,9 @@ Status launch_mass_final(const double *partials, int64_t count, double *mass, hi
 
 Status launch_row_flags_table(const FlagDesc *descs, int32_t n, int64_t total_blocks, bool is_double,
                               unsigned long long *counters, int32_t n_counters, hipStream_t s) {
-  return launch("row_flags_table", k_row_flags_table, dim3((unsigned)total_blocks), dim3(256), 0, s, descs, n,
+  // at least one block: the pass also zeroes the queue counters
+  return launch("row_flags_table", k_row_flags_table, dim3((unsigned)std::max<int64_t>(1, total_blocks)), dim3(256),
+                0, s, descs, n,
                 (int32_t)is_double, counters, n_counters);
 }
 
