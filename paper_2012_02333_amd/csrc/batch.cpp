@@ -320,7 +320,10 @@ static Status batch_create(const cqc_instance *inst, int32_t n_inst, cqc_dtype i
     std::vector<int64_t> prefix(1, 0), bprefix(1, 0);
     for (auto &st : G.steps) {
       descs.push_back(st.second);
-      prefix.push_back(prefix.back() + (G.strip ? st.second.nblocks / kStripRows : st.second.nblocks));
+      const int64_t nb = st.second.nblocks;
+      prefix.push_back(prefix.back() + (G.strip   ? nb / kStripRows
+                                        : G.small ? (nb + kSmallTilesPerItem - 1) / kSmallTilesPerItem
+                                                  : nb));
       bprefix.push_back(bprefix.back() + st.second.nbatch);
     }
     put(B.desc_off[g], descs.data(), sizeof(ContractArgs) * descs.size());

@@ -668,8 +668,17 @@ __global__ __launch_bounds__(256) void k_contract_queue(const ContractArgs *desc
     const int64_t it = item;
     if (it >= total) return;
     const int d = find_desc(prefix, ndesc, it);
-    if (SMALL) contract_small_tile<T, O, BM, BN, WM, WN, MODE, XE>(descs[d], (uint32_t)(it - prefix[d]));
-    else contract_tile<T, O, BM, BN, WM, WN, MODE, XE>(descs[d], (uint32_t)(it - prefix[d]));
+    if (SMALL) {
+      // kSmallTilesPerItem consecutive tiles of one step per item
+      const ContractArgs &a = descs[d];
+      const int64_t t0 = (it - prefix[d]) * kSmallTilesPerItem;
+      for (int j = 0; j < kSmallTilesPerItem && t0 + j < a.nblocks; ++j) {
+        if (j) __syncthreads();
+        contract_small_tile<T, O, BM, BN, WM, WN, MODE, XE>(a, (uint32_t)(t0 + j));
+      }
+    } else {
+      contract_tile<T, O, BM, BN, WM, WN, MODE, XE>(descs[d], (uint32_t)(it - prefix[d]));
+    }
   }
 }
 
