@@ -74,4 +74,9 @@ Status launch(const char *name, Kernel k, dim3 grid, dim3 block, size_t shmem,
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Tiles per work-queue item of the batched small-term tile kernels (one
+// counter increment and descriptor lookup per item instead of per tile);
+// shared by the batch planner and the queue kernel.
+constexpr int kSmallTilesPerItem = 4;
+
 }  // namespace cqc

@@ -169,9 +169,6 @@ Status launch_contract_queue(Acc acc, int mode, int cfg, bool small, const Queue
 // or intermediate mode, no row flags): a step of nblocks tiles is nblocks /
 // kStripRows queue items.
 constexpr int kStripRows = 2;
-// Tiles per work-queue item of the batched small-term tile kernels (one
-// counter increment and descriptor lookup per item instead of per tile).
-constexpr int kSmallTilesPerItem = 4;
 Status launch_contract_strip_queue(int mode, const QueueLaunch &q, hipStream_t s);
 
 // Batched row flags (descriptor table in device memory, block_start = prefix)
