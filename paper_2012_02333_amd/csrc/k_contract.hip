@@ -50,9 +50,10 @@ __global__ __launch_bounds__(1024) void k_mass_final(const double *partials, int
                                                      double *mass, const int32_t *gate, int32_t gate_val) {
   if (gated_off(gate, gate_val)) return;
   // thread t adds partials t + 1024 (8 q + u) into accumulator u (eight loads
-  // in flight per thread), then the accumulators and the threads are combined
-  // in a fixed tree: the same order for every call of the same count
-  __shared__ double tsum[1024];
+  // in flight per thread), then the accumulators, the lanes of each wave (a
+  // fixed butterfly) and the sixteen waves are combined in fixed trees: the
+  // same order for every call of the same count, with one block barrier
+  __shared__ double wsum[16];
   double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int64_t i = threadIdx.x;
   for (; i + 7 * 1024 < count; i += 8 * 1024) {
@@ -60,13 +61,16 @@ __global__ __launch_bounds__(1024) void k_mass_final(const double *partials, int
     for (int u = 0; u < 8; ++u) v[u] += partials[i + u * 1024];
   }
   for (; i < count; i += 1024) v[0] += partials[i];
-  tsum[threadIdx.x] = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+  double t = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+  t = wave_sum_f64(t);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = t;
   __syncthreads();
-  for (int w = 512; w >= 1; w >>= 1) {
-    if ((int)threadIdx.x < w) tsum[threadIdx.x] += tsum[threadIdx.x + w];
-    __syncthreads();
+  if (threadIdx.x < 64) {
+    double w = threadIdx.x < 16 ? wsum[threadIdx.x] : 0.0;
+#pragma unroll
+    for (int o = 8; o >= 1; o >>= 1) w += __shfl_xor(w, o, 64);
+    if (threadIdx.x == 0) mass[0] = w;
   }
-  if (threadIdx.x == 0) mass[0] = tsum[0];
 }
 
 template <typename T, typename O, int BM, int BN, int WM, int WN, int MODE, int XE = 0>
