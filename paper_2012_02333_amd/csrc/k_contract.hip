@@ -49,19 +49,36 @@ __device__ __forceinline__ void xent4_at(const ContractArgs &a, int64_t o, const
 __global__ __launch_bounds__(1024) void k_mass_final(const double *partials, int64_t count,
                                                      double *mass, const int32_t *gate, int32_t gate_val) {
   if (gated_off(gate, gate_val)) return;
-  // thread t adds partials t + 1024 (8 q + u) into accumulator u (eight loads
-  // in flight per thread), then the accumulators, the lanes of each wave (a
-  // fixed butterfly) and the sixteen waves are combined in fixed trees: the
-  // same order for every call of the same count, with one block barrier
+  // thread t adds partials t + 1024 (16 q + u) into accumulator u (sixteen
+  // loads in flight per thread, missing ones read as zero), then the
+  // accumulators, the lanes of each wave (a fixed butterfly) and the sixteen
+  // waves are combined in fixed trees: the same order for every call of the
+  // same count, with one block barrier
+  constexpr int U = 16;
   __shared__ double wsum[16];
-  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int64_t i = threadIdx.x;
-  for (; i + 7 * 1024 < count; i += 8 * 1024) {
+  double v[U];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] += partials[i + u * 1024];
+  for (int u = 0; u < U; ++u) v[u] = 0.0;
+  int64_t i = threadIdx.x;
+  for (; i + (U - 1) * 1024 < count; i += U * 1024) {
+    double x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) x[u] = partials[i + u * 1024];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] += x[u];
   }
-  for (; i < count; i += 1024) v[0] += partials[i];
-  double t = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+  if (i < count) {
+    double x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) x[u] = i + u * 1024 < count ? partials[i + u * 1024] : 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] += x[u];
+  }
+#pragma unroll
+  for (int w = U / 2; w >= 1; w >>= 1)
+#pragma unroll
+    for (int u = 0; u < w; ++u) v[u] += v[u + w];
+  double t = v[0];
   t = wave_sum_f64(t);
   if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = t;
   __syncthreads();
