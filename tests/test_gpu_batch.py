@@ -108,6 +108,43 @@ def test_batch_graph_replay():
         assert torch.equal(batch.mass, eager_mass), rep
 
 
+def test_batch_without_row_flags_runs_repeatedly():
+    """A batch in which no instance's plan uses row flags (at most two cuts
+    per contraction): the flag pass has no entry tensors and only zeroes the
+    work-queue counters, so every run must redo all the work.  Three runs,
+    the entries scaled by 2 in place before each later one: every output and
+    mass bit for bit twice the previous (outputs scale exactly by 2), and the
+    first run equals the one-instance calls."""
+    _gpu()
+    C = W.CutMap
+    cuts_w = [C(18, [9, 9], [0, 0], [1, 1], list(range(18))),
+              C(14, [7, 7], [0], [1], list(range(14))),
+              C(15, [5, 5, 5], [0, 1], [1, 2], list(range(15)))]
+    ents = [[torch.from_numpy(E.astype(np.float32)).cuda() for E in W.random_entries(c, seed=750 + i)]
+            for i, c in enumerate(cuts_w)]
+    cuts = [cqc.CutMap.from_workload(c) for c in cuts_w]
+    batch = cqc.Batch(ents, cuts, precision="fp32")
+    batch.run()
+    torch.cuda.synchronize()
+    for k in range(len(cuts)):
+        p1, _ = cqc.reconstruct_fd(ents[k], cuts[k], precision="fp32")
+        assert torch.equal(batch.outs[k], p1), k
+    prev = [o.clone() for o in batch.outs]
+    prev_m = batch.mass.clone()
+    for rep in range(2):
+        for e in ents:
+            e[0].mul_(2.0)
+        for o in batch.outs:
+            o.fill_(-1.0)
+        batch.run()
+        torch.cuda.synchronize()
+        for k in range(len(cuts)):
+            assert torch.equal(batch.outs[k], 2.0 * prev[k]), (rep, k)
+        assert torch.equal(batch.mass, 2.0 * prev_m), rep
+        prev = [o.clone() for o in batch.outs]
+        prev_m = batch.mass.clone()
+
+
 def test_batch_strips_equal_single_calls():
     """Instances whose small-term steps run as two-tile strips in the batch
     (FP32, no row flags: two subcircuits with two cuts, a chain with two cuts
