@@ -589,18 +589,31 @@ void k_bwd_queue(const BwdArgs *descs, const int64_t *prefix, int ndesc, unsigne
 //     32 w .. 32 w + 31 of the tile and accumulates over the whole chunk;
 //   dY[rowY(s,rY)][n] (+)= sum_m X[rowX(s,rX)][m] dZ_b[m][n]: wave w owns
 //     columns 16 w .. 16 w + 15 of each sub-tile and sums over the tile's rows.
-// Label s is MFMA row l % 16 (labels >= 4^nS are zero rows); lane l feeds the
-// inner indices 4 (l / 16) + t of a 16-index group to MFMA t.  The label
-// operands of the next sub-tile are loaded with its dL/dZ, so no wait inside
-// the matrix-core loop covers the staging loads.  Partials (fixed order, added
-// by the reduce pass): X side part[(rY kChunks + column chunk)][row][m], Y side
+// Two product forms:
+//   16 labels (two shared cuts): 16 x 16 x 4 products, label s is MFMA row
+//     l % 16; lane l feeds the inner indices 4 (l / 16) + t of a 16-index
+//     group to MFMA t;
+//   at most 4 labels (one shared cut or none, ONE): the 16-block 4 x 4 x 1
+//     product, in which lane 4 q + i feeds element i of block q's A column and
+//     B row, and lane 4 q + j, register r receives block q's C[r][j].  For dX,
+//     block q takes column 16 c + q of the sub-tile, rows 4 g + i and label j;
+//     for dY, block q = 4 h + c takes row 4 k + h, label i and column 4 c + j
+//     of the wave's 16.  The blocks' sums are added across lanes (over q for
+//     dX at the end of the chunk, over h for dY per sub-tile), so all of the
+//     products' work is useful instead of a quarter of it.
+// Labels >= 4^nS are zero rows or never-stored outputs.  The label operands of
+// the next sub-tile are loaded with its dL/dZ, so no wait inside the
+// matrix-core loop covers the staging loads.  Partials (fixed order, added by
+// the reduce pass): X side part[(rY kChunks + column chunk)][row][m], Y side
 // part2[(rX kChunks2 + row tile)][row][n].
-__device__ __forceinline__ void bwd_dual_block(const BwdArgs &a, int64_t blk) {
-  constexpr int TR = kDualRows, TC = kDualCols, LD = TC + 4;
+constexpr int kDualLd = kDualCols + 4;
+template <bool ONE>
+__device__ __forceinline__ void bwd_dual_block(const BwdArgs &a, int64_t blk, float (*gs)[kDualRows][kDualLd]) {
+  constexpr int TR = kDualRows, TC = kDualCols;
   using V = f32x4;
-  __shared__ float gs[2][TR][LD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, lg = lane >> 4;
+  const int q4 = lane >> 2, i4 = lane & 3;   // 4 x 4 x 1 block and element
   const int64_t M = int64_t(1) << a.logM, N = int64_t(1) << a.logN;
   const int RYn = 1 << (2 * a.nRY), SN = 1 << (2 * a.nS);
   int64_t b = blk;
@@ -613,35 +626,50 @@ __device__ __forceinline__ void bwd_dual_block(const BwdArgs &a, int64_t blk) {
   const float *X = static_cast<const float *>(a.X);
   const float *Y = static_cast<const float *>(a.Y);
   const float *dZ = static_cast<const float *>(a.dZ) + ((int64_t)rX * RYn + rY) * M * N;
-  // Every load below is an unconditional 16-byte global load: the column
-  // sub-tiles are always whole (N >= 64, both powers of two), and a row past M
-  // (tiles of M = 64) or a label past 4^nS reads a clamped in-range address.
-  // Rows past M are zeroed when staged (they are summed over for dY); a label
-  // past 4^nS only feeds MFMA output rows that are never stored.  Nothing
-  // consumes a loaded value before the staging point, so no wait sits between
-  // the loads and the matrix-core work they overlap.
+  // Every load below is an unconditional global load: the column sub-tiles
+  // are always whole (N >= 64, both powers of two), and a row past M (tiles of
+  // M = 64) or a label past 4^nS reads a clamped in-range address.  Rows past
+  // M are zeroed when staged (they are summed over for dY); a label past 4^nS
+  // only feeds MFMA outputs that are never stored.  Nothing consumes a loaded
+  // value before the staging point, so no wait sits between the loads and the
+  // matrix-core work they overlap.
   auto ld = [](const float *p) {
     const f32x4 v = *(const __attribute__((address_space(1))) f32x4 *)p;
     return make_float4(v[0], v[1], v[2], v[3]);
   };
+  auto ld1 = [](const float *p) { return *(const __attribute__((address_space(1))) float *)p; };
   auto sel = [](bool ok, float4 v) {
     return make_float4(ok ? v.x : 0.f, ok ? v.y : 0.f, ok ? v.z : 0.f, ok ? v.w : 0.f);
   };
-  // this lane's label row as an MFMA operand row (label l % 16)
-  const bool sok = l16 < SN;
-  const float *xl = X + (int64_t)(sok ? row_of(a.mx, l16, rX) : 0) * M;
-  const float *yl = Y + (int64_t)(sok ? row_of(a.my, l16, rY) : 0) * N;
+  // this lane's label as an MFMA operand row: l % 16 (16-label form), i4 (ONE)
+  const int lab = ONE ? i4 : l16;
+  const bool sok = lab < SN;
+  const float *xl = X + (int64_t)(sok ? row_of(a.mx, lab, rX) : 0) * M;
+  const float *yl = Y + (int64_t)(sok ? row_of(a.my, lab, rY) : 0) * N;
   // X operands of the tile's rows, once per block: rows m0 + 16 kr + 4 lg + t
-  float xa[TR / 16][4];
+  // (16-label form) or m0 + 4 k + lg (ONE: the dY block's row phase h = lg)
+  float xa[TR / 4];
+  if constexpr (ONE) {
 #pragma unroll
-  for (int kr = 0; kr < TR / 16; ++kr) {
-    const int64_t m = m0 + 16 * kr + 4 * lg;
-    const float4 v = sel(m < M, ld(xl + (m < M ? m : 0)));
-    xa[kr][0] = v.x, xa[kr][1] = v.y, xa[kr][2] = v.z, xa[kr][3] = v.w;
+    for (int k = 0; k < TR / 4; ++k) {
+      const int64_t m = m0 + 4 * k + lg;
+      const float v = ld1(xl + (m < M ? m : 0));
+      xa[k] = m < M ? v : 0.f;
+    }
+  } else {
+#pragma unroll
+    for (int kr = 0; kr < TR / 16; ++kr) {
+      const int64_t m = m0 + 16 * kr + 4 * lg;
+      const float4 v = sel(m < M, ld(xl + (m < M ? m : 0)));
+      xa[4 * kr] = v.x, xa[4 * kr + 1] = v.y, xa[4 * kr + 2] = v.z, xa[4 * kr + 3] = v.w;
+    }
   }
-  // staging: thread t loads rows t / 16 + 16 j, columns 4 (t % 16) + 0..3
+  // staging: thread t loads rows t / 16 + 16 j, columns 4 (t % 16) + 0..3;
+  // label operands of a sub-tile: columns 16 kq + 4 lg + 0..3 (16-label form)
+  // or column 16 kq + q4 (ONE)
   float4 gr[TR / 16];
   float4 yn[TC / 16];
+  float yn1[TC / 16];
   auto load_sub = [&](int64_t c0) {
 #pragma unroll
     for (int j = 0; j < TR / 16; ++j) {
@@ -649,7 +677,10 @@ __device__ __forceinline__ void bwd_dual_block(const BwdArgs &a, int64_t blk) {
       gr[j] = ld(dZ + (m < M ? m : 0) * N + c0 + 4 * (tid & 15));
     }
 #pragma unroll
-    for (int kq = 0; kq < TC / 16; ++kq) yn[kq] = ld(yl + c0 + 16 * kq + 4 * lg);
+    for (int kq = 0; kq < TC / 16; ++kq) {
+      if constexpr (ONE) yn1[kq] = ld1(yl + c0 + 16 * kq + q4);
+      else yn[kq] = ld(yl + c0 + 16 * kq + 4 * lg);
+    }
   };
   auto store_sub = [&](int buf) {
 #pragma unroll
@@ -657,21 +688,32 @@ __device__ __forceinline__ void bwd_dual_block(const BwdArgs &a, int64_t blk) {
       *reinterpret_cast<float4 *>(&gs[buf][(tid >> 4) + 16 * j][4 * (tid & 15)]) =
           sel(m0 + (tid >> 4) + 16 * j < M, gr[j]);
   };
-  V ax[2] = {V{0, 0, 0, 0}, V{0, 0, 0, 0}};
+  V ax[ONE ? 8 : 2];
+#pragma unroll
+  for (int r = 0; r < (ONE ? 8 : 2); ++r) ax[r] = V{0, 0, 0, 0};
   float4 yc[TC / 16];
+  float yc1[TC / 16];
+  auto next_y = [&]() {
+#pragma unroll
+    for (int kq = 0; kq < TC / 16; ++kq) {
+      if constexpr (ONE) yc1[kq] = yn1[kq];
+      else yc[kq] = yn[kq];
+    }
+  };
   const int nsub = (int)((n1 - n0) / TC);
   load_sub(n0);
   store_sub(0);
-#pragma unroll
-  for (int kq = 0; kq < TC / 16; ++kq) yc[kq] = yn[kq];
+  next_y();
   __syncthreads();
   __attribute__((address_space(1))) float *part2 =
       (__attribute__((address_space(1))) float *)static_cast<float *>(a.part2) +
       ((int64_t)rX * a.kChunks2 + mt) * a.rowsY * N;
+  // dY output rows: labels 4 lg + r (16-label form, register r) or lg (ONE:
+  // after the sum over row phases each lane stores the label of its phase)
   int yrow[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int sr = 4 * lg + r;
+    const int sr = ONE ? lg : 4 * lg + r;
     yrow[r] = sr < SN ? row_of(a.my, sr, rY) : -1;
   }
   for (int i = 0; i < nsub; ++i) {
@@ -679,54 +721,103 @@ __device__ __forceinline__ void bwd_dual_block(const BwdArgs &a, int64_t blk) {
     const int64_t c0 = n0 + (int64_t)i * TC;
     const bool more = i + 1 < nsub;
     if (more) load_sub(c0 + TC);
-    // dX: rows 32 w + 16 mb + l16 against the sub-tile's 64 columns
+    if constexpr (ONE) {
+      // dX: rows 32 w + 4 g + i4 at column 16 kq + q4, against label i4
 #pragma unroll
-    for (int kq = 0; kq < TC / 16; ++kq)
+      for (int kq = 0; kq < TC / 16; ++kq)
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb) {
-        const float4 g = *reinterpret_cast<const float4 *>(&gs[cur][32 * wave + 16 * mb + l16][16 * kq + 4 * lg]);
-        const float gv[4] = {g.x, g.y, g.z, g.w};
-        const float yv[4] = {yc[kq].x, yc[kq].y, yc[kq].z, yc[kq].w};
+        for (int g = 0; g < 8; ++g)
+          ax[g] = __builtin_amdgcn_mfma_f32_4x4x1f32(gs[cur][32 * wave + 4 * g + i4][16 * kq + q4], yc1[kq],
+                                                     ax[g], 0, 0, 0);
+      // dY: rows 4 k + lg (row phase h = lg), columns 16 w + 4 c + i4 (c = q4 % 4)
+      V ay[4] = {V{0, 0, 0, 0}, V{0, 0, 0, 0}, V{0, 0, 0, 0}, V{0, 0, 0, 0}};
 #pragma unroll
-        for (int t = 0; t < 4; ++t) ax[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(yv[t], gv[t], ax[mb], 0, 0, 0);
+      for (int k = 0; k < TR / 4; ++k)
+        ay[k & 3] = __builtin_amdgcn_mfma_f32_4x4x1f32(xa[k], gs[cur][4 * k + lg][16 * wave + l16], ay[k & 3], 0, 0,
+                                                       0);
+      float v[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        v[r] = (ay[0][r] + ay[1][r]) + (ay[2][r] + ay[3][r]);
+        v[r] += __shfl_xor(v[r], 16, 64);
+        v[r] += __shfl_xor(v[r], 32, 64);
       }
-    // dY: columns 16 w + l16 over the tile's rows
-    V ay = V{0, 0, 0, 0};
+      // lane (h, c, j) stores label h of column 16 w + 4 c + j
+      const float out = lg == 0 ? v[0] : lg == 1 ? v[1] : lg == 2 ? v[2] : v[3];
+      if (yrow[0] >= 0) part2[(int64_t)yrow[0] * N + c0 + 16 * wave + l16] = out;
+    } else {
+      // dX: rows 32 w + 16 mb + l16 against the sub-tile's 64 columns
 #pragma unroll
-    for (int kr = 0; kr < TR / 16; ++kr)
+      for (int kq = 0; kq < TC / 16; ++kq)
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-        ay = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[kr][t], gs[cur][16 * kr + 4 * lg + t][16 * wave + l16], ay, 0, 0, 0);
-    const int64_t n = c0 + 16 * wave + l16;
+        for (int mb = 0; mb < 2; ++mb) {
+          const float4 g = *reinterpret_cast<const float4 *>(&gs[cur][32 * wave + 16 * mb + l16][16 * kq + 4 * lg]);
+          const float gv[4] = {g.x, g.y, g.z, g.w};
+          const float yv[4] = {yc[kq].x, yc[kq].y, yc[kq].z, yc[kq].w};
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      if (yrow[r] >= 0) part2[(int64_t)yrow[r] * N + n] = ay[r];
+          for (int t = 0; t < 4; ++t) ax[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(yv[t], gv[t], ax[mb], 0, 0, 0);
+        }
+      // dY: columns 16 w + l16 over the tile's rows
+      V ay = V{0, 0, 0, 0};
+#pragma unroll
+      for (int kr = 0; kr < TR / 16; ++kr)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          ay = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[4 * kr + t], gs[cur][16 * kr + 4 * lg + t][16 * wave + l16], ay,
+                                                    0, 0, 0);
+      const int64_t n = c0 + 16 * wave + l16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (yrow[r] >= 0) part2[(int64_t)yrow[r] * N + n] = ay[r];
+    }
     if (more) {
       store_sub(cur ^ 1);
-#pragma unroll
-      for (int kq = 0; kq < TC / 16; ++kq) yc[kq] = yn[kq];
+      next_y();
     }
     __syncthreads();
   }
   __attribute__((address_space(1))) float *part =
       (__attribute__((address_space(1))) float *)static_cast<float *>(a.part) +
       ((int64_t)rY * a.kChunks + kc) * a.rowsX * M;
+  if constexpr (ONE) {
+    // sum the 16 column phases (blocks q4); lane (q4 < 8, j) then stores rows
+    // 32 w + 4 q4 .. + 3 of label j as one 16-byte store
+    float4 o = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int sr = 4 * lg + r;
-    if (sr >= SN) continue;
-    const int64_t row = row_of(a.mx, sr, rX);
+    for (int g = 0; g < 8; ++g) {
+      float v[4];
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb) {
-      const int64_t m = m0 + 32 * wave + 16 * mb + l16;
-      if (m < M) part[row * M + m] = ax[mb][r];
+      for (int r = 0; r < 4; ++r) {
+        v[r] = ax[g][r];
+#pragma unroll
+        for (int s = 4; s <= 32; s <<= 1) v[r] += __shfl_xor(v[r], s, 64);
+      }
+      if (q4 == g) o = make_float4(v[0], v[1], v[2], v[3]);
+    }
+    const int64_t m = m0 + 32 * wave + 4 * q4;
+    if (q4 < 8 && sok && m < M) {
+      const int64_t row = row_of(a.mx, i4, rX);
+      *reinterpret_cast<__attribute__((address_space(1))) f32x4 *>(part + row * M + m) = f32x4{o.x, o.y, o.z, o.w};
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int sr = 4 * lg + r;
+      if (sr >= SN) continue;
+      const int64_t row = row_of(a.mx, sr, rX);
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb) {
+        const int64_t m = m0 + 32 * wave + 16 * mb + l16;
+        if (m < M) part[row * M + m] = ax[mb][r];
+      }
     }
   }
 }
 
-__global__ __launch_bounds__(256) void k_bwd_dual_queue(const BwdArgs *descs, const int64_t *prefix, int ndesc,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_bwd_dual_queue(const BwdArgs *descs, const int64_t *prefix, int ndesc,
                                                         unsigned long long *queue, int64_t total) {
   __shared__ int64_t item;
+  __shared__ float gs[2][kDualRows][kDualLd];
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0) item = (int64_t)atomicAdd(queue, 1ull);
@@ -734,7 +825,9 @@ __global__ __launch_bounds__(256) void k_bwd_dual_queue(const BwdArgs *descs, co
     const int64_t it = item;
     if (it >= total) return;
     const int d = find_desc(prefix, ndesc, it);
-    bwd_dual_block(descs[d], it - prefix[d]);
+    const BwdArgs &a = descs[d];
+    if (a.nS <= 1) bwd_dual_block<true>(a, it - prefix[d], gs);
+    else bwd_dual_block<false>(a, it - prefix[d], gs);
   }
 }
 
