@@ -396,7 +396,11 @@ int cqc_dd_query_destroy(cqc_dd_query q);
  * as E_c):
  *     dL/dE_c[r, y] = 2^-K sum_{l: row_c(l)=r} sum_{x: x_c=y} G[x] prod_{c'!=c} E_c'[row_c'(l), x_c']
  * Every output element is written (not accumulated).  Reductions run in a
- * fixed order, so results are bitwise reproducible. */
+ * fixed order, so results are bitwise reproducible.  F32 arithmetic: FP32
+ * accumulation throughout; the products of steps with three or four shared
+ * cuts (inner extent of at least 16) run as the six-product BF16X6 split
+ * (above), whose products keep FP32 accuracy (dropped terms below 2^-24 of
+ * |a b|). */
 int cqc_backward_workspace_size(const cqc_instance *inst, int32_t n_inst, cqc_dtype in_t,
                                 cqc_precision prec, size_t *bytes);
 int cqc_reconstruct_backward(const cqc_instance *inst, int32_t n_inst, cqc_dtype in_t,

@@ -10,7 +10,9 @@
 // applies the scale.  Matrix-core row i <-> label s, column j <-> the output
 // column, k <-> the inner index; each lane takes 4 consecutive inner indices
 // with one 16-byte load and feeds them to 4 MFMAs (inner index 4*(lane/16)+t
-// in MFMA t, the same for both operands).
+// in MFMA t, the same for both operands).  FP32 tiles of 64 labels run their
+// products split into bfloat16 parts on the BF16 matrix cores (six products,
+// FP32 accumulation, FP32-level accuracy); see bwd_block_staged.
 #include <algorithm>
 
 #include "bwd.hpp"
@@ -253,6 +255,25 @@ __device__ __forceinline__ void bwd_y_block(const BwdArgs &a, int64_t blk) {
 // loads from clamped addresses, and nothing consumes a loaded value before
 // its use (a select right after a load would wait for it there).
 constexpr int kStagedLd = 36;
+// Split form of the 64-label FP32 tiles (FAST, SB = 4): the label slices are
+// staged as three bfloat16 part planes [2][3][64][kSplitLd] (pitch 48: the
+// 16-byte operand reads of 16 rows x 2 lane groups fall on distinct 16-byte
+// slots modulo 512 bytes).
+constexpr int kSplitLd = 48;
+template <int SB> struct StagedLds {
+  static constexpr int kF32 = 2 * 16 * SB * kStagedLd;
+  static constexpr int kSplit = SB == 4 ? 2 * 3 * 64 * kSplitLd / 2 : 0;
+  static constexpr int kFloats = kF32 > kSplit ? kF32 : kSplit;
+};
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+// a = h + m + l, each part the round-to-nearest bfloat16 of what is left (the
+// remainders are exact in FP32, so the parts carry 24 significand bits)
+__device__ __forceinline__ void split_bf16(float a, __bf16 &h, __bf16 &m, __bf16 &l) {
+  h = (__bf16)a;
+  const float r1 = a - (float)h;
+  m = (__bf16)r1;
+  l = (__bf16)(r1 - (float)m);
+}
 template <bool YS, bool FAST, int SB = 4, int OB = 4>
 __device__ __forceinline__ void bwd_block_staged(const BwdArgs &a, int64_t blk, float (*ls)[16 * SB][kStagedLd]) {
   // Pitch 36 floats.  The 16-byte fragment reads conflict on LDS banks at this
@@ -262,6 +283,18 @@ __device__ __forceinline__ void bwd_block_staged(const BwdArgs &a, int64_t blk, 
   constexpr int KS = 32;
   static_assert(kStagedLd == KS + 4, "staging pitch");
   constexpr int RPT = SB / 4;   // label rows staged per thread
+  // Split form: every label and dL/dZ value a = a0 + a1 + a2 in bfloat16
+  // parts, and the six products a_i b_j with i + j <= 2 accumulated in FP32 on
+  // v_mfma_f32_16x16x32_bf16, smallest first (the dropped products and the
+  // split's remainder are below 2^-24 of |a b|: FP32-level products at the
+  // bfloat16 matrix-core rate).  A lane feeds the inner indices 8 (l / 16)
+  // .. + 7 of a 32-index step; both operands use that order.
+  constexpr bool SPL = FAST && SB == 4 && OB == 4;
+  // dX side (dL/dZ rows along the inner index): a lane's eight inner indices
+  // are 4 (l / 16) + t and 16 + 4 (l / 16) + t, so that each load instruction
+  // reads 64 contiguous bytes per row; the label parts are staged in the same
+  // order (slot 8 (l / 16) + e holds that lane's e-th index)
+  constexpr bool PERM = SPL && !YS;
   using Op = BOp<float>;
   using V = typename Op::V;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -323,6 +356,37 @@ __device__ __forceinline__ void bwd_block_staged(const BwdArgs &a, int64_t blk, 
     }
   };
   auto sstore = [&](int buf) {
+    if constexpr (SPL) {
+      // three part planes; values past the chunk end are zero
+      __bf16 *lb = reinterpret_cast<__bf16 *>(ls);
+      bf16x8 ph, pm, pl;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float x = gok[e >> 2] ? g[0][e] : 0.f;
+        __bf16 h, m, l;
+        split_bf16(x, h, m, l);
+        ph[e] = h, pm[e] = m, pl[e] = l;
+      }
+      __bf16 *d = lb + ((buf * 3) * 64 + sr) * kSplitLd;
+      if constexpr (PERM) {
+        // inner index i sits at slot 8 ((i % 16) / 4) + 4 (i / 16) + i % 4
+        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+        const int sa = 8 * ((8 * sq & 15) >> 2) + 4 * (8 * sq >> 4);
+        const int sbb = 8 * (((8 * sq + 4) & 15) >> 2) + 4 * ((8 * sq + 4) >> 4);
+        const bf16x8 *pp[3] = {&ph, &pm, &pl};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const bf16x8 v = *pp[q];
+          *reinterpret_cast<bf16x4 *>(d + q * 64 * kSplitLd + sa) = bf16x4{v[0], v[1], v[2], v[3]};
+          *reinterpret_cast<bf16x4 *>(d + q * 64 * kSplitLd + sbb) = bf16x4{v[4], v[5], v[6], v[7]};
+        }
+      } else {
+        *reinterpret_cast<bf16x8 *>(d + 8 * sq) = ph;
+        *reinterpret_cast<bf16x8 *>(d + 8 * sq + 64 * kSplitLd) = pm;
+        *reinterpret_cast<bf16x8 *>(d + 8 * sq + 2 * 64 * kSplitLd) = pl;
+      }
+      return;
+    }
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
       float *d = &ls[buf][sr + 64 * r][8 * sq];
@@ -404,6 +468,76 @@ __device__ __forceinline__ void bwd_block_staged(const BwdArgs &a, int64_t blk, 
         for (int ob = 0; ob < OB; ++ob) acc[sb][ob] = Op::run(av[t], bv[h][ob][t], acc[sb][ob]);
     }
   };
+  // split form: dL/dZ operands of the step at s0 (inner indices s0 + 8 lg +
+  // 4 hh + t, or s0 + 16 hh + 4 lg + t on the dX side); with only 16 indices
+  // left (full false) the loads past them read first-half addresses, and their
+  // values are zeroed before use
+  auto spl_load = [&](float (&dst)[2][OB][4], int64_t s0, bool full) {
+    const int64_t c = s0 + (PERM ? 4 * lg : 8 * lg - (full || lg < 2 ? 0 : 16));
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+      const int64_t cc = PERM ? c + (full ? 16 * hh : 0) : c + 4 * hh;
+      if constexpr (kVecY) {
+        if (vecy) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const f32x4 q = *(const __attribute__((address_space(1))) f32x4 *)(dZ + (cc + t) * N + oc4);
+#pragma unroll
+            for (int ob = 0; ob < OB; ++ob) dst[hh][ob][t] = q[ob];
+          }
+          continue;
+        }
+      }
+#pragma unroll
+      for (int ob = 0; ob < OB; ++ob) {
+        const int64_t o = ow + ob * 16 + l16;
+        const int64_t oc = o < OUT ? o : 0;
+        if (!YS) {
+          const f32x4 q = *(const __attribute__((address_space(1))) f32x4 *)(dZ + oc * N + cc);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) dst[hh][ob][t] = q[t];
+        } else {
+          const __attribute__((address_space(1))) float *q =
+              (const __attribute__((address_space(1))) float *)dZ + cc * N + oc;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) dst[hh][ob][t] = q[t * N];
+        }
+      }
+    }
+  };
+  // the parts of a step's dL/dZ operands, split once when they arrive (the
+  // lanes past a 16-index last step get zeros)
+  bf16x8 dp[SPL ? OB : 1][3];
+  auto spl_split = [&](const float (&src)[2][OB][4], bool full) {
+    const bool hv = full || lg < 2;
+#pragma unroll
+    for (int ob = 0; ob < (SPL ? OB : 0); ++ob)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const bool ok = PERM ? full || e < 4 : hv;
+        const float x = ok ? src[e >> 2][ob][e & 3] : 0.f;
+        __bf16 h, m, l;
+        split_bf16(x, h, m, l);
+        dp[ob][0][e] = h, dp[ob][1][e] = m, dp[ob][2][e] = l;
+      }
+  };
+  auto spl_step = [&](int cur) {
+    const __bf16 *lb = reinterpret_cast<const __bf16 *>(ls) + (cur * 3) * 64 * kSplitLd;
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) {
+      bf16x8 lp[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        lp[q] = *reinterpret_cast<const bf16x8 *>(lb + (q * 64 + sb * 16 + l16) * kSplitLd + 8 * lg);
+      // (label part, dL/dZ part), smallest first
+      constexpr int kPi[6] = {0, 2, 1, 0, 1, 0}, kPj[6] = {2, 0, 1, 1, 0, 0};
+#pragma unroll
+      for (int u = 0; u < 6; ++u)
+#pragma unroll
+        for (int ob = 0; ob < (SPL ? OB : 0); ++ob)
+          acc[sb][ob] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lp[kPi[u]], dp[ob][kPj[u]], acc[sb][ob], 0, 0, 0);
+    }
+  };
   if constexpr (FAST) {
     // every operand of step n0 + KS (label slice and both dL/dZ halves) is
     // loaded at the top of step n0 into a second register set; step n0 reads
@@ -413,8 +547,13 @@ __device__ __forceinline__ void bwd_block_staged(const BwdArgs &a, int64_t blk, 
     if (k0 < k1) {
       gload(k0);
       sstore(0);
-      bload(0, k0);
-      if (k0 + 16 < k1) bload(1, k0 + 16);
+      if constexpr (SPL) {
+        spl_load(bn, k0, k0 + 16 < k1);
+        spl_split(bn, k0 + 16 < k1);
+      } else {
+        bload(0, k0);
+        if (k0 + 16 < k1) bload(1, k0 + 16);
+      }
     }
     __syncthreads();
     int cur = 0;
@@ -422,7 +561,10 @@ __device__ __forceinline__ void bwd_block_staged(const BwdArgs &a, int64_t blk, 
       const bool more = n0 + KS < k1;
       const bool h1 = n0 + 16 < k1;
       const bool h1n = n0 + KS + 16 < k1;
-      if (more) {
+      if (SPL && more) {
+        gload(n0 + KS);
+        spl_load(bn, n0 + KS, h1n);
+      } else if (more) {
         gload(n0 + KS);
         const int64_t c = n0 + KS + 4 * lg;
 #pragma unroll
@@ -462,8 +604,19 @@ __device__ __forceinline__ void bwd_block_staged(const BwdArgs &a, int64_t blk, 
       // keep the loads above the matrix-core work (the scheduler would sink
       // them next to their use to save registers, and the work would wait)
       __builtin_amdgcn_sched_barrier(0);
-      half(cur, 0);
-      if (h1) half(cur, 1);
+      if constexpr (SPL) {
+        spl_step(cur);
+        if (more) {
+          sstore(cur ^ 1);
+          spl_split(bn, h1n);
+        }
+        __syncthreads();
+        cur ^= 1;
+        continue;
+      } else {
+        half(cur, 0);
+        if (h1) half(cur, 1);
+      }
       if (more) {
         sstore(cur ^ 1);
 #pragma unroll
@@ -532,7 +685,8 @@ template <typename T, int SB, int MB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BwdCfg<T, SB>::kWaves, 8)))
 void k_bwd_x(const BwdArgs a) {
   if constexpr (sizeof(T) == 4 && ((SB == 4 && MB == 4) || (SB == 16 && MB == 1))) {
-    __shared__ float ls[2][16 * SB][kStagedLd];
+    __shared__ __attribute__((aligned(16))) float lsraw[StagedLds<SB>::kFloats];
+    auto ls = reinterpret_cast<float (*)[16 * SB][kStagedLd]>(lsraw);
     if (a.logN >= 4) bwd_block_staged<false, true, SB, MB>(a, blockIdx.x, ls);
     else bwd_block_staged<false, false, SB, MB>(a, blockIdx.x, ls);
   } else {
@@ -544,7 +698,8 @@ template <typename T, int SB, int NB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BwdCfg<T, SB>::kWaves, 8)))
 void k_bwd_y(const BwdArgs a) {
   if constexpr (sizeof(T) == 4 && ((SB == 4 && NB == 4) || (SB == 16 && NB == 1))) {
-    __shared__ float ls[2][16 * SB][kStagedLd];
+    __shared__ __attribute__((aligned(16))) float lsraw[StagedLds<SB>::kFloats];
+    auto ls = reinterpret_cast<float (*)[16 * SB][kStagedLd]>(lsraw);
     if (a.logM >= 4) bwd_block_staged<true, true, SB, NB>(a, blockIdx.x, ls);
     else bwd_block_staged<true, false, SB, NB>(a, blockIdx.x, ls);
   } else {
@@ -568,7 +723,8 @@ void k_bwd_queue(const BwdArgs *descs, const int64_t *prefix, int ndesc, unsigne
     if (it >= total) return;
     const int d = find_desc(prefix, ndesc, it);
     if constexpr (sizeof(T) == 4 && ((SB == 4 && MB == 4) || (SB == 16 && MB == 1))) {
-      __shared__ float ls[2][16 * SB][kStagedLd];
+      __shared__ __attribute__((aligned(16))) float lsraw[StagedLds<SB>::kFloats];
+      auto ls = reinterpret_cast<float (*)[16 * SB][kStagedLd]>(lsraw);
       const BwdArgs &a = descs[d];
       if ((Y ? a.logM : a.logN) >= 4) bwd_block_staged<Y, true, SB, MB>(a, it - prefix[d], ls);
       else bwd_block_staged<Y, false, SB, MB>(a, it - prefix[d], ls);
@@ -976,19 +1132,18 @@ __global__ __launch_bounds__(256) void k_bwd_prep(const BwdGatherDesc *descs, co
   }
 }
 
-// Label blocks of 16 per block tile.  Three shared cuts take 64 labels per
-// tile.  Four take 64 on the dY side and, in FP32, 256 on the dX side: there
-// the 256 label rows of a 32-index slice are staged in LDS once per block (as
-// the 64 are), dL/dZ is read once instead of four times, and the dX launch
-// measured 9% faster; the dY side, whose dL/dZ loads are strided columns,
-// measured 5% slower with 256 and keeps 64.  (An earlier 256-label form in
-// which every wave loaded the same 256 operand rows itself was 1.5x slower
-// than 64.)  Five and more cuts take 256 (dL/dZ would otherwise be read 16
-// times).
+// Label blocks of 16 per block tile.  Three and four shared cuts take 64
+// labels per tile: in FP32 those tiles run the split products, which made
+// them faster on the dX side at four cuts than 256-label FP32 tiles (C5 dX
+// launches 0.79 -> 0.70 ms), although they read dL/dZ four times instead of
+// once.  Five and more cuts take 256 (dL/dZ would otherwise be read 16 times;
+// the 256 label rows of a 32-index slice are staged in LDS once per block).
+// (An earlier 256-label form in which every wave loaded the same 256 operand
+// rows itself was 1.5x slower than 64.)
 static int sb_for(int nS, bool y, bool f32) {
+  (void)y, (void)f32;
   if (nS <= 2) return 1;
-  if (nS == 3) return 4;
-  if (nS == 4) return f32 && !y ? 16 : 4;
+  if (nS <= 4) return 4;
   return 16;
 }
 
