@@ -262,7 +262,7 @@ constexpr int kStagedLd = 36;
 constexpr int kSplitLd = 48;
 template <int SB> struct StagedLds {
   static constexpr int kF32 = 2 * 16 * SB * kStagedLd;
-  static constexpr int kSplit = SB == 4 ? 2 * 3 * 64 * kSplitLd / 2 : 0;
+  static constexpr int kSplit = SB == 4 || SB == 8 ? 2 * 3 * 16 * SB * kSplitLd / 2 : 0;
   static constexpr int kFloats = kF32 > kSplit ? kF32 : kSplit;
 };
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -289,7 +289,8 @@ __device__ __forceinline__ void bwd_block_staged(const BwdArgs &a, int64_t blk, 
   // split's remainder are below 2^-24 of |a b|: FP32-level products at the
   // bfloat16 matrix-core rate).  A lane feeds the inner indices 8 (l / 16)
   // .. + 7 of a 32-index step; both operands use that order.
-  constexpr bool SPL = FAST && SB == 4 && OB == 4;
+  constexpr bool SPL = FAST && ((SB == 4 && OB == 4) || (SB == 8 && OB == 2));
+  constexpr int LR = 16 * SB;   // label rows of a tile
   // dX side (dL/dZ rows along the inner index): a lane's eight inner indices
   // are 4 (l / 16) + t and 16 + 4 (l / 16) + t, so that each load instruction
   // reads 64 contiguous bytes per row; the label parts are staged in the same
@@ -359,15 +360,17 @@ __device__ __forceinline__ void bwd_block_staged(const BwdArgs &a, int64_t blk, 
     if constexpr (SPL) {
       // three part planes; values past the chunk end are zero
       __bf16 *lb = reinterpret_cast<__bf16 *>(ls);
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
       bf16x8 ph, pm, pl;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const float x = gok[e >> 2] ? g[0][e] : 0.f;
+        const float x = gok[e >> 2] ? g[r][e] : 0.f;
         __bf16 h, m, l;
         split_bf16(x, h, m, l);
         ph[e] = h, pm[e] = m, pl[e] = l;
       }
-      __bf16 *d = lb + ((buf * 3) * 64 + sr) * kSplitLd;
+      __bf16 *d = lb + ((buf * 3) * LR + sr + 64 * r) * kSplitLd;
       if constexpr (PERM) {
         // inner index i sits at slot 8 ((i % 16) / 4) + 4 (i / 16) + i % 4
         typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
@@ -377,13 +380,14 @@ __device__ __forceinline__ void bwd_block_staged(const BwdArgs &a, int64_t blk, 
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
           const bf16x8 v = *pp[q];
-          *reinterpret_cast<bf16x4 *>(d + q * 64 * kSplitLd + sa) = bf16x4{v[0], v[1], v[2], v[3]};
-          *reinterpret_cast<bf16x4 *>(d + q * 64 * kSplitLd + sbb) = bf16x4{v[4], v[5], v[6], v[7]};
+          *reinterpret_cast<bf16x4 *>(d + q * LR * kSplitLd + sa) = bf16x4{v[0], v[1], v[2], v[3]};
+          *reinterpret_cast<bf16x4 *>(d + q * LR * kSplitLd + sbb) = bf16x4{v[4], v[5], v[6], v[7]};
         }
       } else {
         *reinterpret_cast<bf16x8 *>(d + 8 * sq) = ph;
-        *reinterpret_cast<bf16x8 *>(d + 8 * sq + 64 * kSplitLd) = pm;
-        *reinterpret_cast<bf16x8 *>(d + 8 * sq + 2 * 64 * kSplitLd) = pl;
+        *reinterpret_cast<bf16x8 *>(d + 8 * sq + LR * kSplitLd) = pm;
+        *reinterpret_cast<bf16x8 *>(d + 8 * sq + 2 * LR * kSplitLd) = pl;
+      }
       }
       return;
     }
@@ -522,13 +526,13 @@ __device__ __forceinline__ void bwd_block_staged(const BwdArgs &a, int64_t blk, 
       }
   };
   auto spl_step = [&](int cur) {
-    const __bf16 *lb = reinterpret_cast<const __bf16 *>(ls) + (cur * 3) * 64 * kSplitLd;
+    const __bf16 *lb = reinterpret_cast<const __bf16 *>(ls) + (cur * 3) * LR * kSplitLd;
 #pragma unroll
     for (int sb = 0; sb < SB; ++sb) {
       bf16x8 lp[3];
 #pragma unroll
       for (int q = 0; q < 3; ++q)
-        lp[q] = *reinterpret_cast<const bf16x8 *>(lb + (q * 64 + sb * 16 + l16) * kSplitLd + 8 * lg);
+        lp[q] = *reinterpret_cast<const bf16x8 *>(lb + (q * LR + sb * 16 + l16) * kSplitLd + 8 * lg);
       // (label part, dL/dZ part), smallest first
       constexpr int kPi[6] = {0, 2, 1, 0, 1, 0}, kPj[6] = {2, 0, 1, 1, 0, 0};
 #pragma unroll
@@ -684,7 +688,7 @@ __device__ __forceinline__ void bwd_block_staged(const BwdArgs &a, int64_t blk, 
 template <typename T, int SB, int MB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BwdCfg<T, SB>::kWaves, 8)))
 void k_bwd_x(const BwdArgs a) {
-  if constexpr (sizeof(T) == 4 && ((SB == 4 && MB == 4) || (SB == 16 && MB == 1))) {
+  if constexpr (sizeof(T) == 4 && ((SB == 4 && MB == 4) || (SB == 8 && MB == 2) || (SB == 16 && MB == 1))) {
     __shared__ __attribute__((aligned(16))) float lsraw[StagedLds<SB>::kFloats];
     auto ls = reinterpret_cast<float (*)[16 * SB][kStagedLd]>(lsraw);
     if (a.logN >= 4) bwd_block_staged<false, true, SB, MB>(a, blockIdx.x, ls);
@@ -722,7 +726,7 @@ void k_bwd_queue(const BwdArgs *descs, const int64_t *prefix, int ndesc, unsigne
     const int64_t it = item;
     if (it >= total) return;
     const int d = find_desc(prefix, ndesc, it);
-    if constexpr (sizeof(T) == 4 && ((SB == 4 && MB == 4) || (SB == 16 && MB == 1))) {
+    if constexpr (sizeof(T) == 4 && ((SB == 4 && MB == 4) || (SB == 8 && MB == 2) || (SB == 16 && MB == 1))) {
       __shared__ __attribute__((aligned(16))) float lsraw[StagedLds<SB>::kFloats];
       auto ls = reinterpret_cast<float (*)[16 * SB][kStagedLd]>(lsraw);
       const BwdArgs &a = descs[d];
@@ -1132,20 +1136,27 @@ __global__ __launch_bounds__(256) void k_bwd_prep(const BwdGatherDesc *descs, co
   }
 }
 
-// Label blocks of 16 per block tile.  Three and four shared cuts take 64
-// labels per tile: in FP32 those tiles run the split products, which made
-// them faster on the dX side at four cuts than 256-label FP32 tiles (C5 dX
-// launches 0.79 -> 0.70 ms), although they read dL/dZ four times instead of
-// once.  Five and more cuts take 256 (dL/dZ would otherwise be read 16 times;
-// the 256 label rows of a 32-index slice are staged in LDS once per block).
-// (An earlier 256-label form in which every wave loaded the same 256 operand
-// rows itself was 1.5x slower than 64.)
+// Label blocks of 16 per block tile.  Three shared cuts take 64 labels per
+// tile, four take 128 on the dX side (two output blocks per wave, so dL/dZ is
+// read twice) and 64 on the dY side; in FP32 these tiles run the split
+// products.  Measured in C5: the split 64-label dX tiles at four cuts were
+// faster than FP32 256-label ones (0.79 -> 0.70 ms for the dX launches,
+// although they read dL/dZ four times instead of once) and 128-label split
+// tiles faster still (0.65 ms); on the dY side 128 labels with two output
+// blocks measured 0.64 ms against 0.54 ms for 64 with four (its dL/dZ loads
+// then cover two adjacent columns per lane instead of four).  Five and more
+// cuts take 256 (dL/dZ would otherwise be read 16 times; the 256 label rows of
+// a 32-index slice are staged in LDS once per block).  (An earlier 256-label
+// form in which every wave loaded the same 256 operand rows itself was 1.5x
+// slower than 64.)
 static int sb_for(int nS, bool y, bool f32) {
-  (void)y, (void)f32;
   if (nS <= 2) return 1;
-  if (nS <= 4) return 4;
+  if (nS == 3) return 4;
+  if (nS == 4) return f32 && !y ? 8 : 4;
   return 16;
 }
+// output blocks of 16 per wave for a label-block count
+static int ob_for(int SB) { return SB == 16 ? 1 : SB == 8 ? 2 : 4; }
 
 template <typename T>
 static Status launch_bwd_t(const BwdArgs &a, bool which_y, hipStream_t s) {
@@ -1155,15 +1166,17 @@ static Status launch_bwd_t(const BwdArgs &a, bool which_y, hipStream_t s) {
   const int64_t M = int64_t(1) << a.logM, N = int64_t(1) << a.logN;
   const int RXn = 1 << (2 * a.nRX), RYn = 1 << (2 * a.nRY);
   if (!which_y) {
-    const int MB = SB == 16 ? 1 : 4;
+    const int MB = ob_for(SB);
     const int64_t tiles = (M + 64 * MB - 1) / (64 * MB);
     const int64_t P = (int64_t)RYn * a.kChunks;
     const dim3 g((unsigned)(P * RXn * sSuper * tiles)), b(256);
     if (SB == 1) return launch("bwd_x", k_bwd_x<T, 1, 4>, g, b, 0, s, a);
     if (SB == 4) return launch("bwd_x", k_bwd_x<T, 4, 4>, g, b, 0, s, a);
+    if constexpr (sizeof(T) == 4)
+      if (SB == 8) return launch("bwd_x", k_bwd_x<T, 8, 2>, g, b, 0, s, a);
     return launch("bwd_x", k_bwd_x<T, 16, 1>, g, b, 0, s, a);
   }
-  const int NB = SB == 16 ? 1 : 4;
+  const int NB = ob_for(SB);
   const int64_t tiles = (N + 64 * NB - 1) / (64 * NB);
   const int64_t P = (int64_t)RXn * a.kChunks;
   const dim3 g((unsigned)(P * RYn * sSuper * tiles)), b(256);
@@ -1184,7 +1197,7 @@ int64_t bwd_blocks(const BwdArgs &a, bool which_y, bool f32) {
   const int sSuper = (SN + 16 * SB - 1) / (16 * SB);
   const int64_t M = int64_t(1) << a.logM, N = int64_t(1) << a.logN;
   const int64_t RXn = int64_t(1) << (2 * a.nRX), RYn = int64_t(1) << (2 * a.nRY);
-  const int B = SB == 16 ? 1 : 4;
+  const int B = ob_for(SB);
   if (!which_y) return (RYn * a.kChunks) * RXn * sSuper * ((M + 64 * B - 1) / (64 * B));
   return (RXn * a.kChunks) * RYn * sSuper * ((N + 64 * B - 1) / (64 * B));
 }
@@ -1200,6 +1213,8 @@ static Status launch_bwd_queue_t(const BwdQueue &q, hipStream_t s) {
   }
   if (q.sb == 1) return launch(nm, k_bwd_queue<T, 1, 4, false>, g, b, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
   if (q.sb == 4) return launch(nm, k_bwd_queue<T, 4, 4, false>, g, b, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
+  if constexpr (sizeof(T) == 4)
+    if (q.sb == 8) return launch(nm, k_bwd_queue<T, 8, 2, false>, g, b, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
   return launch(nm, k_bwd_queue<T, 16, 1, false>, g, b, 0, s, q.descs, q.prefix, q.ndesc, q.queue, q.total);
 }
 
