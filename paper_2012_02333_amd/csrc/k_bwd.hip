@@ -245,8 +245,8 @@ __device__ __forceinline__ void bwd_y_block(const BwdArgs &a, int64_t blk) {
     }
 }
 
-// 16 SB label rows x 64 OB outputs per block (four waves of 16 OB: 64 x 256
-// or 256 x 64), the label rows' 32-index slices staged in LDS once per block
+// 16 SB label rows x 64 OB outputs per block (four waves of 16 OB: 64 x 256,
+// 128 x 128 or 256 x 64), the label rows' 32-index slices staged in LDS once per block
 // (double-buffered) instead of loaded by every wave; the dL/dZ operand per
 // wave from global memory, one 16-index half ahead.  Y: the dY side (label rows of X over m, dZ columns);
 // else the dX side (label rows of Y over n, dZ rows).
@@ -255,10 +255,10 @@ __device__ __forceinline__ void bwd_y_block(const BwdArgs &a, int64_t blk) {
 // loads from clamped addresses, and nothing consumes a loaded value before
 // its use (a select right after a load would wait for it there).
 constexpr int kStagedLd = 36;
-// Split form of the 64-label FP32 tiles (FAST, SB = 4): the label slices are
-// staged as three bfloat16 part planes [2][3][64][kSplitLd] (pitch 48: the
-// 16-byte operand reads of 16 rows x 2 lane groups fall on distinct 16-byte
-// slots modulo 512 bytes).
+// Split form of the 64- and 128-label FP32 tiles (FAST, SB = 4 or 8): the
+// label slices are staged as three bfloat16 part planes [2][3][16 SB][kSplitLd]
+// (pitch 48: the 16-byte operand reads of 16 rows x 2 lane groups fall on
+// distinct 16-byte slots modulo 512 bytes).
 constexpr int kSplitLd = 48;
 template <int SB> struct StagedLds {
   static constexpr int kF32 = 2 * 16 * SB * kStagedLd;
