@@ -28,9 +28,9 @@ struct BwdInstancePlan {
 };
 
 BwdSide choose_bwd_side(int64_t inner, int64_t rest, int64_t out_elems, int64_t dz_elems, size_t esz,
-                        double min_budget) {
+                        double min_budget, double dz_frac) {
   BwdSide s;
-  const double budget = std::max(min_budget, 0.25 * (double)dz_elems * (double)esz);
+  const double budget = std::max(min_budget, dz_frac * (double)dz_elems * (double)esz);
   int64_t kc = 128;
   if (kc > inner) kc = (inner + 15) / 16 * 16;
   while (true) {

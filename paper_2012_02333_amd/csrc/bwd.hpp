@@ -36,14 +36,14 @@ inline int64_t bwd_dual_blocks(const BwdArgs &a, int64_t nbatch) {
 
 // Split-K choice of one side of an adjoint step: inner-dimension chunk, chunks
 // per rest-label value and partial count P = rest * chunks, the smallest
-// chunk (from 128) whose partials fit max(min_budget, dz bytes / 4).
+// chunk (from 128) whose partials fit max(min_budget, dz_frac * dz bytes).
 struct BwdSide {
   int64_t kChunk = 16;
   int32_t kChunks = 1;
   int64_t P = 1;
 };
 BwdSide choose_bwd_side(int64_t inner, int64_t rest, int64_t out_elems, int64_t dz_elems, size_t esz,
-                        double min_budget);
+                        double min_budget, double dz_frac = 0.25);
 
 // Batched adjoint tables (device memory).
 struct BwdReduceDesc {    // out[i] = scale * sum_{p < P} part[p][i], i < count
