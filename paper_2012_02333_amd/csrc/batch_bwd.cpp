@@ -51,7 +51,8 @@ static constexpr double kBatchBwdMinBudget = 1.0 * (1 << 20);
 // Partials budget per step side as a fraction of its dL/dZ bytes.  Measured
 // on the 256-instance training step: the dX launches took 0.65 ms at 1/4,
 // 0.59 at 1/16 (longer inner chunks, fewer partial sums to write and add),
-// 0.88 at 1/32 (too few blocks); the dY launches were fastest at 1/4.
+// 0.88 at 1/32 (too few blocks); the dY launches were fastest at 1/4 (0.54 ms
+// against 0.59 at 1/2 and 0.56 at 1/16).
 static constexpr double kBatchBwdFracX = 1.0 / 16, kBatchBwdFracY = 0.25;
 
 struct BwdBuild {
