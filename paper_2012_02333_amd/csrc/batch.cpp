@@ -55,10 +55,22 @@ struct BatchBuild {
 // shape class (the cache single calls consult) where a queue kernel has that
 // tile and the operands fit it, else the built-in rule.  The queue kernels
 // have no 256 x 16 form; its steps take the 16 x 64 tile.
+// In a work-queue launch the wide kernel's tiles share the launch with those
+// of every other step of its group, so a step with few tiles does not leave
+// the chip idle (which is why a single call keeps the register kernel below
+// 2^22 outputs): FP32 steps of three or more shared cuts with both operands at
+// least 128 wide take the wide kernel from 2^kBatchWideLog outputs.  Measured
+// on the 256-instance training step: 4.01 ms per step with 2^22, 3.97 with
+// 2^20, 3.94 with 2^19, 3.96 with 2^17 and 2^18.  Such a step's outputs then
+// differ from the single call's by FP32 rounding (another product order).
+static constexpr int kBatchWideLog = 19;
 static int queue_cfg(Acc acc, const Step &st, int mode, bool out_double) {
   const Acc sa = step_acc(acc, st.wide_ok(), (int)st.S.size());
   const int nS = (int)st.S.size();
   int c = choose_tile(sa, nS, st.logM, st.logN, st.wide_ok(), st.nbatch);
+  if (sa == Acc::F32 && st.wide_ok() && nS >= 3 && st.logM >= 7 && st.logN >= 7 &&
+      (int64_t(1) << (st.logM + st.logN)) * st.nbatch >= (int64_t(1) << kBatchWideLog))
+    c = kTileW;
   int tc = 0, xcd = 0;
   if (tuned_choice(sa, mode, nS <= 2, st.logM, st.logN, nS, out_double, &tc, &xcd) && tile_ok(sa, tc) &&
       (tc != kTileW || st.wide_ok()))
