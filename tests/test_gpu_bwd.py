@@ -34,7 +34,7 @@ def _vjp_gpu(entries_np, wcut, G, dtype, prec):
 @pytest.mark.parametrize("prec,dtype,tol", [("fp64", torch.float64, 1e-12), ("fp32", torch.float32, 1e-5)])
 @pytest.mark.parametrize("shape", [((4, 3), (1,), 4), ((5, 5), (2,), 6), ((3, 2, 3), (3, 3), 4),
                                    ((2, 3, 3, 2), (1, 2, 2), 4), ((6, 6), (3,), 6), ((5, 5), (4,), 4),
-                                   ((4, 4), (5,), 4)])
+                                   ((4, 4), (5,), 4), ((1, 5), (4,), 4), ((5, 1), (4,), 4)])
 def test_vjp_simulated(shape, prec, dtype, tol):
     _gpu()
     own, bridges, layers = shape
