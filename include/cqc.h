@@ -67,8 +67,8 @@ typedef enum { CQC_F32 = 0, CQC_F64 = 1 } cqc_dtype;
  *           accumulation (Henry, Tang, Heinecke, ARITH 2019).
  *   BF16X3: the speed end of the same split: two bfloat16 parts
  *           (a = a0+a1) and the three products a_i b_j with i+j <= 1; the
- *           dropped part and product leave up to about 3 * 2^-18 of |a b| per
- *           product (about 1e-5 relative, above the FP32 forms' error).
+ *           dropped part and product leave up to 2^-15 of |a b| per product
+ *           (about 3e-5 relative, above the FP32 forms' error).
  * Steps with at most 16 terms (<= 2 shared cuts) or a one-column operand
  * run the FP32 form under both split precisions.                        */
 typedef enum { CQC_PREC_FP64 = 0, CQC_PREC_FP32 = 1, CQC_PREC_BF16X6 = 2, CQC_PREC_BF16X3 = 3 } cqc_precision;

@@ -15,7 +15,7 @@
 //           FP32 rate: 2.7x the FP32 form's arithmetic throughput).
 //   BF16X3  two parts a = a0 + a1 (16 significand bits) and the three products
 //           a_i b_j with i + j <= 1, smallest first: half the BF16X6 matrix-core
-//           work, with the dropped part and product up to about 3 * 2^-18 of
+//           work, with the dropped part and product up to 2^-15 of
 //           |a b| per product - the speed end of the same split.
 //
 // A label-list pass first compacts, for every batch entry of the step, the

@@ -1,11 +1,11 @@
 """The two-part split-BF16 form (BF16X3: a = a0 + a1, products a_i b_j with
 i + j <= 1) against the FP64 oracle, and its place between BF16X6 and FP32.
 
-Bars, derived from the split: each operand keeps 16 significand bits (the
-remainder after two parts is below 2^-18 |a|), so the dropped part and product
-leave at most about 3 * 2^-18 = 192 u of |a b| per product; elementwise
-|p - ref| <= 4 (3 t + 50) u T_x (gpu_util.sum_terms) and relative L1 <=
-1.2e-5 kappa.  Steps with at most 16 terms run FP32 under BF16X3 as under
+Bars, derived from the split: the remainder after two parts is at most
+2^-17 |a| and the second part at most 2^-8 |a|, so the dropped product a1 b1
+and the remainders leave at most 2^-15 = 512 u of |a b| per product (bounds
+checked on the host in test_split_bound); elementwise |p - ref| <=
+4 (3 t + 130) u T_x (gpu_util.sum_terms) and relative L1 <= 3.1e-5 kappa.  Steps with at most 16 terms run FP32 under BF16X3 as under
 BF16X6, so the cases here have three or more shared cuts where it matters.
 """
 import numpy as np

@@ -41,7 +41,8 @@ def _check(cut, ents, prec, xs=None, out_dtype=None):
     kap = metrics.kappa(e64, cut, np.abs(ref).sum()) if xs is None else 1.0
     print(f"{prec}: rel_l1={err:.3e} kappa={kap:.2f}")
     # FP32 and BF16X6: the flat 1e-6 bar (kappa is a diagnostic); BF16X3's
-    # bar is its dropped part, 1.2e-5 of T_x, hence kappa-scaled
+    # bar is its dropped part, at most 2^-15 = 3.05e-5 of T_x, hence
+    # kappa-scaled
     bar = REL_L1[prec] * (max(1.0, kap) if prec == "bf16x3" else 1.0)
     assert err <= bar
     ok, info = elementwise_ok(got, ref, abs_bound(e64, cut, xs), U32, sum_terms(prec, 4 ** cut.n_cuts))
